@@ -1,0 +1,419 @@
+/*
+ * Plain FP64 oracle for fixed-step IRKGL16 in the floating-point-symplectic
+ * second-order (eta) formulation.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct CPU
+ * reference that the GPU library is checked against.  It shares no code,
+ * header, table or helper with the GPU library; only the test-suite, the
+ * smoke check and the benchmark's CPU-baseline leg may load it.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math -fopenmp -shared -fPIC
+ * (strict IEEE binary64: no contraction into fma, no reassociation).
+ *
+ * What one step computes (second-order problem q'' = g(q), v = q'):
+ *   initial guess (section 2.5, eq. IRK_init2; eq. Pol0 for nu):
+ *       V0_i = v + sum_j nu_ij R_prev_j
+ *       L0_j = hb_j V0_j
+ *       Q_i  = q + sum_j mu_ij L0_j
+ *   fixed-point iteration k = 1, 2, ... (eq. IRK_FP2, eqs. Gi/Qi2):
+ *       G_i  = g(Q_i)
+ *       R_i  = hb_i G_i                         (hb_i = fl(h b_i))
+ *       Qn_i = q + h (c_i v + sum_j eta_ij R_j)
+ *       Delta^l = max_i |Qn_i^l - Q_i^l|        (eq. Delta_n)
+ *       Q = Qn; stop when, for every position component l, Delta^l == 0 or
+ *       min(Delta^l[1..k-2]) <= min(Delta^l[k-1], Delta^l[k])  (eq. stopping)
+ *   update (eq. qnvn2) with double-word state (section 5, compensated
+ *   summation with a two-double state):
+ *       S_v = sum_i R_i,  S_c = sum_i c_i R_i
+ *       v <- v (+) S_v;   q <- q (+) h (v.hi - S_c);   R_prev <- R
+ *   where x (+) d is: (s,e) = TwoSum(x.hi, d); t = e + x.lo;
+ *   (x.hi, x.lo) = Fast2Sum(s, t).
+ * Stage values only read the hi parts of q and v.  The R that drives the
+ * update is the last one computed (from the previous iterate), so a step costs
+ * exactly 8k force evaluations.  All sums run in ascending index order.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "tableau.h"
+
+#define S 8
+
+enum {
+  ORC_KEPLER = 0,
+  ORC_GRAVITY = 1,
+  ORC_CHAIN = 2,
+  /* problems used only by oracle pins */
+  ORC_HARMONIC = 10, /* g = -G q               */
+  ORC_CONST = 11,    /* g = G (every component) */
+  ORC_HENON = 12,    /* Henon-Heiles, Dq = 2    */
+};
+
+enum {
+  ORC_FLAG_NO_COMPENSATION = 1, /* negative control: plain state update   */
+  ORC_FLAG_NAIVE_ETA = 2,       /* negative control: eta without completion */
+  ORC_FLAG_NO_EXTRAPOLATION = 4 /* initial guess with R_prev = 0 every step */
+};
+
+enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_ENONFINITE = -4, ORC_ENOCONV = 1 };
+
+typedef struct {
+  int32_t kind, n, d;
+  const double *mass;     /* GRAVITY: n masses; CHAIN: n site masses or NULL */
+  const double *coupling; /* CHAIN: n+1 bond stiffnesses or NULL             */
+  double G, eps, beta;
+} orc_problem;
+
+typedef struct {
+  int64_t steps_done;
+  int64_t iterations;       /* sum of k over steps */
+  int32_t max_k;
+  int32_t nonconverged;     /* steps that hit max_iter */
+  int32_t status;
+} orc_stats;
+
+/* ---------------- forces g(Q) ---------------- */
+
+static double mass_of(const orc_problem *p, int body) {
+  if (p->kind == ORC_GRAVITY) return p->mass[body];
+  if (p->kind == ORC_CHAIN) return p->mass ? p->mass[body] : 1.0;
+  return 1.0;
+}
+
+static double dV(double s, double beta) { return s + beta * (s * s * s); }
+
+void orc_force(const orc_problem *p, const double *Q, double *G) {
+  const int n = p->n, d = p->d, Dq = n * d;
+  switch (p->kind) {
+  case ORC_KEPLER: {
+    double r2 = 0.0;
+    for (int k = 0; k < Dq; ++k) r2 += Q[k] * Q[k];
+    double r3 = r2 * sqrt(r2);
+    for (int k = 0; k < Dq; ++k) G[k] = -p->G * Q[k] / r3;
+    break;
+  }
+  case ORC_GRAVITY: {
+    double eps2 = p->eps * p->eps;
+    for (int a = 0; a < n; ++a) {
+      double acc[3] = {0.0, 0.0, 0.0};
+      for (int b = 0; b < n; ++b) {
+        if (b == a) continue;
+        double dx[3], r2 = 0.0;
+        for (int k = 0; k < d; ++k) {
+          dx[k] = Q[b * d + k] - Q[a * d + k];
+          r2 += dx[k] * dx[k];
+        }
+        r2 += eps2;
+        double w = p->mass[b] / (r2 * sqrt(r2));
+        for (int k = 0; k < d; ++k) acc[k] += w * dx[k];
+      }
+      for (int k = 0; k < d; ++k) G[a * d + k] = p->G * acc[k];
+    }
+    break;
+  }
+  case ORC_CHAIN: {
+    for (int i = 0; i < n; ++i) {
+      double ql = (i > 0) ? Q[i - 1] : 0.0;
+      double qr = (i < n - 1) ? Q[i + 1] : 0.0;
+      double kl = p->coupling ? p->coupling[i] : 1.0;
+      double kr = p->coupling ? p->coupling[i + 1] : 1.0;
+      double F = kr * dV(qr - Q[i], p->beta) - kl * dV(Q[i] - ql, p->beta);
+      G[i] = F / mass_of(p, i);
+    }
+    break;
+  }
+  case ORC_HARMONIC:
+    for (int k = 0; k < Dq; ++k) G[k] = -p->G * Q[k];
+    break;
+  case ORC_CONST:
+    for (int k = 0; k < Dq; ++k) G[k] = p->G;
+    break;
+  case ORC_HENON:
+    G[0] = -Q[0] - 2.0 * Q[0] * Q[1];
+    G[1] = -Q[1] - (Q[0] * Q[0] - Q[1] * Q[1]);
+    break;
+  }
+}
+
+/* Hamiltonian H(q, p) of each problem (for energy-error pins). */
+double orc_energy(const orc_problem *pr, const double *q, const double *p) {
+  const int n = pr->n, d = pr->d, Dq = n * d;
+  double T = 0.0, U = 0.0;
+  for (int a = 0; a < n; ++a)
+    for (int k = 0; k < d; ++k) T += p[a * d + k] * p[a * d + k] / (2.0 * mass_of(pr, a));
+  switch (pr->kind) {
+  case ORC_KEPLER: {
+    double r2 = 0.0;
+    for (int k = 0; k < Dq; ++k) r2 += q[k] * q[k];
+    U = -pr->G / sqrt(r2);
+    break;
+  }
+  case ORC_GRAVITY: {
+    double eps2 = pr->eps * pr->eps;
+    for (int a = 0; a < n; ++a)
+      for (int b = a + 1; b < n; ++b) {
+        double r2 = 0.0;
+        for (int k = 0; k < d; ++k) {
+          double dx = q[b * d + k] - q[a * d + k];
+          r2 += dx * dx;
+        }
+        U -= pr->G * pr->mass[a] * pr->mass[b] / sqrt(r2 + eps2);
+      }
+    break;
+  }
+  case ORC_CHAIN:
+    for (int i = 0; i <= n; ++i) {
+      double ql = (i > 0) ? q[i - 1] : 0.0;
+      double qr = (i < n) ? q[i] : 0.0;
+      double s = qr - ql, k = pr->coupling ? pr->coupling[i] : 1.0;
+      U += k * (0.5 * s * s + 0.25 * pr->beta * s * s * s * s);
+    }
+    break;
+  case ORC_HARMONIC:
+    for (int k = 0; k < Dq; ++k) U += 0.5 * pr->G * q[k] * q[k];
+    break;
+  case ORC_CONST:
+    for (int k = 0; k < Dq; ++k) U -= pr->G * q[k];
+    break;
+  case ORC_HENON:
+    U = 0.5 * (q[0] * q[0] + q[1] * q[1]) + q[0] * q[0] * q[1] - q[1] * q[1] * q[1] / 3.0;
+    break;
+  }
+  return T + U;
+}
+
+/* ---------------- double-word helpers ---------------- */
+
+/* x (+) delta: (s,e) = TwoSum(hi, delta) [Knuth]; t = e + lo;
+ * (hi, lo) = Fast2Sum(s, t) [Dekker]. */
+static void dw_add(double *hi, double *lo, double delta) {
+  double s = *hi + delta;
+  double bv = s - *hi;
+  double e = (*hi - (s - bv)) + (delta - bv);
+  double t = e + *lo;
+  double h2 = s + t;
+  *lo = t - (h2 - s);
+  *hi = h2;
+}
+
+void orc_dw_add(double *hi, double *lo, double delta) { dw_add(hi, lo, delta); }
+
+/* The stopping rule (eq. stopping) for one component.  `mind` holds
+ * min(Delta[1..k-2]) and `prev` holds Delta[k-1] (both +inf initially).
+ * Returns 1 if this component allows stopping, and advances the history. */
+static int stop_component(double delta, double *mind, double *prev) {
+  double m = (*prev < delta) ? *prev : delta;
+  int ok = (delta == 0.0) || (*mind <= m);
+  if (*prev < *mind) *mind = *prev;
+  *prev = delta;
+  return ok;
+}
+
+int orc_stop_component(double delta, double *mind, double *prev) {
+  return stop_component(delta, mind, prev);
+}
+
+/* ---------------- one instance ---------------- */
+
+static int valid_problem(const orc_problem *p) {
+  if (p->n < 1 || p->d < 1 || p->d > 3) return 0;
+  switch (p->kind) {
+  case ORC_KEPLER: return p->n == 1;
+  case ORC_GRAVITY:
+    if (!p->mass) return 0;
+    for (int a = 0; a < p->n; ++a)
+      if (!(p->mass[a] > 0.0)) return 0;
+    return 1;
+  case ORC_CHAIN: return p->d == 1;
+  case ORC_HARMONIC: case ORC_CONST: return 1;
+  case ORC_HENON: return p->n * p->d == 2;
+  }
+  return 0;
+}
+
+/*
+ * Integrate one instance.  q0, p0: Dq values.  Frames f = 0..nsteps/stride
+ * (state after f*stride steps; frame 0 is the initial state) are written to
+ * q_out/p_out as [frame][Dq] with p = m * v.hi.  iters (nullable): k of each
+ * step.  delta1 (nullable): max over components of Delta^[1] of each step.
+ * After a non-finite Delta the instance stops and its remaining frames are NaN.
+ */
+int orc_integrate(const orc_problem *p, const double *q0, const double *p0, double h,
+                  int64_t nsteps, int64_t stride, int32_t max_iter, int32_t flags,
+                  double *q_out, double *p_out, int32_t *iters, double *delta1,
+                  orc_stats *st) {
+  if (!valid_problem(p) || !(isfinite(h)) || nsteps < 0 || stride < 1 || nsteps % stride ||
+      max_iter < 1)
+    return ORC_EINVAL;
+  const int Dq = p->n * p->d;
+  double *buf = (double *)calloc((size_t)Dq * (6 + 6 * S), sizeof(double));
+  if (!buf) return ORC_ENOMEM;
+  double *qh = buf, *ql = qh + Dq, *vh = ql + Dq, *vl = vh + Dq, *mind = vl + Dq,
+         *prev = mind + Dq;
+  double *Q = prev + Dq, *Qn = Q + S * Dq, *G = Qn + S * Dq, *R = G + S * Dq,
+         *Rp = R + S * Dq, *V0 = Rp + S * Dq;
+  double eta[S][S];
+  for (int i = 0; i < S; ++i)
+    for (int j = 0; j < S; ++j)
+      eta[i][j] = ((flags & ORC_FLAG_NAIVE_ETA) && j > i) ? ORC_ETA_NAIVE[i][j] : ORC_ETA[i][j];
+  double hb[S];
+  for (int i = 0; i < S; ++i) hb[i] = h * ORC_B[i];
+  for (int l = 0; l < Dq; ++l) {
+    qh[l] = q0[l];
+    vh[l] = p0[l] / mass_of(p, l / p->d);
+  }
+  orc_stats loc = {0, 0, 0, 0, ORC_OK};
+  int64_t frame = 0;
+  for (int l = 0; l < Dq; ++l) {
+    q_out[l] = qh[l];
+    p_out[l] = mass_of(p, l / p->d) * vh[l];
+  }
+  int dead = 0;
+  for (int64_t n = 1; n <= nsteps; ++n) {
+    if (!dead) {
+      if (flags & ORC_FLAG_NO_EXTRAPOLATION) memset(Rp, 0, sizeof(double) * S * Dq);
+      /* initial guess */
+      for (int i = 0; i < S; ++i)
+        for (int l = 0; l < Dq; ++l) {
+          double s = 0.0;
+          for (int j = 0; j < S; ++j) s += ORC_NU[i][j] * Rp[j * Dq + l];
+          V0[i * Dq + l] = vh[l] + s;
+        }
+      for (int i = 0; i < S; ++i)
+        for (int l = 0; l < Dq; ++l) {
+          double s = 0.0;
+          for (int j = 0; j < S; ++j) s += ORC_MU[i][j] * (hb[j] * V0[j * Dq + l]);
+          Q[i * Dq + l] = qh[l] + s;
+        }
+      for (int l = 0; l < Dq; ++l) mind[l] = prev[l] = INFINITY;
+      /* fixed-point iteration */
+      int k = 0, conv = 0;
+      while (!conv && k < max_iter) {
+        ++k;
+        for (int i = 0; i < S; ++i) orc_force(p, Q + i * Dq, G + i * Dq);
+        for (int i = 0; i < S; ++i)
+          for (int l = 0; l < Dq; ++l) R[i * Dq + l] = hb[i] * G[i * Dq + l];
+        for (int i = 0; i < S; ++i)
+          for (int l = 0; l < Dq; ++l) {
+            double s = 0.0;
+            for (int j = 0; j < S; ++j) s += eta[i][j] * R[j * Dq + l];
+            Qn[i * Dq + l] = qh[l] + h * (ORC_C[i] * vh[l] + s);
+          }
+        conv = 1;
+        double dmax = 0.0;
+        for (int l = 0; l < Dq; ++l) {
+          double dl = 0.0;
+          for (int i = 0; i < S; ++i) {
+            double a = fabs(Qn[i * Dq + l] - Q[i * Dq + l]);
+            if (!(a <= dl)) dl = a; /* NaN propagates */
+          }
+          if (!isfinite(dl)) dead = 1;
+          if (dl > dmax) dmax = dl;
+          if (!stop_component(dl, mind + l, prev + l)) conv = 0;
+        }
+        if (k == 1 && delta1) delta1[n - 1] = dmax;
+        memcpy(Q, Qn, sizeof(double) * S * Dq);
+        if (dead) break;
+      }
+      if (!dead) {
+        if (!conv) ++loc.nonconverged;
+        loc.iterations += k;
+        if (k > loc.max_k) loc.max_k = k;
+        if (iters) iters[n - 1] = k;
+        /* update with compensated summation */
+        for (int l = 0; l < Dq; ++l) {
+          double sv = 0.0, sc = 0.0;
+          for (int i = 0; i < S; ++i) sv += R[i * Dq + l];
+          for (int i = 0; i < S; ++i) sc += ORC_C[i] * R[i * Dq + l];
+          if (flags & ORC_FLAG_NO_COMPENSATION) {
+            vh[l] += sv;
+            qh[l] += h * (vh[l] - sc);
+          } else {
+            dw_add(vh + l, vl + l, sv);
+            dw_add(qh + l, ql + l, h * (vh[l] - sc));
+          }
+        }
+        memcpy(Rp, R, sizeof(double) * S * Dq);
+        loc.steps_done = n;
+      } else {
+        loc.status = ORC_ENONFINITE;
+        if (iters) iters[n - 1] = k;
+      }
+    } else if (iters) {
+      iters[n - 1] = 0;
+    }
+    if (n % stride == 0) {
+      ++frame;
+      for (int l = 0; l < Dq; ++l) {
+        q_out[frame * Dq + l] = dead ? NAN : qh[l];
+        p_out[frame * Dq + l] = dead ? NAN : mass_of(p, l / p->d) * vh[l];
+      }
+    }
+  }
+  if (loc.status == ORC_OK && loc.nonconverged) loc.status = ORC_ENOCONV;
+  if (st) *st = loc;
+  free(buf);
+  return loc.status;
+}
+
+/*
+ * Many instances (OpenMP across instances).  Packing: instance i has
+ * Dq_i = n_i d_i values in q0/p0 (concatenated in order) and
+ * F_i = nsteps_i / stride_i + 1 frames of Dq_i values in q_out/p_out.
+ * iters_total[i] = sum of k; status[i] = per-instance code.
+ */
+int orc_integrate_batch(int32_t n_inst, const orc_problem *probs, const double *q0,
+                        const double *p0, const double *h, const int64_t *nsteps,
+                        const int64_t *stride, int32_t max_iter, int32_t flags, double *q_out,
+                        double *p_out, int64_t *iters_total, int32_t *status) {
+  int64_t *in_off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_inst + 1));
+  int64_t *out_off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_inst + 1));
+  if (!in_off || !out_off) {
+    free(in_off);
+    free(out_off);
+    return ORC_ENOMEM;
+  }
+  in_off[0] = out_off[0] = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    int64_t Dq = (int64_t)probs[i].n * probs[i].d;
+    if (stride[i] < 1 || nsteps[i] < 0 || nsteps[i] % stride[i]) {
+      free(in_off);
+      free(out_off);
+      return ORC_EINVAL;
+    }
+    in_off[i + 1] = in_off[i] + Dq;
+    out_off[i + 1] = out_off[i] + Dq * (nsteps[i] / stride[i] + 1);
+  }
+  int worst = ORC_OK;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int i = 0; i < n_inst; ++i) {
+    orc_stats st;
+    int rc = orc_integrate(probs + i, q0 + in_off[i], p0 + in_off[i], h[i], nsteps[i], stride[i],
+                           max_iter, flags, q_out + out_off[i], p_out + out_off[i], NULL, NULL,
+                           &st);
+    if (iters_total) iters_total[i] = st.iterations;
+    if (status) status[i] = rc;
+    if (rc < 0) {
+#pragma omp critical
+      if (rc < worst) worst = rc;
+    }
+  }
+  free(in_off);
+  free(out_off);
+  return worst;
+}
+
+/* Table access for pins (read-only copies). */
+void orc_tableau(double *c, double *b, double *eta, double *mu, double *nu) {
+  for (int i = 0; i < S; ++i) {
+    c[i] = ORC_C[i];
+    b[i] = ORC_B[i];
+    for (int j = 0; j < S; ++j) {
+      eta[i * S + j] = ORC_ETA[i][j];
+      mu[i * S + j] = ORC_MU[i][j];
+      nu[i * S + j] = ORC_NU[i][j];
+    }
+  }
+}
