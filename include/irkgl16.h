@@ -1,0 +1,131 @@
+/*
+ * irkgl16.h -- C ABI of the MI355X (gfx950) IRKGL16 library.
+ *
+ * The library integrates many independent separable second-order Hamiltonian
+ * systems  q'' = g(q),  p = m v,  H = sum |p|^2/(2m) + U(q)  (paper section 2.3,
+ * eqs. sHam / Hamode2) with the fixed-step 8-stage Gauss-Legendre collocation
+ * method of order 16 (section 2.2) in its floating-point-symplectic
+ * second-order form (section 2.4, eqs. Gi, Qi2, qnvn2), solved by the
+ * stage-wise fixed-point iteration with extrapolated initial guess
+ * (section 2.5, eqs. IRK_init2, IRK_FP2) and the stopping rule of eq. stopping;
+ * the state (q, v) is kept as a pair of binary64 numbers and updated with
+ * compensated summation (section 5).  All arithmetic is IEEE binary64; every
+ * step runs in HIP kernels on the GPU.
+ *
+ * Threading: a context is not thread-safe; use one per host thread.
+ * Errors: every call returns a status code (below); no C++ exception crosses
+ * this interface.
+ */
+#ifndef IRKGL16_H
+#define IRKGL16_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define IRKGL16_OK 0
+#define IRKGL16_EINVAL (-1)     /* bad argument: kind, n, d, mass, h, stride...  */
+#define IRKGL16_ENOMEM (-2)     /* host or device allocation failed              */
+#define IRKGL16_EDEVICE (-3)    /* no usable GPU, or a HIP runtime error         */
+#define IRKGL16_ENONFINITE (-4) /* an instance produced NaN/Inf (others written) */
+#define IRKGL16_ENOCONV 1       /* warning: some steps stopped at max_iter       */
+
+/* ---- force kinds -------------------------------------------------------- */
+/* KEPLER : g(q) = -G q / |q|^3                      (n = 1, d = 2 or 3)
+ * GRAVITY: g_a  = G sum_{b != a} m_b (q_b - q_a) / (|q_b - q_a|^2 + eps^2)^{3/2}
+ *          (Plummer-softened Newtonian gravity; section 5.1.2, eq. Ham2)
+ * CHAIN  : g_i  = [k_{i+1} V'(q_{i+1} - q_i) - k_i V'(q_i - q_{i-1})] / m_i,
+ *          V'(s) = s + beta s^3, fixed ends q_0 = q_{n+1} = 0 (FPU-beta; d = 1) */
+#define IRKGL16_KEPLER 0
+#define IRKGL16_GRAVITY 1
+#define IRKGL16_CHAIN 2
+
+/* ---- option flags ------------------------------------------------------- */
+/* q0/p0/q_out/p_out of irkgl16_integrate are device pointers and the work is
+ * only enqueued on the context's stream (the caller synchronizes). */
+#define IRKGL16_DEVICE_PTRS 1u
+/* Plain form: one kernel launch per step per instance, instances in turn (the
+ * comparison baseline for the batched persistent kernel). */
+#define IRKGL16_PLAIN 2u
+
+typedef struct irkgl16_ctx irkgl16_ctx;
+
+/* One instance.  n bodies (GRAVITY) or sites (CHAIN) of dimension d; Dq = n d
+ * position components.  mass: GRAVITY n masses > 0 (required); CHAIN n site
+ * masses > 0 or NULL (all 1); KEPLER ignored (1).  coupling: CHAIN n+1 bond
+ * stiffnesses k_0..k_n or NULL (all 1).  G: KEPLER the gravitational parameter,
+ * GRAVITY the constant.  eps >= 0 softening (GRAVITY).  beta: CHAIN.  The
+ * arrays are host memory, read during irkgl16_create only. */
+typedef struct {
+  int32_t kind, n, d;
+  const double *mass;
+  const double *coupling;
+  double G, eps, beta;
+} irkgl16_problem;
+
+/* max_iter: cap on fixed-point iterations per step (<= 0 means 100; the paper
+ * sets none).  record_iters: keep the iteration count of every step.  flags:
+ * IRKGL16_* option flags. */
+typedef struct {
+  int32_t max_iter;
+  int32_t record_iters;
+  uint32_t flags;
+} irkgl16_options;
+
+/* Results of the last irkgl16_integrate call.  The three pointers are
+ * optional caller-owned host arrays filled when non-NULL:
+ * inst_iterations[n_inst] (sum of k), inst_status[n_inst] (status code per
+ * instance), step_iters[sum nsteps] (k of every step, instance-major; only with
+ * record_iters). */
+typedef struct {
+  int64_t steps;              /* instance-steps done                        */
+  int64_t iterations;         /* sum of k over all steps                    */
+  int64_t nonconverged_steps; /* steps that stopped at max_iter             */
+  int32_t max_k;              /* largest k of any step                      */
+  int32_t n_nonfinite;        /* instances stopped by a NaN/Inf             */
+  double device_ms;           /* GPU time of the call (HIP events, stream)  */
+  int64_t *inst_iterations;
+  int32_t *inst_status;
+  uint8_t *step_iters;
+} irkgl16_stats;
+
+/* Create a context for n_inst instances (probs[n_inst], host memory, copied).
+ * hip_stream: a hipStream_t to enqueue on, or NULL for a library-owned stream.
+ * Returns IRKGL16_EDEVICE when no GPU is usable.  *out is NULL on failure. */
+int irkgl16_create(irkgl16_ctx **out, const irkgl16_problem *probs, int32_t n_inst,
+                   const irkgl16_options *opt, void *hip_stream);
+
+/* Integrate every instance from its initial state.
+ * q0, p0: sum(Dq_i) doubles, instances concatenated in order (host memory, or
+ *         device memory with IRKGL16_DEVICE_PTRS).  v = fl(p / m) on input.
+ * h, nsteps, out_stride: n_inst values each (host memory, always).  h finite
+ *         and nonzero (h < 0 integrates backwards); nsteps >= 0;
+ *         out_stride >= 1 divides nsteps.
+ * q_out, p_out: sum(Dq_i * (nsteps_i / out_stride_i + 1)) doubles, instance i
+ *         as [frame][Dq_i]; frame f is the state after f * out_stride_i steps
+ *         (frame 0 = initial state), q = q.hi and p = m * v.hi.  Frames after an
+ *         instance became non-finite are NaN.
+ * stats: nullable.  In host mode the call returns when outputs are complete;
+ * with IRKGL16_DEVICE_PTRS it returns after enqueueing (stats, if given, force a
+ * stream synchronization).  Returns the worst status over instances. */
+int irkgl16_integrate(irkgl16_ctx *ctx, const double *q0, const double *p0, const double *h,
+                      const int64_t *nsteps, const int64_t *out_stride, double *q_out,
+                      double *p_out, irkgl16_stats *stats);
+
+/* Synchronize the context's stream and fill stats for the last integrate call.
+ * Returns that call's worst status. */
+int irkgl16_last_stats(irkgl16_ctx *ctx, irkgl16_stats *stats);
+
+/* Release a context and its device memory.  NULL-safe. */
+void irkgl16_destroy(irkgl16_ctx *ctx);
+
+/* Static description of a status code. */
+const char *irkgl16_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IRKGL16_H */

@@ -222,9 +222,10 @@ int ddo_integrate(const ddo_problem *p, const double *q0, const double *p0, doub
         dd dl = mk(0.0);
         for (int i = 0; i < S; ++i) {
           dd a = ddabs(sub(Qn[i * Dq + l], Q[i * Dq + l]));
-          if (!(a.hi <= dl.hi) || lt(dl, a)) dl = a;
+          if (isnan(a.hi) || lt(dl, a)) dl = a;
         }
         if (!isfinite(dl.hi)) bad = 1;
+        if (isnan(dl.hi)) { bad = 1; }
         dd m = lt(prev[l], dl) ? prev[l] : dl;
         int ok = (dl.hi == 0.0 && dl.lo == 0.0) || !lt(m, mind[l]);
         if (lt(prev[l], mind[l])) mind[l] = prev[l];

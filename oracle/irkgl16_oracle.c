@@ -307,7 +307,7 @@ int orc_integrate(const orc_problem *p, const double *q0, const double *p0, doub
           double dl = 0.0;
           for (int i = 0; i < S; ++i) {
             double a = fabs(Qn[i * Dq + l] - Q[i * Dq + l]);
-            if (!(a <= dl)) dl = a; /* NaN propagates */
+            if (isnan(a) || a > dl) dl = a; /* a NaN, once seen, is kept */
           }
           if (!isfinite(dl)) dead = 1;
           if (dl > dmax) dmax = dl;

@@ -1,0 +1,131 @@
+// Device-side building blocks shared by the IRKGL16 kernels (gfx950, FP64).
+//
+// Everything here is compiled with -ffp-contract=off: a product is only fused
+// into an fma where the code says fma(), so the two-double state updates keep
+// their exact error terms.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "irkgl16_coeffs.h"
+
+namespace irk {
+
+constexpr int kS = 8;  // stages
+
+// Force kinds (same numbering as the C ABI).
+constexpr int kKepler = 0;
+constexpr int kGravity = 1;
+constexpr int kChain = 2;
+
+// Per-instance status codes (same numbering as the C ABI).
+constexpr int kOk = 0;
+constexpr int kNonFinite = -4;
+
+// Device descriptor of one instance.  Offsets are in doubles (or bytes for
+// step_iters) into the context's arenas.
+struct InstDesc {
+  int64_t state_off;  // [q_hi, q_lo, v_hi, v_lo] x Dq, then R_prev as [Dq][8]
+  int64_t in_off;     // q0/p0 offset
+  int64_t out_off;    // first frame in q_out/p_out ([frame][Dq])
+  int64_t iters_off;  // per-step iteration counts, or -1
+  int64_t nsteps;
+  int64_t stride;
+  double h, G, eps, beta;
+  int32_t mass_off;      // n masses (GRAVITY, CHAIN) or -1 (all ones)
+  int32_t coupling_off;  // n+1 stiffnesses (CHAIN) or -1 (all ones)
+  int32_t kind, n, d, pad;
+};
+
+// Per-instance results, persistent across launches (resumable state).
+struct InstStat {
+  int64_t steps_done;
+  int64_t iterations;
+  int64_t nonconv;
+  int32_t max_k;
+  int32_t status;
+};
+
+// Coefficient table in device memory, read with wave-uniform (scalar) loads so
+// that the 8x8 tables live in SGPRs/scalar cache rather than as materialised
+// 64-bit immediates in vector registers.  Layout (doubles):
+// [0,8) c, [8,16) b, [16,80) eta, [80,144) mu, [144,208) nu (row-major, row =
+// stage formed, column = stage summed over).
+constexpr int kTabC = 0, kTabB = 8, kTabEta = 16, kTabMu = 80, kTabNu = 144, kTabSize = 208;
+
+// Pointer into the constant address space: loads through it with uniform
+// indices become scalar (SMEM) loads.
+typedef const __attribute__((address_space(4))) double* ConstTab;
+
+__device__ __forceinline__ ConstTab const_tab(const double* p) { return (ConstTab)p; }
+
+// Returns the same pointer, but opaque to the optimiser: loads through the
+// result cannot be hoisted above this point.  Used once per coefficient row so
+// that only the row in use occupies scalar registers (hoisting all 208
+// coefficients out of the step loop overflows the SGPR file).
+__device__ __forceinline__ ConstTab row_tab(ConstTab p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
+struct LaunchArgs {
+  const double* tab;
+  const InstDesc* desc;
+  InstStat* stat;
+  double* state;
+  const double* params;
+  double* qout;
+  double* pout;
+  uint8_t* step_iters;
+  const int32_t* queue;  // instance ids of this class, in processing order
+  int32_t queue_len;
+  int32_t max_iter;
+  int32_t* queue_head;   // atomic work counter (zeroed by the prepare kernel)
+  int64_t step_budget;   // max steps per instance in this launch (<= 0: all)
+};
+
+// x (+) d on a two-double value: (s, e) = TwoSum(hi, d); t = e + lo;
+// (hi, lo) = Fast2Sum(s, t).
+__device__ __forceinline__ void dw_add(double& hi, double& lo, double d) {
+  const double s = hi + d;
+  const double bv = s - hi;
+  const double e = (hi - (s - bv)) + (d - bv);
+  const double t = e + lo;
+  const double h2 = s + t;
+  lo = t - (h2 - s);
+  hi = h2;
+}
+
+// r2^(-3/2) for r2 > 0: hardware reciprocal square root refined by two
+// Newton-Raphson steps y <- y + y (1 - r2 y^2) / 2 (error ~1 ulp), then cubed.
+__device__ __forceinline__ double rinv3(double r2) {
+  double y = __builtin_amdgcn_rsq(r2);
+  double t = r2 * y;
+  double e = fma(-t, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  t = r2 * y;
+  e = fma(-t, y, 1.0);
+  y = fma(0.5 * y, e, y);
+  return (y * y) * y;
+}
+
+// Stopping rule of eq. stopping for one component: `mind` = min(Delta[1..k-2]),
+// `prev` = Delta[k-1], both +inf before the first iteration.  Returns whether
+// this component allows stopping and advances the history.
+__device__ __forceinline__ bool stop_component(double delta, double& mind, double& prev) {
+  const double m = (prev < delta) ? prev : delta;
+  const bool ok = (delta == 0.0) || (mind <= m);
+  if (prev < mind) mind = prev;
+  prev = delta;
+  return ok;
+}
+
+// NaN-keeping running maximum of |differences|.
+__device__ __forceinline__ double max_keep_nan(double acc, double a) {
+  return (a != a || a > acc) ? a : acc;
+}
+
+__device__ __forceinline__ bool finite(double x) { return x - x == 0.0; }
+
+}  // namespace irk

@@ -1,0 +1,509 @@
+// Host runtime behind the C ABI declared in include/irkgl16.h.
+//
+// A context owns the device copies of every instance's problem constants, a
+// resumable state arena (q, v as two-double values plus the previous step's
+// stage increments), per-instance statistics and one work queue per kernel
+// class.  irkgl16_integrate uploads per-call step sizes and counts, launches
+// the setup kernel and one persistent kernel per class on the context's
+// stream, and (in host-pointer mode) copies the output frames back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/irkgl16.h"
+#include "device_common.h"
+
+namespace irk {
+hipError_t launch_prepare(const InstDesc* desc, InstStat* stat, double* state,
+                          const double* params, const double* q0, const double* p0, double* qout,
+                          double* pout, uint8_t* step_iters, int32_t* heads, int n_heads,
+                          int n_inst, hipStream_t st);
+hipError_t launch_small_class(int kind, int nb, int d, const LaunchArgs& a, int n_items,
+                              int num_cus, hipStream_t st);
+bool small_class_supported(int kind, int nb, int d);
+hipError_t launch_wg_class(int kind, int d, int n, const LaunchArgs& a, int n_items, int num_cus,
+                           hipStream_t st);
+bool wg_class_supported(int kind, int n, int d);
+}  // namespace irk
+
+namespace {
+
+struct KernelClass {
+  int kind, nb, d;
+  bool small;
+  std::vector<int32_t> ids;
+  int64_t queue_off = 0;
+};
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  hipError_t ensure(size_t n) {
+    if (n <= bytes && p) return hipSuccess;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    if (n == 0) n = 8;
+    hipError_t e = hipMalloc(&p, n);
+    if (e == hipSuccess) bytes = n;
+    return e;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+bool finite(double x) { return std::isfinite(x); }
+
+int validate_problem(const irkgl16_problem& p) {
+  if (p.n < 1 || p.d < 1 || p.d > 3) return IRKGL16_EINVAL;
+  switch (p.kind) {
+    case IRKGL16_KEPLER:
+      if (p.n != 1 || p.d < 2 || !finite(p.G)) return IRKGL16_EINVAL;
+      return IRKGL16_OK;
+    case IRKGL16_GRAVITY:
+      if (!p.mass || !finite(p.G) || !finite(p.eps) || p.eps < 0.0) return IRKGL16_EINVAL;
+      for (int a = 0; a < p.n; ++a)
+        if (!(p.mass[a] > 0.0) || !finite(p.mass[a])) return IRKGL16_EINVAL;
+      return IRKGL16_OK;
+    case IRKGL16_CHAIN:
+      if (p.d != 1 || !finite(p.beta)) return IRKGL16_EINVAL;
+      if (p.mass)
+        for (int a = 0; a < p.n; ++a)
+          if (!(p.mass[a] > 0.0) || !finite(p.mass[a])) return IRKGL16_EINVAL;
+      if (p.coupling)
+        for (int a = 0; a <= p.n; ++a)
+          if (!finite(p.coupling[a])) return IRKGL16_EINVAL;
+      return IRKGL16_OK;
+    default:
+      return IRKGL16_EINVAL;
+  }
+}
+
+}  // namespace
+
+struct irkgl16_ctx {
+  int device = 0;
+  int num_cus = 1;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int32_t n_inst = 0;
+  int32_t max_iter = 100;
+  bool record = false;
+  uint32_t flags = 0;
+
+  std::vector<irk::InstDesc> desc;
+  std::vector<int32_t> dq;
+  std::vector<KernelClass> classes;
+  int64_t total_dq = 0;
+
+  DevBuf d_tab, d_desc, d_stat, d_state, d_params, d_queue, d_heads, d_plainq;
+  DevBuf d_q0, d_p0, d_qout, d_pout, d_iters;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+  // last call
+  bool have_last = false;
+  bool last_synced = false;
+  int64_t last_iters_total = 0;
+  std::vector<int64_t> last_nsteps;
+  std::vector<irk::InstStat> h_stat;
+  float last_ms = 0.f;
+
+  ~irkgl16_ctx() {
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+#define HIP_TRY(expr)                                   \
+  do {                                                  \
+    hipError_t _e = (expr);                             \
+    if (_e != hipSuccess) return IRKGL16_EDEVICE;       \
+  } while (0)
+
+static int alloc_try(DevBuf& b, size_t n) {
+  hipError_t e = b.ensure(n);
+  if (e == hipErrorOutOfMemory) return IRKGL16_ENOMEM;
+  if (e != hipSuccess) return IRKGL16_EDEVICE;
+  return IRKGL16_OK;
+}
+
+#define ALLOC_TRY(buf, n)                  \
+  do {                                     \
+    int _rc = alloc_try((buf), (n));       \
+    if (_rc != IRKGL16_OK) return _rc;     \
+  } while (0)
+
+static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t n_inst,
+                       const irkgl16_options* opt, void* hip_stream) {
+  if (!out) return IRKGL16_EINVAL;
+  *out = nullptr;
+  if (n_inst < 0 || (n_inst > 0 && !probs)) return IRKGL16_EINVAL;
+  for (int32_t i = 0; i < n_inst; ++i) {
+    int rc = validate_problem(probs[i]);
+    if (rc != IRKGL16_OK) return rc;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return IRKGL16_EDEVICE;
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return IRKGL16_EDEVICE;
+
+  irkgl16_ctx* c = new (std::nothrow) irkgl16_ctx();
+  if (!c) return IRKGL16_ENOMEM;
+  c->device = dev;
+  c->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+  c->n_inst = n_inst;
+  if (opt) {
+    c->max_iter = opt->max_iter > 0 ? opt->max_iter : 100;
+    c->record = opt->record_iters != 0;
+    c->flags = opt->flags;
+  }
+  if (c->max_iter > 255 && c->record) c->max_iter = 255;  // counts stored as bytes
+
+  auto fail = [&](int rc) {
+    delete c;
+    return rc;
+  };
+
+  // Problem constants and state layout.
+  std::vector<double> params;
+  c->desc.resize(n_inst);
+  c->dq.resize(n_inst);
+  int64_t state_off = 0;
+  std::map<std::tuple<int, int, int, int>, int> cls_index;
+  for (int32_t i = 0; i < n_inst; ++i) {
+    const irkgl16_problem& p = probs[i];
+    irk::InstDesc& d = c->desc[i];
+    std::memset(&d, 0, sizeof(d));
+    d.kind = p.kind;
+    d.n = p.n;
+    d.d = p.d;
+    d.G = p.G;
+    d.eps = p.eps;
+    d.beta = p.beta;
+    d.mass_off = -1;
+    d.coupling_off = -1;
+    if (p.mass && p.kind != IRKGL16_KEPLER) {
+      d.mass_off = (int32_t)params.size();
+      params.insert(params.end(), p.mass, p.mass + p.n);
+    }
+    if (p.coupling && p.kind == IRKGL16_CHAIN) {
+      d.coupling_off = (int32_t)params.size();
+      params.insert(params.end(), p.coupling, p.coupling + p.n + 1);
+    }
+    if (params.size() > (size_t)INT32_MAX) return fail(IRKGL16_EINVAL);
+    const int dqi = p.n * p.d;
+    c->dq[i] = dqi;
+    d.in_off = c->total_dq;
+    c->total_dq += dqi;
+    d.state_off = state_off;
+    state_off += (int64_t)(4 + irk::kS) * dqi;
+    // kernel class
+    bool small = irk::small_class_supported(p.kind, p.n, p.d);
+    if (!small && !irk::wg_class_supported(p.kind, p.n, p.d)) return fail(IRKGL16_EINVAL);
+    auto key = small ? std::make_tuple(1, p.kind, p.n, p.d) : std::make_tuple(0, p.kind, 0, p.d);
+    auto it = cls_index.find(key);
+    int ci;
+    if (it == cls_index.end()) {
+      ci = (int)c->classes.size();
+      cls_index[key] = ci;
+      KernelClass kc;
+      kc.kind = p.kind;
+      kc.nb = small ? p.n : 0;
+      kc.d = p.d;
+      kc.small = small;
+      c->classes.push_back(kc);
+    } else {
+      ci = it->second;
+    }
+    c->classes[ci].ids.push_back(i);
+  }
+  // Generic classes process larger systems first (longest-processing-time order).
+  for (auto& kc : c->classes)
+    if (!kc.small)
+      std::stable_sort(kc.ids.begin(), kc.ids.end(),
+                       [&](int32_t x, int32_t y) { return c->dq[x] > c->dq[y]; });
+  std::vector<int32_t> queue;
+  for (auto& kc : c->classes) {
+    kc.queue_off = (int64_t)queue.size();
+    queue.insert(queue.end(), kc.ids.begin(), kc.ids.end());
+  }
+  std::vector<int32_t> plainq(n_inst);
+  for (int32_t i = 0; i < n_inst; ++i) plainq[i] = i;
+
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreate(&c->stream) != hipSuccess) return fail(IRKGL16_EDEVICE);
+    c->own_stream = true;
+  }
+  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess)
+    return fail(IRKGL16_EDEVICE);
+
+  int rc;
+  if ((rc = alloc_try(c->d_desc, sizeof(irk::InstDesc) * (size_t)std::max(n_inst, 1))) ||
+      (rc = alloc_try(c->d_stat, sizeof(irk::InstStat) * (size_t)std::max(n_inst, 1))) ||
+      (rc = alloc_try(c->d_state, sizeof(double) * (size_t)std::max<int64_t>(state_off, 1))) ||
+      (rc = alloc_try(c->d_params, sizeof(double) * std::max<size_t>(params.size(), 1))) ||
+      (rc = alloc_try(c->d_queue, sizeof(int32_t) * std::max<size_t>(queue.size(), 1))) ||
+      (rc = alloc_try(c->d_plainq, sizeof(int32_t) * std::max<size_t>(plainq.size(), 1))) ||
+      (rc = alloc_try(c->d_heads, sizeof(int32_t) * std::max<size_t>(c->classes.size(), 1))))
+    return fail(rc);
+  {
+    // Coefficient table (layout described in device_common.h).
+    std::vector<double> tab(irk::kTabSize);
+    for (int i = 0; i < irk::kS; ++i) {
+      tab[irk::kTabC + i] = irk::kC[i];
+      tab[irk::kTabB + i] = irk::kB[i];
+      for (int j = 0; j < irk::kS; ++j) {
+        tab[irk::kTabEta + i * irk::kS + j] = irk::kEta[i][j];
+        tab[irk::kTabMu + i * irk::kS + j] = irk::kMu[i][j];
+        tab[irk::kTabNu + i * irk::kS + j] = irk::kNu[i][j];
+      }
+    }
+    if ((rc = alloc_try(c->d_tab, sizeof(double) * tab.size()))) return fail(rc);
+    if (hipMemcpy(c->d_tab.p, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice) !=
+        hipSuccess)
+      return fail(IRKGL16_EDEVICE);
+  }
+  if (!params.empty() &&
+      hipMemcpy(c->d_params.p, params.data(), sizeof(double) * params.size(),
+                hipMemcpyHostToDevice) != hipSuccess)
+    return fail(IRKGL16_EDEVICE);
+  if (!queue.empty() &&
+      (hipMemcpy(c->d_queue.p, queue.data(), sizeof(int32_t) * queue.size(),
+                 hipMemcpyHostToDevice) != hipSuccess ||
+       hipMemcpy(c->d_plainq.p, plainq.data(), sizeof(int32_t) * plainq.size(),
+                 hipMemcpyHostToDevice) != hipSuccess))
+    return fail(IRKGL16_EDEVICE);
+  *out = c;
+  return IRKGL16_OK;
+}
+
+static irk::LaunchArgs base_args(irkgl16_ctx* c, double* qout, double* pout) {
+  irk::LaunchArgs a;
+  a.tab = c->d_tab.as<double>();
+  a.desc = c->d_desc.as<irk::InstDesc>();
+  a.stat = c->d_stat.as<irk::InstStat>();
+  a.state = c->d_state.as<double>();
+  a.params = c->d_params.as<double>();
+  a.qout = qout;
+  a.pout = pout;
+  a.step_iters = c->record ? c->d_iters.as<uint8_t>() : nullptr;
+  a.queue = nullptr;
+  a.queue_len = 0;
+  a.max_iter = c->max_iter;
+  a.queue_head = nullptr;
+  a.step_budget = 0;
+  return a;
+}
+
+static hipError_t launch_class(irkgl16_ctx* c, const KernelClass& kc, const irk::LaunchArgs& a,
+                               int n_items) {
+  if (kc.small) return irk::launch_small_class(kc.kind, kc.nb, kc.d, a, n_items, c->num_cus, c->stream);
+  return irk::launch_wg_class(kc.kind, kc.d, 0, a, n_items, c->num_cus, c->stream);
+}
+
+static int integrate_impl(irkgl16_ctx* c, const double* q0, const double* p0, const double* h,
+                          const int64_t* nsteps, const int64_t* out_stride, double* q_out,
+                          double* p_out, irkgl16_stats* stats) {
+  if (!c) return IRKGL16_EINVAL;
+  const int32_t n = c->n_inst;
+  if (n > 0 && (!q0 || !p0 || !h || !nsteps || !out_stride || !q_out || !p_out))
+    return IRKGL16_EINVAL;
+  int64_t out_total = 0, iters_total = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    if (!std::isfinite(h[i]) || h[i] == 0.0 || nsteps[i] < 0 || out_stride[i] < 1 ||
+        nsteps[i] % out_stride[i] != 0)
+      return IRKGL16_EINVAL;
+    irk::InstDesc& d = c->desc[i];
+    d.h = h[i];
+    d.nsteps = nsteps[i];
+    d.stride = out_stride[i];
+    d.out_off = out_total;
+    out_total += (int64_t)c->dq[i] * (nsteps[i] / out_stride[i] + 1);
+    d.iters_off = c->record ? iters_total : -1;
+    iters_total += nsteps[i];
+  }
+  if (hipSetDevice(c->device) != hipSuccess) return IRKGL16_EDEVICE;
+  const bool dev = (c->flags & IRKGL16_DEVICE_PTRS) != 0;
+  const double *dq0 = q0, *dp0 = p0;
+  double *dqo = q_out, *dpo = p_out;
+  if (!dev) {
+    ALLOC_TRY(c->d_q0, sizeof(double) * (size_t)std::max<int64_t>(c->total_dq, 1));
+    ALLOC_TRY(c->d_p0, sizeof(double) * (size_t)std::max<int64_t>(c->total_dq, 1));
+    ALLOC_TRY(c->d_qout, sizeof(double) * (size_t)std::max<int64_t>(out_total, 1));
+    ALLOC_TRY(c->d_pout, sizeof(double) * (size_t)std::max<int64_t>(out_total, 1));
+    dq0 = c->d_q0.as<double>();
+    dp0 = c->d_p0.as<double>();
+    dqo = c->d_qout.as<double>();
+    dpo = c->d_pout.as<double>();
+  }
+  if (c->record) ALLOC_TRY(c->d_iters, (size_t)std::max<int64_t>(iters_total, 1));
+  c->last_nsteps.assign(nsteps, nsteps + n);
+  c->last_iters_total = iters_total;
+  c->have_last = true;
+  c->last_synced = false;
+  if (n == 0) return IRKGL16_OK;
+
+  HIP_TRY(hipMemcpyAsync(c->d_desc.p, c->desc.data(), sizeof(irk::InstDesc) * n,
+                         hipMemcpyHostToDevice, c->stream));
+  if (!dev) {
+    HIP_TRY(hipMemcpyAsync(c->d_q0.p, q0, sizeof(double) * c->total_dq, hipMemcpyHostToDevice,
+                           c->stream));
+    HIP_TRY(hipMemcpyAsync(c->d_p0.p, p0, sizeof(double) * c->total_dq, hipMemcpyHostToDevice,
+                           c->stream));
+  }
+  HIP_TRY(hipEventRecord(c->ev0, c->stream));
+  HIP_TRY(irk::launch_prepare(c->d_desc.as<irk::InstDesc>(), c->d_stat.as<irk::InstStat>(),
+                              c->d_state.as<double>(), c->d_params.as<double>(), dq0, dp0, dqo,
+                              dpo, c->record ? c->d_iters.as<uint8_t>() : nullptr,
+                              c->d_heads.as<int32_t>(), (int)c->classes.size(), n, c->stream));
+  irk::LaunchArgs a = base_args(c, dqo, dpo);
+  if (c->flags & IRKGL16_PLAIN) {
+    // Plain form: one launch per step per instance, instances in turn.
+    for (const auto& kc : c->classes) {
+      for (int32_t id : kc.ids) {
+        irk::LaunchArgs pa = a;
+        pa.queue = c->d_plainq.as<int32_t>() + id;
+        pa.queue_len = 1;
+        pa.queue_head = nullptr;
+        pa.step_budget = 1;
+        for (int64_t s = 0; s < nsteps[id]; ++s) HIP_TRY(launch_class(c, kc, pa, 1));
+      }
+    }
+  } else {
+    for (size_t k = 0; k < c->classes.size(); ++k) {
+      const auto& kc = c->classes[k];
+      irk::LaunchArgs ca = a;
+      ca.queue = c->d_queue.as<int32_t>() + kc.queue_off;
+      ca.queue_len = (int32_t)kc.ids.size();
+      ca.queue_head = c->d_heads.as<int32_t>() + k;
+      HIP_TRY(launch_class(c, kc, ca, (int)kc.ids.size()));
+    }
+  }
+  HIP_TRY(hipEventRecord(c->ev1, c->stream));
+  if (!dev) {
+    HIP_TRY(hipMemcpyAsync(q_out, dqo, sizeof(double) * out_total, hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipMemcpyAsync(p_out, dpo, sizeof(double) * out_total, hipMemcpyDeviceToHost,
+                           c->stream));
+    return irkgl16_last_stats(c, stats);
+  }
+  if (stats) return irkgl16_last_stats(c, stats);
+  return IRKGL16_OK;
+}
+
+extern "C" {
+
+int irkgl16_create(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t n_inst,
+                   const irkgl16_options* opt, void* hip_stream) {
+  try {
+    return create_impl(out, probs, n_inst, opt, hip_stream);
+  } catch (const std::bad_alloc&) {
+    return IRKGL16_ENOMEM;
+  } catch (...) {
+    return IRKGL16_EDEVICE;
+  }
+}
+
+int irkgl16_integrate(irkgl16_ctx* ctx, const double* q0, const double* p0, const double* h,
+                      const int64_t* nsteps, const int64_t* out_stride, double* q_out,
+                      double* p_out, irkgl16_stats* stats) {
+  try {
+    return integrate_impl(ctx, q0, p0, h, nsteps, out_stride, q_out, p_out, stats);
+  } catch (const std::bad_alloc&) {
+    return IRKGL16_ENOMEM;
+  } catch (...) {
+    return IRKGL16_EDEVICE;
+  }
+}
+
+int irkgl16_last_stats(irkgl16_ctx* c, irkgl16_stats* stats) {
+  if (!c) return IRKGL16_EINVAL;
+  if (!c->have_last) return IRKGL16_EINVAL;
+  try {
+    if (!c->last_synced) {
+      HIP_TRY(hipStreamSynchronize(c->stream));
+      c->h_stat.resize(c->n_inst);
+      if (c->n_inst > 0)
+        HIP_TRY(hipMemcpy(c->h_stat.data(), c->d_stat.p, sizeof(irk::InstStat) * c->n_inst,
+                          hipMemcpyDeviceToHost));
+      float ms = 0.f;
+      if (c->n_inst > 0 && hipEventElapsedTime(&ms, c->ev0, c->ev1) == hipSuccess)
+        c->last_ms = ms;
+      else
+        c->last_ms = 0.f;
+      c->last_synced = true;
+    }
+    int worst = IRKGL16_OK;
+    int64_t steps = 0, iters = 0, nonconv = 0;
+    int32_t maxk = 0, nnf = 0;
+    for (int32_t i = 0; i < c->n_inst; ++i) {
+      const irk::InstStat& s = c->h_stat[i];
+      steps += s.steps_done;
+      iters += s.iterations;
+      nonconv += s.nonconv;
+      maxk = std::max(maxk, s.max_k);
+      int st = s.status;
+      if (st == irk::kOk && s.nonconv > 0) st = IRKGL16_ENOCONV;
+      if (s.status == irk::kNonFinite) ++nnf;
+      if (st < 0 && (worst >= 0 || st < worst)) worst = st;
+      if (st > 0 && worst == IRKGL16_OK) worst = st;
+      if (stats) {
+        if (stats->inst_iterations) stats->inst_iterations[i] = s.iterations;
+        if (stats->inst_status) stats->inst_status[i] = st;
+      }
+    }
+    if (stats) {
+      stats->steps = steps;
+      stats->iterations = iters;
+      stats->nonconverged_steps = nonconv;
+      stats->max_k = maxk;
+      stats->n_nonfinite = nnf;
+      stats->device_ms = (double)c->last_ms;
+      if (stats->step_iters && c->record && c->last_iters_total > 0)
+        HIP_TRY(hipMemcpy(stats->step_iters, c->d_iters.p, (size_t)c->last_iters_total,
+                          hipMemcpyDeviceToHost));
+    }
+    return worst;
+  } catch (...) {
+    return IRKGL16_EDEVICE;
+  }
+}
+
+void irkgl16_destroy(irkgl16_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  delete ctx;
+}
+
+const char* irkgl16_strerror(int status) {
+  switch (status) {
+    case IRKGL16_OK: return "ok";
+    case IRKGL16_EINVAL: return "invalid argument";
+    case IRKGL16_ENOMEM: return "out of memory";
+    case IRKGL16_EDEVICE: return "no usable gfx950 GPU or HIP runtime error";
+    case IRKGL16_ENONFINITE: return "an instance produced a non-finite value";
+    case IRKGL16_ENOCONV: return "some steps stopped at the iteration cap";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,223 @@
+"""ctypes binding of ``libirkgl16.so`` (C ABI in ``include/irkgl16.h``).
+
+Argument marshalling only: every integration step runs in the library's HIP
+kernels.  The functions carry the C names; :class:`Integrator` is a small
+convenience wrapper around them.  Importing this module never falls back to
+another implementation: if the library is missing or cannot be loaded,
+:func:`lib` raises.
+
+Host mode takes numpy arrays.  Device mode (``IRKGL16_DEVICE_PTRS``) takes
+torch CUDA tensors (float64) whose memory the caller owns; the work is
+enqueued on the stream given at creation and the caller synchronizes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libirkgl16.so")
+
+IRKGL16_OK, IRKGL16_EINVAL, IRKGL16_ENOMEM, IRKGL16_EDEVICE = 0, -1, -2, -3
+IRKGL16_ENONFINITE, IRKGL16_ENOCONV = -4, 1
+IRKGL16_KEPLER, IRKGL16_GRAVITY, IRKGL16_CHAIN = 0, 1, 2
+IRKGL16_DEVICE_PTRS, IRKGL16_PLAIN = 1, 2
+
+EXPORTED = ["irkgl16_create", "irkgl16_integrate", "irkgl16_last_stats", "irkgl16_destroy",
+            "irkgl16_strerror"]
+
+
+class irkgl16_problem(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n", C.c_int32), ("d", C.c_int32),
+                ("mass", C.POINTER(C.c_double)), ("coupling", C.POINTER(C.c_double)),
+                ("G", C.c_double), ("eps", C.c_double), ("beta", C.c_double)]
+
+
+class irkgl16_options(C.Structure):
+    _fields_ = [("max_iter", C.c_int32), ("record_iters", C.c_int32), ("flags", C.c_uint32)]
+
+
+class irkgl16_stats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("iterations", C.c_int64),
+                ("nonconverged_steps", C.c_int64), ("max_k", C.c_int32),
+                ("n_nonfinite", C.c_int32), ("device_ms", C.c_double),
+                ("inst_iterations", C.POINTER(C.c_int64)), ("inst_status", C.POINTER(C.c_int32)),
+                ("step_iters", C.POINTER(C.c_uint8))]
+
+
+class IRKGL16Error(RuntimeError):
+    def __init__(self, code, what=""):
+        self.code = code
+        super().__init__(f"{what}: {irkgl16_strerror(code)} ({code})")
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library (raises if it is not built or cannot be loaded)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run paper_2511_03655_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        dp, i64p = C.POINTER(C.c_double), C.POINTER(C.c_int64)
+        L.irkgl16_create.argtypes = [C.POINTER(C.c_void_p), C.POINTER(irkgl16_problem), C.c_int32,
+                                     C.POINTER(irkgl16_options), C.c_void_p]
+        L.irkgl16_create.restype = C.c_int
+        L.irkgl16_integrate.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, dp, i64p, i64p,
+                                        C.c_void_p, C.c_void_p, C.POINTER(irkgl16_stats)]
+        L.irkgl16_integrate.restype = C.c_int
+        L.irkgl16_last_stats.argtypes = [C.c_void_p, C.POINTER(irkgl16_stats)]
+        L.irkgl16_last_stats.restype = C.c_int
+        L.irkgl16_destroy.argtypes = [C.c_void_p]
+        L.irkgl16_destroy.restype = None
+        L.irkgl16_strerror.argtypes = [C.c_int]
+        L.irkgl16_strerror.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def irkgl16_strerror(code):
+    return lib().irkgl16_strerror(int(code)).decode()
+
+
+def _ptr(x):
+    """Address of a numpy array or a torch tensor (no copies)."""
+    if x is None:
+        return None
+    if hasattr(x, "data_ptr"):
+        return C.c_void_p(x.data_ptr())
+    return C.c_void_p(x.ctypes.data)
+
+
+def irkgl16_create(problems, max_iter=0, record_iters=False, flags=0, stream=None):
+    """problems: list of dicts with kind, n, d, mass, coupling, G, eps, beta.
+
+    Returns (ctx_handle, keepalive).  stream: a hipStream_t address or a torch
+    stream (its raw handle is passed).
+    """
+    n = len(problems)
+    arr = (irkgl16_problem * max(n, 1))()
+    keep = []
+    for i, p in enumerate(problems):
+        mass = p.get("mass")
+        coup = p.get("coupling")
+        m = None if mass is None else np.ascontiguousarray(mass, np.float64)
+        c = None if coup is None else np.ascontiguousarray(coup, np.float64)
+        keep += [m, c]
+        arr[i] = irkgl16_problem(int(p["kind"]), int(p["n"]), int(p["d"]),
+                                 m.ctypes.data_as(C.POINTER(C.c_double)) if m is not None else None,
+                                 c.ctypes.data_as(C.POINTER(C.c_double)) if c is not None else None,
+                                 float(p.get("G", 1.0)), float(p.get("eps", 0.0)),
+                                 float(p.get("beta", 0.0)))
+    opt = irkgl16_options(int(max_iter), int(bool(record_iters)), int(flags))
+    if stream is not None and hasattr(stream, "cuda_stream"):
+        stream = stream.cuda_stream
+    ctx = C.c_void_p()
+    rc = lib().irkgl16_create(C.byref(ctx), arr, n, C.byref(opt),
+                              C.c_void_p(stream) if stream else None)
+    if rc != IRKGL16_OK:
+        raise IRKGL16Error(rc, "irkgl16_create")
+    return ctx
+
+
+def irkgl16_integrate(ctx, q0, p0, h, nsteps, out_stride, q_out, p_out, stats=None):
+    h = np.ascontiguousarray(h, np.float64)
+    ns = np.ascontiguousarray(nsteps, np.int64)
+    sd = np.ascontiguousarray(out_stride, np.int64)
+    return lib().irkgl16_integrate(ctx, _ptr(q0), _ptr(p0),
+                                   h.ctypes.data_as(C.POINTER(C.c_double)),
+                                   ns.ctypes.data_as(C.POINTER(C.c_int64)),
+                                   sd.ctypes.data_as(C.POINTER(C.c_int64)), _ptr(q_out),
+                                   _ptr(p_out), C.byref(stats) if stats is not None else None)
+
+
+def irkgl16_last_stats(ctx, stats):
+    return lib().irkgl16_last_stats(ctx, C.byref(stats))
+
+
+def irkgl16_destroy(ctx):
+    if ctx:
+        lib().irkgl16_destroy(ctx)
+
+
+class Integrator:
+    """Owns one context.  Packing follows the C ABI: instances concatenated."""
+
+    def __init__(self, problems, max_iter=0, record_iters=False, flags=0, stream=None):
+        self.problems = list(problems)
+        self.dq = np.array([int(p["n"]) * int(p["d"]) for p in self.problems], np.int64)
+        self.flags = int(flags)
+        self.record_iters = bool(record_iters)
+        self.ctx = irkgl16_create(self.problems, max_iter, record_iters, flags, stream)
+
+    def close(self):
+        if self.ctx:
+            irkgl16_destroy(self.ctx)
+            self.ctx = None
+
+    __del__ = close
+
+    def frames(self, nsteps, stride):
+        return np.asarray(nsteps, np.int64) // np.asarray(stride, np.int64) + 1
+
+    def integrate(self, q0, p0, h, nsteps, out_stride, q_out=None, p_out=None, check=True):
+        """Host mode: numpy in, numpy out.  Returns (q_out, p_out, stats dict, rc)."""
+        n = len(self.problems)
+        h = np.broadcast_to(np.asarray(h, np.float64), (n,))
+        ns = np.broadcast_to(np.asarray(nsteps, np.int64), (n,))
+        sd = np.broadcast_to(np.asarray(out_stride, np.int64), (n,))
+        total = int(np.sum(self.dq * (ns // np.maximum(sd, 1) + 1)))
+        dev = bool(self.flags & IRKGL16_DEVICE_PTRS)
+        if not dev:
+            q0 = np.ascontiguousarray(q0, np.float64)
+            p0 = np.ascontiguousarray(p0, np.float64)
+            if q_out is None:
+                q_out = np.empty(total)
+            if p_out is None:
+                p_out = np.empty(total)
+        st = irkgl16_stats()
+        inst_it = np.zeros(n, np.int64)
+        inst_st = np.zeros(n, np.int32)
+        st.inst_iterations = inst_it.ctypes.data_as(C.POINTER(C.c_int64))
+        st.inst_status = inst_st.ctypes.data_as(C.POINTER(C.c_int32))
+        step_it = None
+        if self.record_iters:
+            step_it = np.zeros(int(np.sum(ns)), np.uint8)
+            st.step_iters = step_it.ctypes.data_as(C.POINTER(C.c_uint8))
+        rc = irkgl16_integrate(self.ctx, q0, p0, h, ns, sd, q_out, p_out,
+                               None if dev else st)
+        if check and rc < 0 and rc != IRKGL16_ENONFINITE:
+            raise IRKGL16Error(rc, "irkgl16_integrate")
+        if dev:
+            return q_out, p_out, None, rc
+        return q_out, p_out, dict(steps=st.steps, iterations=st.iterations,
+                                  nonconverged_steps=st.nonconverged_steps, max_k=st.max_k,
+                                  n_nonfinite=st.n_nonfinite, device_ms=st.device_ms,
+                                  inst_iterations=inst_it, inst_status=inst_st,
+                                  step_iters=step_it), rc
+
+    def last_stats(self):
+        n = len(self.problems)
+        st = irkgl16_stats()
+        inst_it = np.zeros(n, np.int64)
+        inst_st = np.zeros(n, np.int32)
+        st.inst_iterations = inst_it.ctypes.data_as(C.POINTER(C.c_int64))
+        st.inst_status = inst_st.ctypes.data_as(C.POINTER(C.c_int32))
+        rc = irkgl16_last_stats(self.ctx, st)
+        return dict(steps=st.steps, iterations=st.iterations,
+                    nonconverged_steps=st.nonconverged_steps, max_k=st.max_k,
+                    n_nonfinite=st.n_nonfinite, device_ms=st.device_ms,
+                    inst_iterations=inst_it, inst_status=inst_st), rc
+
+
+def split_frames(flat, dq, nframes):
+    """Unpack a packed output array into a list of (frames, Dq) arrays."""
+    out, off = [], 0
+    for d, f in zip(np.atleast_1d(dq), np.atleast_1d(nframes)):
+        out.append(np.asarray(flat[off:off + d * f]).reshape(f, d))
+        off += d * f
+    return out

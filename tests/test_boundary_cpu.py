@@ -1,0 +1,75 @@
+"""C-ABI boundary checks that need no GPU: the library loads, exports every
+symbol the header declares, validates arguments and reports a missing device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2511_03655_amd import irkgl16 as K
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "irkgl16.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(irkgl16_\w+)\s*\(", src)))
+
+
+def test_header_symbols_are_exported():
+    L = K.lib()
+    names = declared_functions()
+    assert names, "no declarations found"
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) <= set(K.EXPORTED) | set(names)
+
+
+def test_strerror_covers_codes():
+    for code in (0, -1, -2, -3, -4, 1):
+        assert K.irkgl16_strerror(code) != "unknown status"
+    assert K.irkgl16_strerror(12345) == "unknown status"
+
+
+def _has_gpu():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+@pytest.mark.skipif(_has_gpu(), reason="checks the no-device path")
+def test_create_without_gpu_reports_edevice():
+    p = [dict(kind=K.IRKGL16_KEPLER, n=1, d=2, G=1.0)]
+    with pytest.raises(K.IRKGL16Error) as e:
+        K.irkgl16_create(p)
+    assert e.value.code == K.IRKGL16_EDEVICE
+
+
+@pytest.mark.parametrize("bad", [
+    dict(kind=7, n=1, d=2),
+    dict(kind=K.IRKGL16_KEPLER, n=2, d=2),
+    dict(kind=K.IRKGL16_KEPLER, n=1, d=1),
+    dict(kind=K.IRKGL16_GRAVITY, n=3, d=3),                       # no masses
+    dict(kind=K.IRKGL16_GRAVITY, n=2, d=3, mass=[1.0, -1.0]),
+    dict(kind=K.IRKGL16_GRAVITY, n=2, d=3, mass=[1.0, 1.0], eps=-1.0),
+    dict(kind=K.IRKGL16_GRAVITY, n=2, d=3, mass=[1.0, np.nan]),
+    dict(kind=K.IRKGL16_CHAIN, n=4, d=2),
+    dict(kind=K.IRKGL16_CHAIN, n=4, d=1, beta=np.inf),
+    dict(kind=K.IRKGL16_CHAIN, n=0, d=1),
+])
+def test_create_rejects_invalid_problems(bad):
+    with pytest.raises(K.IRKGL16Error) as e:
+        K.irkgl16_create([bad])
+    assert e.value.code == K.IRKGL16_EINVAL
+
+
+def test_null_arguments_rejected():
+    L = K.lib()
+    assert L.irkgl16_create(None, None, 0, None, None) == K.IRKGL16_EINVAL
+    assert L.irkgl16_integrate(None, None, None, None, None, None, None, None, None) == K.IRKGL16_EINVAL
+    assert L.irkgl16_last_stats(None, None) == K.IRKGL16_EINVAL
+    L.irkgl16_destroy(None)  # NULL-safe
