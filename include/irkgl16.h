@@ -50,6 +50,15 @@ extern "C" {
 /* Plain form: one kernel launch per step per instance, instances in turn (the
  * comparison baseline for the batched persistent kernel). */
 #define IRKGL16_PLAIN 2u
+/* Reproducible arithmetic: every operation in the reference order of a plain
+ * strict-IEEE evaluation of the formulas (separate multiply and add, sums from
+ * zero in ascending index order, correctly rounded square root and division,
+ * forces summed over ordered pairs), so results are bit-identical to such a
+ * CPU implementation.  Slower; the default uses fused multiply-adds, a refined
+ * reciprocal square root and pair symmetry (results then agree to rounding
+ * level, and the fixed-point iteration counts, which are decided at rounding
+ * level, may differ). */
+#define IRKGL16_REPRODUCIBLE 4u
 
 typedef struct irkgl16_ctx irkgl16_ctx;
 

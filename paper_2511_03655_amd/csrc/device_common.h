@@ -83,6 +83,7 @@ struct LaunchArgs {
   int32_t max_iter;
   int32_t* queue_head;   // atomic work counter (zeroed by the prepare kernel)
   int64_t step_budget;   // max steps per instance in this launch (<= 0: all)
+  int32_t exact;         // reproducible arithmetic (see the EXACT policies below)
 };
 
 // x (+) d on a two-double value: (s, e) = TwoSum(hi, d); t = e + lo;
@@ -127,5 +128,71 @@ __device__ __forceinline__ double max_keep_nan(double acc, double a) {
 }
 
 __device__ __forceinline__ bool finite(double x) { return x - x == 0.0; }
+
+// ---------------------------------------------------------------------------
+// Arithmetic policies.  EXACT = false: fused multiply-adds and the refined
+// reciprocal square root (fastest).  EXACT = true: the reference operation
+// order of a plain IEEE implementation -- separate multiply and add, sums from
+// 0.0 in ascending index order, correctly rounded sqrt and division -- so that
+// results are bit-identical to a strict-IEEE CPU evaluation of the same
+// formulas.
+
+// sum_j w[off + j] x[j], j = 0..7
+template <bool EXACT>
+__device__ __forceinline__ double row_dot(ConstTab w, int off, const double (&x)[kS]) {
+  if constexpr (EXACT) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < kS; ++j) s = s + w[off + j] * x[j];
+    return s;
+  } else {
+    double s = w[off] * x[0];
+#pragma unroll
+    for (int j = 1; j < kS; ++j) s = fma(w[off + j], x[j], s);
+    return s;
+  }
+}
+
+// Stage value q + h (c_s v + sum_j eta_sj R_j)  (eqs. Qi2 / IRK_FP2).
+template <bool EXACT>
+__device__ __forceinline__ double stage_value(ConstTab w, int s, double q, double v, double h,
+                                              const double (&R)[kS]) {
+  if constexpr (EXACT) {
+    return q + h * (w[kTabC + s] * v + row_dot<true>(w, kTabEta + s * kS, R));
+  } else {
+    double acc = w[kTabC + s] * v;
+#pragma unroll
+    for (int j = 0; j < kS; ++j) acc = fma(w[kTabEta + s * kS + j], R[j], acc);
+    return fma(h, acc, q);
+  }
+}
+
+// sum_i R_i and sum_i c_i R_i (eq. qnvn2).
+template <bool EXACT>
+__device__ __forceinline__ void step_sums(ConstTab w, const double (&R)[kS], double& sv,
+                                          double& sc) {
+  if constexpr (EXACT) {
+    sv = 0.0;
+#pragma unroll
+    for (int i = 0; i < kS; ++i) sv = sv + R[i];
+    sc = row_dot<true>(w, kTabC, R);
+  } else {
+    sv = R[0];
+#pragma unroll
+    for (int i = 1; i < kS; ++i) sv += R[i];
+    sc = row_dot<false>(w, kTabC, R);
+  }
+}
+
+// (|d|^2 + eps^2)^(-3/2) times m: fast form via the refined reciprocal square
+// root, exact form m / (r2 sqrt(r2)) with correctly rounded sqrt and division.
+template <bool EXACT>
+__device__ __forceinline__ double pair_weight(double r2, double m) {
+  if constexpr (EXACT) {
+    return m / (r2 * sqrt(r2));
+  } else {
+    return m * rinv3(r2);
+  }
+}
 
 }  // namespace irk

@@ -26,7 +26,7 @@ namespace irk {
 // Initial guess for the owned components from their previous-step increments
 // Rp (eq. IRK_init2): V0_i = v + sum_j nu_ij Rp_j, L0_j = h b_j V0_j,
 // Q_i = q + sum_j mu_ij L0_j.  Rows of nu and mu are fetched one at a time.
-template <int CPL>
+template <int CPL, bool EXACT>
 __device__ __forceinline__ void initial_guess(ConstTab T, const double (&qh)[CPL],
                                               const double (&vh)[CPL], const double (&Rp)[CPL][kS],
                                               double h, double (&Q)[CPL][kS]) {
@@ -36,45 +36,71 @@ __device__ __forceinline__ void initial_guess(ConstTab T, const double (&qh)[CPL
     const ConstTab r = row_tab(T);
     const double hb = h * r[kTabB + s];
 #pragma unroll
-    for (int cc = 0; cc < CPL; ++cc) {
-      double acc = r[kTabNu + s * kS] * Rp[cc][0];
-#pragma unroll
-      for (int j = 1; j < kS; ++j) acc = fma(r[kTabNu + s * kS + j], Rp[cc][j], acc);
-      L0[cc][s] = hb * (vh[cc] + acc);
-    }
+    for (int cc = 0; cc < CPL; ++cc) L0[cc][s] = hb * (vh[cc] + row_dot<EXACT>(r, kTabNu + s * kS, Rp[cc]));
   }
 #pragma unroll
   for (int s = 0; s < kS; ++s) {
     const ConstTab r = row_tab(T);
 #pragma unroll
-    for (int cc = 0; cc < CPL; ++cc) {
-      double acc = r[kTabMu + s * kS] * L0[cc][0];
-#pragma unroll
-      for (int j = 1; j < kS; ++j) acc = fma(r[kTabMu + s * kS + j], L0[cc][j], acc);
-      Q[cc][s] = qh[cc] + acc;
-    }
+    for (int cc = 0; cc < CPL; ++cc) Q[cc][s] = qh[cc] + row_dot<EXACT>(r, kTabMu + s * kS, L0[cc]);
   }
 }
 
 // Reads the stage positions from column `sub` of the slot tile and overwrites
 // the same column with the increments R_sub = h b_sub g(Q_sub): a lane only
 // touches its own column, so no barrier is needed between the read and the
-// write.  Ms: the slot's masses (LDS).
-template <int KIND, int NB, int D>
+// write.  Ms: the slot's masses (LDS); coef = (h b_sub) and G.
+template <int KIND, int NB, int D, bool EXACT>
 __device__ __forceinline__ void stage_increment(double* __restrict__ Xs, int sub,
                                                 const double* __restrict__ Ms, double eps2,
-                                                double coef) {
+                                                double hb, double G) {
   constexpr int DQ = NB * D;
   if constexpr (KIND == kKepler) {
     double q[DQ];
 #pragma unroll
     for (int l = 0; l < DQ; ++l) q[l] = Xs[l * kS + sub];
-    double r2 = q[0] * q[0];
+    if constexpr (EXACT) {  // g = -G q / (r2 sqrt(r2))
+      double r2 = 0.0;
 #pragma unroll
-    for (int l = 1; l < DQ; ++l) r2 = fma(q[l], q[l], r2);
-    const double w = -coef * rinv3(r2);
+      for (int l = 0; l < DQ; ++l) r2 = r2 + q[l] * q[l];
+      const double r3 = r2 * sqrt(r2);
 #pragma unroll
-    for (int l = 0; l < DQ; ++l) Xs[l * kS + sub] = w * q[l];
+      for (int l = 0; l < DQ; ++l) Xs[l * kS + sub] = hb * (-G * q[l] / r3);
+    } else {
+      double r2 = q[0] * q[0];
+#pragma unroll
+      for (int l = 1; l < DQ; ++l) r2 = fma(q[l], q[l], r2);
+      const double w = -(hb * G) * rinv3(r2);
+#pragma unroll
+      for (int l = 0; l < DQ; ++l) Xs[l * kS + sub] = w * q[l];
+    }
+  } else if constexpr (EXACT) {
+    // Ordered pairs, b ascending for every a, as in the force's definition.
+    double out[DQ];
+#pragma unroll
+    for (int a = 0; a < NB; ++a) {
+      double acc[D];
+#pragma unroll
+      for (int k = 0; k < D; ++k) acc[k] = 0.0;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        if (b == a) continue;
+        double dx[D], r2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          dx[k] = Xs[(b * D + k) * kS + sub] - Xs[(a * D + k) * kS + sub];
+          r2 = r2 + dx[k] * dx[k];
+        }
+        r2 = r2 + eps2;
+        const double w = pair_weight<true>(r2, Ms[b]);
+#pragma unroll
+        for (int k = 0; k < D; ++k) acc[k] = acc[k] + w * dx[k];
+      }
+#pragma unroll
+      for (int k = 0; k < D; ++k) out[a * D + k] = hb * (G * acc[k]);
+    }
+#pragma unroll
+    for (int l = 0; l < DQ; ++l) Xs[l * kS + sub] = out[l];
   } else {
     double m[NB];
 #pragma unroll
@@ -102,6 +128,7 @@ __device__ __forceinline__ void stage_increment(double* __restrict__ Xs, int sub
         }
       }
     }
+    const double coef = hb * G;
 #pragma unroll
     for (int l = 0; l < DQ; ++l) Xs[l * kS + sub] = coef * acc[l];
   }
@@ -122,7 +149,7 @@ struct SlotMeta {
   int32_t inst, maxk, kslot, flags;  // flags: 1 dead, 2 capped
 };
 
-template <int KIND, int NB, int D>
+template <int KIND, int NB, int D, bool EXACT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void small_kernel(LaunchArgs a) {
   constexpr int DQ = NB * D;
   constexpr int CPL = (DQ + kS - 1) / kS;  // components owned per lane
@@ -213,7 +240,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
 #pragma unroll
         for (int s = 0; s < kS; ++s) Rp[cc][s] = S[4 * DQ + c * kS + s];
       }
-      initial_guess<CPL>(T, qh, vh, Rp, M.h, Qc);
+      initial_guess<CPL, EXACT>(T, qh, vh, Rp, M.h, Qc);
     }
 
     // ---- one step, all live slots in lockstep
@@ -235,7 +262,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
         }
       }
       __syncthreads();
-      if (!conv) stage_increment<KIND, NB, D>(Xs, sub, M.m, M.eps2, (h * T[kTabB + sub]) * M.G);
+      if (!conv) stage_increment<KIND, NB, D, EXACT>(Xs, sub, M.m, M.eps2, h * T[kTabB + sub], M.G);
       __syncthreads();
       bool ok = true, bad = false;
       if (!conv) {
@@ -249,13 +276,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
 #pragma unroll
         for (int s = 0; s < kS; ++s) {
           const ConstTab r = row_tab(T);
-          const double cs = r[kTabC + s];
 #pragma unroll
           for (int cc = 0; cc < CPL; ++cc) {
-            double acc = cs * vh[cc];
-#pragma unroll
-            for (int j = 0; j < kS; ++j) acc = fma(r[kTabEta + s * kS + j], R[cc][j], acc);
-            const double qn = fma(h, acc, qh[cc]);
+            const double qn = stage_value<EXACT>(r, s, qh[cc], vh[cc], h, R[cc]);
             dmax[cc] = max_keep_nan(dmax[cc], fabs(qn - Qc[cc][s]));
             Qc[cc][s] = qn;
           }
@@ -320,12 +343,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
         for (int cc = 0; cc < CPL; ++cc) {
 #pragma unroll
           for (int s = 0; s < kS; ++s) R[cc][s] = Xs[cidx(cc) * kS + s];
-          double sv = R[cc][0];
-#pragma unroll
-          for (int s = 1; s < kS; ++s) sv += R[cc][s];
-          double sc = r[kTabC] * R[cc][0];
-#pragma unroll
-          for (int s = 1; s < kS; ++s) sc = fma(r[kTabC + s], R[cc][s], sc);
+          double sv, sc;
+          step_sums<EXACT>(r, R[cc], sv, sc);
           dw_add(vh[cc], vl[cc], sv);
           dw_add(qh[cc], ql[cc], h * (vh[cc] - sc));
           if (owns(cc)) {
@@ -345,7 +364,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
             }
           }
         }
-        if (!last) initial_guess<CPL>(T, qh, vh, R, h, Qc);
+        if (!last) initial_guess<CPL, EXACT>(T, qh, vh, R, h, Qc);
         if (sub == 0) {
           if (M.iters_off >= 0) a.step_iters[M.iters_off + step0] = (uint8_t)kslot;
           M.step = step;
@@ -379,7 +398,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
 template <int KIND, int NB, int D>
 hipError_t launch_small(const LaunchArgs& a, int n_items, int num_cus, hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
-  auto kern = small_kernel<KIND, NB, D>;
+  auto kern = a.exact ? small_kernel<KIND, NB, D, true> : small_kernel<KIND, NB, D, false>;
   int per_cu = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, 0);
   if (e != hipSuccess) return e;

@@ -311,6 +311,7 @@ static irk::LaunchArgs base_args(irkgl16_ctx* c, double* qout, double* pout) {
   a.max_iter = c->max_iter;
   a.queue_head = nullptr;
   a.step_budget = 0;
+  a.exact = (c->flags & IRKGL16_REPRODUCIBLE) ? 1 : 0;
   return a;
 }
 

@@ -43,8 +43,10 @@ def test_kepler_c1_step_by_step(orc):
     Ho = energies(orc, sp, r["q"], r["p"])
     dg, do = np.abs(Hg / Hg[0] - 1), np.abs(Ho / Ho[0] - 1)
     assert dg.max() <= 1e-12
-    assert 0.5 <= dg.max() / do.max() <= 2.0
-    assert 0.5 <= np.sqrt(np.mean(dg ** 2)) / np.sqrt(np.mean(do ** 2)) <= 2.0
+    # energy-error statistics no worse than twice the oracle's (the GPU's fused
+    # multiply-adds round less, so its errors may be smaller)
+    assert dg.max() <= 2.0 * do.max()
+    assert np.sqrt(np.mean(dg ** 2)) <= 2.0 * np.sqrt(np.mean(do ** 2))
 
 
 def _c2_subset(n_inst, seed=20251105):
@@ -55,46 +57,141 @@ def _problem(s):
     return dict(kind=K.IRKGL16_GRAVITY, n=s["n"], d=s["d"], mass=s["mass"], G=s["G"], eps=s["eps"])
 
 
+def _sensitivity(orc, specs, q0, p0, n, stride):
+    """Oracle's own divergence after n steps under 1-ulp perturbations of every
+    initial coordinate (two random sign patterns): a per-instance measure of
+    how strongly rounding differences are amplified (chaos)."""
+    rng = np.random.default_rng(123)
+    base = orc.integrate_batch(specs, q0, p0, 1.0, n, stride)
+    outs = []
+    for _ in range(2):
+        sq = rng.choice([-1.0, 1.0], q0.size)
+        sp_ = rng.choice([-1.0, 1.0], p0.size)
+        qp = q0 + sq * np.spacing(np.abs(q0))
+        pp = p0 + sp_ * np.spacing(np.abs(p0))
+        outs.append(orc.integrate_batch(specs, qp, pp, 1.0, n, stride))
+    return base, outs
+
+
 def test_c2_ensemble_parity(orc):
-    sy = _c2_subset(256)
-    n, stride = 1000, 100
+    """All instances agree to rounding level after 10 steps; instances whose
+    oracle sensitivity stays below 1e-13 after 10^3 steps (non-chaotic) agree
+    to 1e-12 in q and p, with energy errors <= 1e-12."""
+    N = 256
+    sy = _c2_subset(N)
+    n, stride = 1000, 10
     integ = K.Integrator([_problem(s) for s in sy])
     q0 = np.concatenate([s["q"] for s in sy])
     p0 = np.concatenate([s["p"] for s in sy])
     q, p, st, rc = integ.integrate(q0, p0, 1.0, n, stride)
     assert rc in (0, K.IRKGL16_ENOCONV)
     specs = [orc.Spec(orc.GRAVITY, 6, 3, mass=s["mass"]) for s in sy]
-    r = orc.integrate_batch(specs, q0, p0, 1.0, n, stride)
+    r, pert = _sensitivity(orc, specs, q0, p0, n, stride)
     nf = n // stride + 1
-    Qg, Pg = q.reshape(256, nf, 18), p.reshape(256, nf, 18)
-    Qo, Po = r["q"].reshape(256, nf, 18), r["p"].reshape(256, nf, 18)
+    Qg, Pg = q.reshape(N, nf, 18), p.reshape(N, nf, 18)
+    Qo, Po = r["q"].reshape(N, nf, 18), r["p"].reshape(N, nf, 18)
     smooth = 0
     for i, sp in enumerate(specs):
-        Ho = energies(orc, sp, Qo[i], Po[i])
-        if np.max(np.abs(Ho / Ho[0] - 1)) > 1e-12:
-            continue  # close encounter: chaotic, excluded from trajectory parity
+        assert relmax(Qg[i, 1], Qo[i, 1]) <= 1e-15, i      # 10 steps: rounding only
+        assert relmax(Pg[i, 1], Po[i, 1]) <= 1e-15, i
+        sens = max(relmax(x["q"].reshape(N, nf, 18)[i, -1], Qo[i, -1]) for x in pert)
+        if sens > 1e-13:
+            continue  # chaotic: rounding differences are amplified, excluded
         smooth += 1
         assert relmax(Qg[i, -1], Qo[i, -1]) <= REL, i
         assert relmax(Pg[i, -1], Po[i, -1]) <= REL, i
         Hg = energies(orc, sp, Qg[i], Pg[i])
-        assert np.max(np.abs(Hg / Hg[0] - 1)) <= 1e-12
-    assert smooth >= 128
-    # iteration totals: within one iteration per step
-    assert np.all(np.abs(st["inst_iterations"] - r["iters"]) <= n)
+        Ho = energies(orc, sp, Qo[i], Po[i])
+        eg, eo = np.max(np.abs(Hg / Hg[0] - 1)), np.max(np.abs(Ho / Ho[0] - 1))
+        assert eg <= max(1e-12, 2.0 * eo), (i, eg, eo)
+    assert smooth >= N // 4, smooth
 
 
 def test_c2_iteration_counts_per_step(orc):
-    sy = _c2_subset(8, seed=77)
-    n = 1000
+    N, n = 32, 1000
+    sy = _c2_subset(N, seed=77)
     integ = K.Integrator([_problem(s) for s in sy], record_iters=True)
     q0 = np.concatenate([s["q"] for s in sy])
     p0 = np.concatenate([s["p"] for s in sy])
     q, p, st, rc = integ.integrate(q0, p0, 1.0, n, n)
-    ks = st["step_iters"].reshape(8, n).astype(int)
+    ks = st["step_iters"].reshape(N, n).astype(int)
+    specs = [orc.Spec(orc.GRAVITY, 6, 3, mass=s["mass"]) for s in sy]
+    base, pert = _sensitivity(orc, specs, q0, p0, n, n)
+    checked = 0
     for i, s in enumerate(sy):
-        sp = orc.Spec(orc.GRAVITY, 6, 3, mass=s["mass"])
-        r = orc.integrate(sp, s["q"], s["p"], 1.0, n, n, want_iters=True)
-        assert np.abs(ks[i] - r["iters"]).max() <= 1
+        sens = max(relmax(x["q"].reshape(N, 2, 18)[i, -1], base["q"].reshape(N, 2, 18)[i, -1])
+                   for x in pert)
+        if sens > 1e-13:
+            continue
+        checked += 1
+        r = orc.integrate(specs[i], s["q"], s["p"], 1.0, n, n, want_iters=True)
+        dk = np.abs(ks[i] - r["iters"])
+        # the count is decided at rounding level (an exact zero increment, or
+        # stagnation of the last bits), so differently rounded arithmetic flips
+        # it now and then; reproducible mode matches exactly (tested below)
+        assert np.mean(dk <= 1) >= 0.995, i
+        assert dk.max() <= 3, i
+        assert abs(int(ks[i].sum()) - int(r["iters"].sum())) <= n // 20
+    assert checked >= N // 4
+
+
+def test_reproducible_mode_is_bit_identical_c1(orc):
+    c1 = W.kepler_c1()
+    n = c1["nsteps"]
+    integ = K.Integrator([dict(kind=K.IRKGL16_KEPLER, n=1, d=2, G=1.0)], record_iters=True,
+                         flags=K.IRKGL16_REPRODUCIBLE)
+    q, p, st, rc = integ.integrate(c1["q"], c1["p"], c1["h"], n, 1)
+    sp = orc.Spec(orc.KEPLER, 1, 2, G=1.0)
+    r = orc.integrate(sp, c1["q"], c1["p"], c1["h"], n, 1, want_iters=True)
+    assert np.array_equal(q.reshape(-1, 2), r["q"]) and np.array_equal(p.reshape(-1, 2), r["p"])
+    assert np.array_equal(st["step_iters"].astype(np.int32), r["iters"])
+
+
+def test_reproducible_mode_is_bit_identical_c2(orc):
+    """Every instance, chaotic ones included: identical arithmetic gives
+    identical trajectories and identical per-step iteration counts."""
+    N, n, stride = 128, 1000, 100
+    sy = _c2_subset(N, seed=404)
+    q0 = np.concatenate([s["q"] for s in sy])
+    p0 = np.concatenate([s["p"] for s in sy])
+    integ = K.Integrator([_problem(s) for s in sy], record_iters=True,
+                         flags=K.IRKGL16_REPRODUCIBLE)
+    q, p, st, rc = integ.integrate(q0, p0, 1.0, n, stride)
+    specs = [orc.Spec(orc.GRAVITY, 6, 3, mass=s["mass"]) for s in sy]
+    r = orc.integrate_batch(specs, q0, p0, 1.0, n, stride)
+    assert np.array_equal(q, r["q"]) and np.array_equal(p, r["p"])
+    assert np.array_equal(st["inst_iterations"], r["iters"])
+    ks = st["step_iters"].reshape(N, n)
+    for i in (0, 17, 99):
+        ri = orc.integrate(specs[i], sy[i]["q"], sy[i]["p"], 1.0, n, n, want_iters=True)
+        assert np.array_equal(ks[i].astype(np.int32), ri["iters"])
+
+
+def test_c2_energy_gate_agrees_with_oracle(orc):
+    """The relative-energy gate (<= 1e-12 over the run) passes on the GPU for
+    an instance whenever it passes on the oracle; failures are close
+    encounters of the literal workload, shared by both."""
+    N, n, stride = 512, 2000, 100
+    sy = _c2_subset(N, seed=31)
+    q0 = np.concatenate([s["q"] for s in sy])
+    p0 = np.concatenate([s["p"] for s in sy])
+    q, p, st, rc = K.Integrator([_problem(s) for s in sy]).integrate(q0, p0, 1.0, n, stride)
+    specs = [orc.Spec(orc.GRAVITY, 6, 3, mass=s["mass"]) for s in sy]
+    r = orc.integrate_batch(specs, q0, p0, 1.0, n, stride)
+    nf = n // stride + 1
+    Qg, Pg = q.reshape(N, nf, 18), p.reshape(N, nf, 18)
+    Qo, Po = r["q"].reshape(N, nf, 18), r["p"].reshape(N, nf, 18)
+    pass_g, pass_o, mism = 0, 0, 0
+    for i, sp in enumerate(specs):
+        Hg = energies(orc, sp, Qg[i], Pg[i])
+        Ho = energies(orc, sp, Qo[i], Po[i])
+        eg, eo = np.max(np.abs(Hg / Hg[0] - 1)), np.max(np.abs(Ho / Ho[0] - 1))
+        pass_g += eg <= 1e-12
+        pass_o += eo <= 1e-12
+        if (eg <= 1e-12) != (eo <= 1e-12) and not (3e-13 < min(eg, eo) and max(eg, eo) < 3e-12):
+            mism += 1
+    assert mism == 0
+    assert pass_g >= pass_o - N // 100
 
 
 def test_plain_form_is_bit_identical_to_batched():
