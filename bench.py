@@ -90,8 +90,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--ode-steps", type=int, default=NSTEPS)
     ap.add_argument("--instances", type=int, default=N_INST)
-    ap.add_argument("--cpu-sample", type=int, default=4096)
-    ap.add_argument("--cpu-steps", type=int, default=2000)
+    ap.add_argument("--cpu-sample", type=int, default=16384)
+    ap.add_argument("--cpu-steps", type=int, default=4000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     args = ap.parse_args()
@@ -179,6 +179,22 @@ def main():
         pi.close()
         bi.close()
 
+    repro = None
+    if not args.no_plain:
+        # reproducible (bit-identical to the strict-IEEE reference order) mode, one call
+        ri = K.Integrator(probs, flags=K.IRKGL16_DEVICE_PTRS | K.IRKGL16_REPRODUCIBLE,
+                          stream=stream)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        rc_r = K.irkgl16_integrate(ri.ctx, q0_d, p0_d, np.full(n_inst, H),
+                                   np.full(n_inst, nsteps, np.int64),
+                                   np.full(n_inst, nsteps, np.int64), q_out, p_out)
+        torch.cuda.synchronize()
+        dtr = time.perf_counter() - t
+        repro = dict(value=inst_steps / dtr, unit="instance-steps/s", rc=int(rc_r),
+                     sample="full workload, one call, IRKGL16_REPRODUCIBLE")
+        ri.close()
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(sy, min(args.cpu_sample, n_inst), args.cpu_steps)
@@ -209,6 +225,7 @@ def main():
         "accuracy": {"gate": "relative energy error first->last frame <= 1e-12",
                      "pass_frac": gate, "median_dE": float(np.median(dE))},
         "plain": plain,
+        "reproducible": repro,
         "cpu_baseline": cpu,
         "status": rc,
     }

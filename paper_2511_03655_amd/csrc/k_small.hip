@@ -23,29 +23,6 @@
 
 namespace irk {
 
-// Initial guess for the owned components from their previous-step increments
-// Rp (eq. IRK_init2): V0_i = v + sum_j nu_ij Rp_j, L0_j = h b_j V0_j,
-// Q_i = q + sum_j mu_ij L0_j.  Rows of nu and mu are fetched one at a time.
-template <int CPL, bool EXACT>
-__device__ __forceinline__ void initial_guess(ConstTab T, const double (&qh)[CPL],
-                                              const double (&vh)[CPL], const double (&Rp)[CPL][kS],
-                                              double h, double (&Q)[CPL][kS]) {
-  double L0[CPL][kS];
-#pragma unroll
-  for (int s = 0; s < kS; ++s) {
-    const ConstTab r = row_tab(T);
-    const double hb = h * r[kTabB + s];
-#pragma unroll
-    for (int cc = 0; cc < CPL; ++cc) L0[cc][s] = hb * (vh[cc] + row_dot<EXACT>(r, kTabNu + s * kS, Rp[cc]));
-  }
-#pragma unroll
-  for (int s = 0; s < kS; ++s) {
-    const ConstTab r = row_tab(T);
-#pragma unroll
-    for (int cc = 0; cc < CPL; ++cc) Q[cc][s] = qh[cc] + row_dot<EXACT>(r, kTabMu + s * kS, L0[cc]);
-  }
-}
-
 // Reads the stage positions from column `sub` of the slot tile and overwrites
 // the same column with the increments R_sub = h b_sub g(Q_sub): a lane only
 // touches its own column, so no barrier is needed between the read and the

@@ -1,8 +1,411 @@
-// placeholder: generic workgroup-per-instance kernels (filled in next)
+// Persistent batched IRKGL16 kernel for larger systems: gravitational systems
+// of up to 512 bodies (Plummer clusters, planetary systems with many bodies)
+// and FPU-beta chains of up to 1024 sites.
+//
+// Mapping: one lane owns one body (d = 3) or chain site (d = 1) with all 8
+// stage values of its components in registers, so the 8x8 stage contraction
+// Q_i = q + h (c_i v + sum_j eta_ij R_j) (eq. IRK_FP2), the max-norm increment
+// and stopping rule (eqs. Delta_n, stopping), the compensated update
+// (eq. qnvn2) and the extrapolated initial guess (eq. IRK_init2) are all
+// lane-local.  The force needs the other bodies' (or the neighbours') stage
+// positions: each iteration the lanes publish their 8 x d stage positions to an
+// LDS tile laid out [unit][stage][component], and every lane reads the source
+// units it needs from there (gravity: all bodies of its system, summed in
+// ascending order; chain: the two neighbours).
+//
+// A workgroup of T lanes is split into T / S slots of S lanes (S >= n, one
+// system per slot); slots iterate in lockstep, converged slots are masked, and
+// a slot whose system finishes pulls the next one from the class queue.  Per
+// system arithmetic does not depend on the slot or workgroup that runs it.
 #include "device_common.h"
+
 namespace irk {
-bool wg_class_supported(int, int, int) { return false; }
-hipError_t launch_wg_class(int, int, int, const LaunchArgs&, int, int, hipStream_t) {
+
+struct WgMeta {
+  int64_t nsteps, stride, out_off, iters_off, state_off, step, target, it_sum, nonconv;
+  double h, G, eps2, beta;
+  int32_t inst, n, maxk, kslot, flags, notok, bad, pad;
+};
+
+template <int KIND, int D, bool EXACT>
+__device__ __forceinline__ void unit_increments(const double* __restrict__ Qs,
+                                                const double* __restrict__ Ms, int base, int u,
+                                                int n, const WgMeta& M, double kl, double kr,
+                                                const double (&Q)[D][kS], ConstTab T, double h,
+                                                double (&R)[D][kS]) {
+  if constexpr (KIND == kGravity) {
+    double acc[D][kS];
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+#pragma unroll
+      for (int s = 0; s < kS; ++s) acc[d][s] = 0.0;
+    const double eps2 = M.eps2;
+    for (int b = 0; b < n; ++b) {
+      if (b == u) continue;
+      const double* qb = Qs + (size_t)(base + b) * kS * D;
+      const double mb = Ms[base + b];
+#pragma unroll
+      for (int s = 0; s < kS; ++s) {
+        double dx[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) dx[d] = qb[s * D + d] - Q[d][s];
+        if constexpr (EXACT) {
+          double r2 = 0.0;
+#pragma unroll
+          for (int d = 0; d < D; ++d) r2 = r2 + dx[d] * dx[d];
+          r2 = r2 + eps2;
+          const double w = pair_weight<true>(r2, mb);
+#pragma unroll
+          for (int d = 0; d < D; ++d) acc[d][s] = acc[d][s] + w * dx[d];
+        } else {
+          double r2 = dx[0] * dx[0];
+#pragma unroll
+          for (int d = 1; d < D; ++d) r2 = fma(dx[d], dx[d], r2);
+          const double w = mb * rinv3(r2 + eps2);
+#pragma unroll
+          for (int d = 0; d < D; ++d) acc[d][s] = fma(w, dx[d], acc[d][s]);
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < kS; ++s) {
+      const double hb = h * T[kTabB + s];
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        if constexpr (EXACT)
+          R[d][s] = hb * (M.G * acc[d][s]);
+        else
+          R[d][s] = (hb * M.G) * acc[d][s];
+      }
+    }
+  } else {  // chain, D == 1: F = k_r V'(q_{i+1} - q_i) - k_l V'(q_i - q_{i-1})
+    const double beta = M.beta;
+    const double inv_m = Ms[base + u];
+#pragma unroll
+    for (int s = 0; s < kS; ++s) {
+      const double ql = (u > 0) ? Qs[(size_t)(base + u - 1) * kS + s] : 0.0;
+      const double qr = (u < n - 1) ? Qs[(size_t)(base + u + 1) * kS + s] : 0.0;
+      const double sr = qr - Q[0][s];
+      const double sl = Q[0][s] - ql;
+      double F;
+      if constexpr (EXACT) {
+        F = kr * (sr + beta * (sr * sr * sr)) - kl * (sl + beta * (sl * sl * sl));
+      } else {
+        const double vr = fma(beta * sr * sr, sr, sr);
+        const double vl = fma(beta * sl * sl, sl, sl);
+        F = fma(kr, vr, -(kl * vl));
+      }
+      R[0][s] = (h * T[kTabB + s]) * (F / inv_m);
+    }
+  }
+}
+
+template <int KIND, int D, bool EXACT>
+__global__ __launch_bounds__(1024) void wg_kernel(LaunchArgs a, int S) {
+  extern __shared__ double lds[];
+  const int TT = blockDim.x;
+  const int nslots = TT / S;
+  double* Qs = lds;                                  // [TT][8][D]
+  double* Ms = Qs + (size_t)TT * kS * D;             // [TT] masses of the units
+  WgMeta* meta = reinterpret_cast<WgMeta*>(Ms + TT);  // [nslots]
+  int32_t* slot_inst = reinterpret_cast<int32_t*>(meta + nslots);
+  int32_t* qdone = slot_inst + nslots;
+
+  const int tid = threadIdx.x;
+  const int slot = tid / S;
+  const int u = tid - slot * S;
+  const int base = slot * S;
+  WgMeta& M = meta[slot];
+  const ConstTab T = const_tab(a.tab);
+
+  int inst = -1;
+  double qh[D], ql[D], vh[D], vl[D], mind[D], prv[D];
+  double Q[D][kS], R[D][kS];
+  double mown = 1.0, kl = 1.0, kr = 1.0;
+
+  if (tid == 0) *qdone = 0;
+  if (tid < nslots) {
+    slot_inst[tid] = -1;
+    meta[tid].inst = -1;
+  }
+  __syncthreads();
+
+  for (;;) {
+    if (u == 0 && slot_inst[slot] < 0 && !*qdone) {
+      if (a.queue_head) {
+        const int idx = atomicAdd(a.queue_head, 1);
+        if (idx < a.queue_len)
+          slot_inst[slot] = a.queue[idx];
+        else
+          *qdone = 1;
+      } else if (slot < a.queue_len) {
+        slot_inst[slot] = a.queue[slot];
+      }
+    }
+    __syncthreads();
+    if (!a.queue_head && tid == 0) *qdone = 1;
+    const int cur = slot_inst[slot];
+    if (__syncthreads_or(cur >= 0) == 0) break;
+
+    const bool fresh = cur >= 0 && cur != inst;
+    if (fresh && u == 0) {
+      const InstDesc& dsc = a.desc[cur];
+      const InstStat st = a.stat[cur];
+      M.inst = cur;
+      M.n = dsc.n;
+      M.h = dsc.h;
+      M.G = dsc.G;
+      M.eps2 = dsc.eps * dsc.eps;
+      M.beta = dsc.beta;
+      M.nsteps = dsc.nsteps;
+      M.stride = dsc.stride;
+      M.out_off = dsc.out_off;
+      M.iters_off = dsc.iters_off;
+      M.state_off = dsc.state_off;
+      M.step = st.steps_done;
+      M.it_sum = st.iterations;
+      M.nonconv = st.nonconv;
+      M.maxk = st.max_k;
+      int64_t target = dsc.nsteps;
+      if (a.step_budget > 0 && st.steps_done + a.step_budget < dsc.nsteps)
+        target = st.steps_done + a.step_budget;
+      if (st.status != kOk) target = st.steps_done;
+      M.target = target;
+    }
+    __syncthreads();
+    const int n = (cur >= 0) ? M.n : 0;
+    const bool mine = u < n;  // this lane owns a unit of the slot's system
+    if (fresh) {
+      inst = cur;
+      const InstDesc& dsc = a.desc[cur];
+      if (mine) {
+        mown = (dsc.mass_off >= 0) ? a.params[dsc.mass_off + u] : 1.0;
+        if constexpr (KIND == kChain) {
+          kl = (dsc.coupling_off >= 0) ? a.params[dsc.coupling_off + u] : 1.0;
+          kr = (dsc.coupling_off >= 0) ? a.params[dsc.coupling_off + u + 1] : 1.0;
+        }
+        Ms[base + u] = mown;
+        const int dq = n * D;
+        const double* Sp = a.state + M.state_off;
+        double Rp[D][kS];
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          const int c = u * D + d;
+          qh[d] = Sp[c];
+          ql[d] = Sp[dq + c];
+          vh[d] = Sp[2 * dq + c];
+          vl[d] = Sp[3 * dq + c];
+#pragma unroll
+          for (int s = 0; s < kS; ++s) Rp[d][s] = Sp[4 * dq + c * kS + s];
+        }
+        initial_guess<D, EXACT>(T, qh, vh, Rp, M.h, Q);
+      }
+    }
+
+    // ---- one step, all live slots in lockstep
+    const bool live = (inst >= 0) && (M.step < M.target);
+    const double h = M.h;
+    bool conv = !live;
+#pragma unroll
+    for (int d = 0; d < D; ++d) mind[d] = prv[d] = __builtin_inf();
+    int k = 0;
+    while (__syncthreads_or(!conv)) {
+      ++k;
+      if (!conv) {
+        if (mine) {
+#pragma unroll
+          for (int s = 0; s < kS; ++s)
+#pragma unroll
+            for (int d = 0; d < D; ++d) Qs[(size_t)(base + u) * kS * D + s * D + d] = Q[d][s];
+        }
+        if (u == 0) {
+          M.notok = 0;
+          M.bad = 0;
+        }
+      }
+      __syncthreads();
+      if (!conv && mine) {
+        unit_increments<KIND, D, EXACT>(Qs, Ms, base, u, n, M, kl, kr, Q, T, h, R);
+        bool ok = true, bad = false;
+        double dmax[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) dmax[d] = 0.0;
+#pragma unroll
+        for (int s = 0; s < kS; ++s) {
+          const ConstTab r = row_tab(T);
+#pragma unroll
+          for (int d = 0; d < D; ++d) {
+            const double qn = stage_value<EXACT>(r, s, qh[d], vh[d], h, R[d]);
+            dmax[d] = max_keep_nan(dmax[d], fabs(qn - Q[d][s]));
+            Q[d][s] = qn;
+          }
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          bad |= !finite(dmax[d]);
+          ok &= stop_component(dmax[d], mind[d], prv[d]);
+        }
+        if (!ok) M.notok = 1;
+        if (bad) M.bad = 1;
+      }
+      __syncthreads();
+      if (!conv) {
+        const bool slot_bad = M.bad != 0;
+        const bool slot_ok = M.notok == 0;
+        if (slot_ok || slot_bad || k >= a.max_iter) {
+          conv = true;
+          if (u == 0) {
+            M.kslot = k;
+            M.flags = (slot_bad ? 1 : 0) | ((!slot_ok && !slot_bad) ? 2 : 0);
+          }
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- end of step
+    bool release = (inst >= 0) && !live;
+    if (live) {
+      const int kslot = M.kslot;
+      const int64_t step0 = M.step, stride = M.stride, out_off = M.out_off;
+      const int dq = n * D;
+      if (M.flags & 1) {
+        if (mine) {
+          const int64_t nf = M.nsteps / stride;
+          for (int64_t f = step0 / stride + 1; f <= nf; ++f)
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+              a.qout[out_off + f * dq + u * D + d] = __builtin_nan("");
+              a.pout[out_off + f * dq + u * D + d] = __builtin_nan("");
+            }
+        }
+        if (u == 0) {
+          if (M.iters_off >= 0) a.step_iters[M.iters_off + step0] = (uint8_t)kslot;
+          InstStat st;
+          st.steps_done = step0;
+          st.iterations = M.it_sum;
+          st.nonconv = M.nonconv;
+          st.max_k = M.maxk;
+          st.status = kNonFinite;
+          a.stat[inst] = st;
+        }
+        release = true;
+      } else {
+        const int64_t step = step0 + 1;
+        const bool frame = (step % stride) == 0;
+        const bool last = step >= M.target;
+        if (mine) {
+          double* Sp = a.state + M.state_off;
+          const ConstTab r = row_tab(T);
+#pragma unroll
+          for (int d = 0; d < D; ++d) {
+            const int c = u * D + d;
+            double sv, sc;
+            step_sums<EXACT>(r, R[d], sv, sc);
+            dw_add(vh[d], vl[d], sv);
+            dw_add(qh[d], ql[d], h * (vh[d] - sc));
+            if (frame) {
+              const int64_t f = step / stride;
+              a.qout[out_off + f * dq + c] = qh[d];
+              a.pout[out_off + f * dq + c] = mown * vh[d];
+            }
+            if (last) {
+              Sp[c] = qh[d];
+              Sp[dq + c] = ql[d];
+              Sp[2 * dq + c] = vh[d];
+              Sp[3 * dq + c] = vl[d];
+#pragma unroll
+              for (int s = 0; s < kS; ++s) Sp[4 * dq + c * kS + s] = R[d][s];
+            }
+          }
+          if (!last) initial_guess<D, EXACT>(T, qh, vh, R, h, Q);
+        }
+        if (u == 0) {
+          if (M.iters_off >= 0) a.step_iters[M.iters_off + step0] = (uint8_t)kslot;
+          M.step = step;
+          M.it_sum += kslot;
+          M.nonconv += (M.flags & 2) ? 1 : 0;
+          if (kslot > M.maxk) M.maxk = kslot;
+          if (last) {
+            InstStat st;
+            st.steps_done = step;
+            st.iterations = M.it_sum;
+            st.nonconv = M.nonconv;
+            st.max_k = M.maxk;
+            st.status = kOk;
+            a.stat[inst] = st;
+          }
+        }
+        release = last;
+      }
+    }
+    __syncthreads();
+    if (release) {
+      if (u == 0) slot_inst[slot] = -1;
+      inst = -1;
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+
+// Largest system (bodies or sites) the workgroup kernel accepts per kind.
+constexpr int kWgMaxGravity = 512;
+constexpr int kWgMaxChain = 1024;
+
+// Slot width for a system of n units: a power of two up to 64, else a multiple
+// of 64.
+int wg_slot_size(int n) {
+  if (n <= 64) {
+    int s = 8;
+    while (s < n) s <<= 1;
+    return s;
+  }
+  return (n + 63) / 64 * 64;
+}
+
+int wg_block_size(int S) { return S <= 256 ? 256 : (S <= 512 ? 512 : 1024); }
+
+size_t wg_lds_bytes(int TT, int S, int D) {
+  const int nslots = TT / S;
+  return sizeof(double) * ((size_t)TT * kS * D + TT) + sizeof(WgMeta) * nslots +
+         sizeof(int32_t) * (nslots + 1);
+}
+
+bool wg_class_supported(int kind, int n, int d) {
+  if (kind == kGravity) return d == 3 && n >= 1 && n <= kWgMaxGravity;
+  if (kind == kChain) return d == 1 && n >= 1 && n <= kWgMaxChain;
+  return false;
+}
+
+template <int KIND, int D>
+hipError_t launch_wg(const LaunchArgs& a, int S, int n_items, int num_cus, hipStream_t st) {
+  const int TT = wg_block_size(S);
+  const size_t lds = wg_lds_bytes(TT, S, D);
+  auto kern = a.exact ? wg_kernel<KIND, D, true> : wg_kernel<KIND, D, false>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  int per_cu = 0;
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, TT, lds);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) return hipErrorInvalidConfiguration;
+  const int nslots = TT / S;
+  const int want = (n_items + nslots - 1) / nslots;
+  const int cap = per_cu * num_cus;
+  const int grid = want < cap ? want : cap;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(TT), lds, st, a, S);
+  return hipGetLastError();
+}
+
+// Class key: (kind, d, S).  n_items instances, all with slot size S.
+hipError_t launch_wg_class(int kind, int d, int S, const LaunchArgs& a, int n_items, int num_cus,
+                           hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  if (kind == kGravity && d == 3) return launch_wg<kGravity, 3>(a, S, n_items, num_cus, st);
+  if (kind == kChain && d == 1) return launch_wg<kChain, 1>(a, S, n_items, num_cus, st);
   return hipErrorInvalidValue;
 }
+
 }  // namespace irk
