@@ -150,8 +150,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
   auto cidx = [&](int cc) { return (sub + kS * cc < DQ) ? sub + kS * cc : DQ - 1; };
 
   int inst = -1;
-  double qh[CPL], ql[CPL], vh[CPL], vl[CPL], mind[CPL], prv[CPL];
-  double Qc[CPL][kS];
+  double qh[CPL] = {}, ql[CPL] = {}, vh[CPL] = {}, vl[CPL] = {}, mind[CPL] = {}, prv[CPL] = {};
+  double Qc[CPL][kS] = {};
 
   if (lane == 0) qdone = 0;
   if (lane < 8) {

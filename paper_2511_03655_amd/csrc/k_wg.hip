@@ -31,24 +31,26 @@ template <int KIND, int D, bool EXACT>
 __device__ __forceinline__ void unit_increments(const double* __restrict__ Qs,
                                                 const double* __restrict__ Ms, int base, int u,
                                                 int n, const WgMeta& M, double kl, double kr,
-                                                const double (&Q)[D][kS], ConstTab T, double h,
-                                                double (&R)[D][kS]) {
+                                                ConstTab T, double h, double (&R)[D][kS]) {
+  // The lane's own stage positions are read back from the tile (it published
+  // them there), so they need not stay in registers across the force loop.
+  const double* qa = Qs + (size_t)(base + u) * kS * D;
   if constexpr (KIND == kGravity) {
-    double acc[D][kS];
-#pragma unroll
-    for (int d = 0; d < D; ++d)
-#pragma unroll
-      for (int s = 0; s < kS; ++s) acc[d][s] = 0.0;
+    // One stage at a time, sources b ascending: only the stage's own position
+    // and accumulator stay live across the source loop.
     const double eps2 = M.eps2;
-    for (int b = 0; b < n; ++b) {
-      if (b == u) continue;
-      const double* qb = Qs + (size_t)(base + b) * kS * D;
-      const double mb = Ms[base + b];
 #pragma unroll
-      for (int s = 0; s < kS; ++s) {
+    for (int s = 0; s < kS; ++s) {
+      double acc[D];
+#pragma unroll
+      for (int d = 0; d < D; ++d) acc[d] = 0.0;
+      for (int b = 0; b < n; ++b) {
+        if (b == u) continue;
+        const double* qb = Qs + (size_t)(base + b) * kS * D + s * D;
+        const double mb = Ms[base + b];
         double dx[D];
 #pragma unroll
-        for (int d = 0; d < D; ++d) dx[d] = qb[s * D + d] - Q[d][s];
+        for (int d = 0; d < D; ++d) dx[d] = qb[d] - qa[s * D + d];
         if constexpr (EXACT) {
           double r2 = 0.0;
 #pragma unroll
@@ -56,37 +58,34 @@ __device__ __forceinline__ void unit_increments(const double* __restrict__ Qs,
           r2 = r2 + eps2;
           const double w = pair_weight<true>(r2, mb);
 #pragma unroll
-          for (int d = 0; d < D; ++d) acc[d][s] = acc[d][s] + w * dx[d];
+          for (int d = 0; d < D; ++d) acc[d] = acc[d] + w * dx[d];
         } else {
           double r2 = dx[0] * dx[0];
 #pragma unroll
           for (int d = 1; d < D; ++d) r2 = fma(dx[d], dx[d], r2);
           const double w = mb * rinv3(r2 + eps2);
 #pragma unroll
-          for (int d = 0; d < D; ++d) acc[d][s] = fma(w, dx[d], acc[d][s]);
+          for (int d = 0; d < D; ++d) acc[d] = fma(w, dx[d], acc[d]);
         }
       }
-    }
-#pragma unroll
-    for (int s = 0; s < kS; ++s) {
       const double hb = h * T[kTabB + s];
 #pragma unroll
       for (int d = 0; d < D; ++d) {
         if constexpr (EXACT)
-          R[d][s] = hb * (M.G * acc[d][s]);
+          R[d][s] = hb * (M.G * acc[d]);
         else
-          R[d][s] = (hb * M.G) * acc[d][s];
+          R[d][s] = (hb * M.G) * acc[d];
       }
     }
   } else {  // chain, D == 1: F = k_r V'(q_{i+1} - q_i) - k_l V'(q_i - q_{i-1})
     const double beta = M.beta;
-    const double inv_m = Ms[base + u];
+    const double m_site = Ms[base + u];
 #pragma unroll
     for (int s = 0; s < kS; ++s) {
       const double ql = (u > 0) ? Qs[(size_t)(base + u - 1) * kS + s] : 0.0;
       const double qr = (u < n - 1) ? Qs[(size_t)(base + u + 1) * kS + s] : 0.0;
-      const double sr = qr - Q[0][s];
-      const double sl = Q[0][s] - ql;
+      const double sr = qr - qa[s];
+      const double sl = qa[s] - ql;
       double F;
       if constexpr (EXACT) {
         F = kr * (sr + beta * (sr * sr * sr)) - kl * (sl + beta * (sl * sl * sl));
@@ -95,13 +94,13 @@ __device__ __forceinline__ void unit_increments(const double* __restrict__ Qs,
         const double vl = fma(beta * sl * sl, sl, sl);
         F = fma(kr, vr, -(kl * vl));
       }
-      R[0][s] = (h * T[kTabB + s]) * (F / inv_m);
+      R[0][s] = (h * T[kTabB + s]) * (F / m_site);
     }
   }
 }
 
-template <int KIND, int D, bool EXACT>
-__global__ __launch_bounds__(1024) void wg_kernel(LaunchArgs a, int S) {
+template <int KIND, int D, bool EXACT, int MAXT>
+__global__ __launch_bounds__(MAXT) void wg_kernel(LaunchArgs a, int S) {
   extern __shared__ double lds[];
   const int TT = blockDim.x;
   const int nslots = TT / S;
@@ -119,8 +118,8 @@ __global__ __launch_bounds__(1024) void wg_kernel(LaunchArgs a, int S) {
   const ConstTab T = const_tab(a.tab);
 
   int inst = -1;
-  double qh[D], ql[D], vh[D], vl[D], mind[D], prv[D];
-  double Q[D][kS], R[D][kS];
+  double qh[D] = {}, ql[D] = {}, vh[D] = {}, vl[D] = {}, mind[D] = {}, prv[D] = {};
+  double Q[D][kS] = {}, R[D][kS] = {};
   double mown = 1.0, kl = 1.0, kr = 1.0;
 
   if (tid == 0) *qdone = 0;
@@ -202,30 +201,33 @@ __global__ __launch_bounds__(1024) void wg_kernel(LaunchArgs a, int S) {
       }
     }
 
-    // ---- one step, all live slots in lockstep
+    // ---- one step, all live slots in lockstep.  The stage positions are
+    // published to the tile before the first iteration and right after each
+    // update (behind the barrier that ends the force reads), so Q is only live
+    // between an update and its publication.
     const bool live = (inst >= 0) && (M.step < M.target);
     const double h = M.h;
     bool conv = !live;
 #pragma unroll
     for (int d = 0; d < D; ++d) mind[d] = prv[d] = __builtin_inf();
+    if (!conv && mine) {
+#pragma unroll
+      for (int s = 0; s < kS; ++s)
+#pragma unroll
+        for (int d = 0; d < D; ++d) Qs[(size_t)(base + u) * kS * D + s * D + d] = Q[d][s];
+    }
     int k = 0;
     while (__syncthreads_or(!conv)) {
       ++k;
-      if (!conv) {
-        if (mine) {
-#pragma unroll
-          for (int s = 0; s < kS; ++s)
-#pragma unroll
-            for (int d = 0; d < D; ++d) Qs[(size_t)(base + u) * kS * D + s * D + d] = Q[d][s];
-        }
-        if (u == 0) {
-          M.notok = 0;
-          M.bad = 0;
-        }
+      if (!conv && u == 0) {
+        M.notok = 0;
+        M.bad = 0;
       }
       __syncthreads();
+      double Qn[D][kS] = {};
       if (!conv && mine) {
-        unit_increments<KIND, D, EXACT>(Qs, Ms, base, u, n, M, kl, kr, Q, T, h, R);
+        unit_increments<KIND, D, EXACT>(Qs, Ms, base, u, n, M, kl, kr, T, h, R);
+        const double* qa = Qs + (size_t)(base + u) * kS * D;
         bool ok = true, bad = false;
         double dmax[D];
 #pragma unroll
@@ -235,9 +237,8 @@ __global__ __launch_bounds__(1024) void wg_kernel(LaunchArgs a, int S) {
           const ConstTab r = row_tab(T);
 #pragma unroll
           for (int d = 0; d < D; ++d) {
-            const double qn = stage_value<EXACT>(r, s, qh[d], vh[d], h, R[d]);
-            dmax[d] = max_keep_nan(dmax[d], fabs(qn - Q[d][s]));
-            Q[d][s] = qn;
+            Qn[d][s] = stage_value<EXACT>(r, s, qh[d], vh[d], h, R[d]);
+            dmax[d] = max_keep_nan(dmax[d], fabs(Qn[d][s] - qa[s * D + d]));
           }
         }
 #pragma unroll
@@ -258,6 +259,11 @@ __global__ __launch_bounds__(1024) void wg_kernel(LaunchArgs a, int S) {
             M.kslot = k;
             M.flags = (slot_bad ? 1 : 0) | ((!slot_ok && !slot_bad) ? 2 : 0);
           }
+        } else if (mine) {
+#pragma unroll
+          for (int s = 0; s < kS; ++s)
+#pragma unroll
+            for (int d = 0; d < D; ++d) Qs[(size_t)(base + u) * kS * D + s * D + d] = Qn[d][s];
         }
       }
     }
@@ -383,7 +389,9 @@ template <int KIND, int D>
 hipError_t launch_wg(const LaunchArgs& a, int S, int n_items, int num_cus, hipStream_t st) {
   const int TT = wg_block_size(S);
   const size_t lds = wg_lds_bytes(TT, S, D);
-  auto kern = a.exact ? wg_kernel<KIND, D, true> : wg_kernel<KIND, D, false>;
+  constexpr int MAXT = (KIND == kGravity) ? 512 : 1024;
+  if (TT > MAXT) return hipErrorInvalidConfiguration;
+  auto kern = a.exact ? wg_kernel<KIND, D, true, MAXT> : wg_kernel<KIND, D, false, MAXT>;
   hipError_t e = hipFuncSetAttribute((const void*)kern,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;

@@ -29,15 +29,17 @@ hipError_t launch_prepare(const InstDesc* desc, InstStat* stat, double* state,
 hipError_t launch_small_class(int kind, int nb, int d, const LaunchArgs& a, int n_items,
                               int num_cus, hipStream_t st);
 bool small_class_supported(int kind, int nb, int d);
-hipError_t launch_wg_class(int kind, int d, int n, const LaunchArgs& a, int n_items, int num_cus,
+hipError_t launch_wg_class(int kind, int d, int S, const LaunchArgs& a, int n_items, int num_cus,
                            hipStream_t st);
 bool wg_class_supported(int kind, int n, int d);
+int wg_slot_size(int n);
 }  // namespace irk
 
 namespace {
 
 struct KernelClass {
   int kind, nb, d;
+  int S = 0;  // slot width of the workgroup-tile kernel
   bool small;
   std::vector<int32_t> ids;
   int64_t queue_off = 0;
@@ -217,7 +219,8 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
     // kernel class
     bool small = irk::small_class_supported(p.kind, p.n, p.d);
     if (!small && !irk::wg_class_supported(p.kind, p.n, p.d)) return fail(IRKGL16_EINVAL);
-    auto key = small ? std::make_tuple(1, p.kind, p.n, p.d) : std::make_tuple(0, p.kind, 0, p.d);
+    const int slot_w = small ? 0 : irk::wg_slot_size(p.n);
+    auto key = small ? std::make_tuple(1, p.kind, p.n, p.d) : std::make_tuple(0, p.kind, slot_w, p.d);
     auto it = cls_index.find(key);
     int ci;
     if (it == cls_index.end()) {
@@ -227,6 +230,7 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
       kc.kind = p.kind;
       kc.nb = small ? p.n : 0;
       kc.d = p.d;
+      kc.S = slot_w;
       kc.small = small;
       c->classes.push_back(kc);
     } else {
@@ -318,7 +322,7 @@ static irk::LaunchArgs base_args(irkgl16_ctx* c, double* qout, double* pout) {
 static hipError_t launch_class(irkgl16_ctx* c, const KernelClass& kc, const irk::LaunchArgs& a,
                                int n_items) {
   if (kc.small) return irk::launch_small_class(kc.kind, kc.nb, kc.d, a, n_items, c->num_cus, c->stream);
-  return irk::launch_wg_class(kc.kind, kc.d, 0, a, n_items, c->num_cus, c->stream);
+  return irk::launch_wg_class(kc.kind, kc.d, kc.S, a, n_items, c->num_cus, c->stream);
 }
 
 static int integrate_impl(irkgl16_ctx* c, const double* q0, const double* p0, const double* h,
