@@ -73,3 +73,24 @@ def test_null_arguments_rejected():
     assert L.irkgl16_integrate(None, None, None, None, None, None, None, None, None) == K.IRKGL16_EINVAL
     assert L.irkgl16_last_stats(None, None) == K.IRKGL16_EINVAL
     L.irkgl16_destroy(None)  # NULL-safe
+
+
+def test_product_table_matches_oracle_table(orc):
+    """The library's coefficient header (its own generator) equals the oracle's
+    table bit-for-bit."""
+    src = open(os.path.join(ROOT, "paper_2511_03655_amd", "csrc", "irkgl16_coeffs.h")).read()
+
+    def grab(name):
+        m = re.search(name + r"\[8\](?:\[8\])? = \{(.*?)\};", src, re.S)
+        return np.array([float.fromhex(x) for x in re.findall(r"-?0x[0-9a-fp.+-]+", m.group(1))])
+    t = orc.tableau()
+    for key, name in (("c", "kC"), ("b", "kB"), ("eta", "kEta"), ("mu", "kMu"), ("nu", "kNu")):
+        assert np.array_equal(grab(name), t[key].ravel()), key
+
+
+def test_graft_entry_build_compiles_everything(tmp_path):
+    import importlib
+    ge = importlib.import_module("__graft_entry__")
+    ge.build()
+    assert os.path.exists(os.path.join(ROOT, "paper_2511_03655_amd", "libirkgl16.so"))
+    assert os.path.exists(os.path.join(ROOT, "oracle", "liborc.so"))
