@@ -33,6 +33,11 @@ hipError_t launch_wg_class(int kind, int d, int S, const LaunchArgs& a, int n_it
                            hipStream_t st);
 bool wg_class_supported(int kind, int n, int d);
 int wg_slot_size(int n);
+bool large_class_supported(int kind, int n, int d);
+size_t large_scratch_bytes(int n, int nchunks);
+int large_chunks(int n, bool exact, int num_cus);
+hipError_t launch_large(const LaunchArgs& a, int inst, int n, void* scratch, int nchunks,
+                        int num_cus, hipStream_t st);
 }  // namespace irk
 
 namespace {
@@ -41,6 +46,7 @@ struct KernelClass {
   int kind, nb, d;
   int S = 0;  // slot width of the workgroup-tile kernel
   bool small;
+  bool large = false;  // one whole-GPU cooperative launch per instance
   std::vector<int32_t> ids;
   int64_t queue_off = 0;
 };
@@ -112,7 +118,8 @@ struct irkgl16_ctx {
   int64_t total_dq = 0;
 
   DevBuf d_tab, d_desc, d_stat, d_state, d_params, d_queue, d_heads, d_plainq;
-  DevBuf d_q0, d_p0, d_qout, d_pout, d_iters;
+  DevBuf d_q0, d_p0, d_qout, d_pout, d_iters, d_large;
+  int large_nmax = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
   // last call
@@ -217,10 +224,14 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
     d.state_off = state_off;
     state_off += (int64_t)(4 + irk::kS) * dqi;
     // kernel class
-    bool small = irk::small_class_supported(p.kind, p.n, p.d);
-    if (!small && !irk::wg_class_supported(p.kind, p.n, p.d)) return fail(IRKGL16_EINVAL);
-    const int slot_w = small ? 0 : irk::wg_slot_size(p.n);
-    auto key = small ? std::make_tuple(1, p.kind, p.n, p.d) : std::make_tuple(0, p.kind, slot_w, p.d);
+    const bool small = irk::small_class_supported(p.kind, p.n, p.d);
+    const bool wg = !small && irk::wg_class_supported(p.kind, p.n, p.d);
+    const bool large = !small && !wg && irk::large_class_supported(p.kind, p.n, p.d);
+    if (!small && !wg && !large) return fail(IRKGL16_EINVAL);
+    if (large) c->large_nmax = std::max(c->large_nmax, (int)p.n);
+    const int slot_w = wg ? irk::wg_slot_size(p.n) : 0;
+    auto key = small ? std::make_tuple(1, p.kind, p.n, p.d)
+                     : (wg ? std::make_tuple(0, p.kind, slot_w, p.d) : std::make_tuple(2, p.kind, 0, p.d));
     auto it = cls_index.find(key);
     int ci;
     if (it == cls_index.end()) {
@@ -232,6 +243,7 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
       kc.d = p.d;
       kc.S = slot_w;
       kc.small = small;
+      kc.large = large;
       c->classes.push_back(kc);
     } else {
       ci = it->second;
@@ -261,6 +273,9 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
     return fail(IRKGL16_EDEVICE);
 
   int rc;
+  if (c->large_nmax > 0 &&
+      (rc = alloc_try(c->d_large, irk::large_scratch_bytes(c->large_nmax, 16))))
+    return fail(rc);
   if ((rc = alloc_try(c->d_desc, sizeof(irk::InstDesc) * (size_t)std::max(n_inst, 1))) ||
       (rc = alloc_try(c->d_stat, sizeof(irk::InstStat) * (size_t)std::max(n_inst, 1))) ||
       (rc = alloc_try(c->d_state, sizeof(double) * (size_t)std::max<int64_t>(state_off, 1))) ||
@@ -322,6 +337,21 @@ static irk::LaunchArgs base_args(irkgl16_ctx* c, double* qout, double* pout) {
 static hipError_t launch_class(irkgl16_ctx* c, const KernelClass& kc, const irk::LaunchArgs& a,
                                int n_items) {
   if (kc.small) return irk::launch_small_class(kc.kind, kc.nb, kc.d, a, n_items, c->num_cus, c->stream);
+  if (kc.large) {
+    // One cooperative whole-GPU launch per instance, in queue order.
+    std::vector<int32_t> ids;
+    if (a.queue_head)
+      ids.assign(kc.ids.begin(), kc.ids.end());
+    else  // plain form: the single instance is identified by its queue position
+      ids.push_back((int32_t)(a.queue - c->d_plainq.as<int32_t>()));
+    for (int32_t id : ids) {
+      const int n = c->desc[id].n;
+      const int ch = irk::large_chunks(n, a.exact != 0, c->num_cus);
+      hipError_t e = irk::launch_large(a, id, n, c->d_large.p, ch, c->num_cus, c->stream);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   return irk::launch_wg_class(kc.kind, kc.d, kc.S, a, n_items, c->num_cus, c->stream);
 }
 

@@ -1,0 +1,67 @@
+"""GPU parity of the whole-GPU path for one large gravitational system
+(N > 512 bodies; the N = 2048 Plummer cluster of the single-large-system
+workload) against the CPU oracle."""
+import numpy as np
+import pytest
+
+from paper_2511_03655_amd import irkgl16 as K
+from paper_2511_03655_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def relmax(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def run(inst, nsteps, stride, flags=0, record=True):
+    prob = dict(kind=K.IRKGL16_GRAVITY, n=inst["n"], d=3, mass=inst["mass"], G=inst["G"],
+                eps=inst["eps"])
+    return K.Integrator([prob], record_iters=record, flags=flags).integrate(
+        inst["q"], inst["p"], inst["h"], nsteps, stride)
+
+
+def oracle_run(orc, inst, nsteps, stride, iters=True):
+    sp = orc.Spec(orc.GRAVITY, inst["n"], 3, mass=inst["mass"], G=inst["G"], eps=inst["eps"])
+    return orc.integrate(sp, inst["q"], inst["p"], inst["h"], nsteps, stride, want_iters=iters)
+
+
+@pytest.mark.parametrize("n,nsteps", [(600, 6), (2048, 3)])
+def test_large_reproducible_bit_identical(orc, n, nsteps):
+    inst = W.plummer(n, seed=11)
+    q, p, st, rc = run(inst, nsteps, 1, flags=K.IRKGL16_REPRODUCIBLE)
+    r = oracle_run(orc, inst, nsteps, 1)
+    assert rc == 0
+    assert np.array_equal(q, r["q"].ravel()) and np.array_equal(p, r["p"].ravel())
+    assert np.array_equal(st["step_iters"].astype(np.int32), r["iters"])
+
+
+def test_large_fast_matches_oracle(orc):
+    inst = W.plummer(2048, seed=3)
+    n = 4
+    q, p, st, rc = run(inst, n, n)
+    r = oracle_run(orc, inst, n, n)
+    assert rc == 0
+    q, p = q.reshape(2, -1), p.reshape(2, -1)
+    assert relmax(q[1], r["q"][1]) <= 1e-14
+    assert relmax(p[1], r["p"][1]) <= 1e-12
+    assert np.abs(st["step_iters"].astype(int) - r["iters"]).max() <= 1
+
+
+def test_large_plain_equals_batched():
+    inst = W.plummer(700, seed=5)
+    a = run(inst, 3, 1)
+    b = run(inst, 3, 1, flags=K.IRKGL16_PLAIN)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_large_nonfinite_stops_cleanly():
+    inst = W.plummer(600, seed=8)
+    inst = dict(inst)
+    inst["eps"] = 0.0
+    q = inst["q"].copy()
+    q[3:6] = q[0:3]  # bodies 0 and 1 coincide: r = 0 without softening
+    inst["q"] = q
+    qo, po, st, rc = run(inst, 4, 1)
+    assert rc == K.IRKGL16_ENONFINITE
+    assert np.all(np.isnan(qo.reshape(5, -1)[1:]))

@@ -72,6 +72,8 @@ def test_fast_within_tolerance(orc, name, inst, nsteps):
     assert relmax(q[1], r["q"][1]) <= max(1e-12, 30 * sens_q), (name, sens_q)
     assert relmax(p[1], r["p"][1]) <= max(1e-12, 30 * sens_p), (name, sens_p)
     dk = np.abs(st["step_iters"].astype(int) - r["iters"])
+    if max(sens_q, sens_p) > 1e-13:
+        dk = dk[:20]  # chaotic: compare counts only before the trajectories separate
     assert np.mean(dk <= 1) >= 0.99 and dk.max() <= 3
 
 
