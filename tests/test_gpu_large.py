@@ -59,9 +59,10 @@ def test_large_nonfinite_stops_cleanly():
     inst = W.plummer(600, seed=8)
     inst = dict(inst)
     inst["eps"] = 0.0
-    q = inst["q"].copy()
-    q[3:6] = q[0:3]  # bodies 0 and 1 coincide: r = 0 without softening
-    inst["q"] = q
+    q, p = inst["q"].copy(), inst["p"].copy()
+    q[3:6] = q[0:3]  # bodies 0 and 1 coincide and move together (equal masses):
+    p[3:6] = p[0:3]  # every stage has r = 0 between them, without softening
+    inst["q"], inst["p"] = q, p
     qo, po, st, rc = run(inst, 4, 1)
     assert rc == K.IRKGL16_ENONFINITE
     assert np.all(np.isnan(qo.reshape(5, -1)[1:]))
