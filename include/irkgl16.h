@@ -134,6 +134,62 @@ void irkgl16_destroy(irkgl16_ctx *ctx);
 /* Static description of a status code. */
 const char *irkgl16_strerror(int status);
 
+/* ---- serving ------------------------------------------------------------
+ * A server integrates requests that arrive over time with continuous batching:
+ * a serving thread admits pending requests (first come, first served) whenever
+ * their device memory fits under cap_bytes, advances every resident request by
+ * up to slice_steps steps in one batched launch per kernel class, streams the
+ * finished output frames of the slice to host memory, retires finished requests
+ * and admits new ones before the next slice.  A request's resumable state
+ * (two-double q and v, previous-step increments, counters) stays on the device
+ * between slices, so its result is bit-identical to integrating it alone with
+ * irkgl16_integrate under the same flags. */
+typedef struct irkgl16_server irkgl16_server;
+
+typedef struct {
+  int64_t cap_bytes;   /* device memory for resident requests (> 0)            */
+  int64_t slice_steps; /* steps per request per slice (<= 0 means 1000)        */
+  int32_t max_iter;    /* as in irkgl16_options                                */
+  int32_t max_resident;/* resident requests at most (<= 0 means 65536)         */
+  uint32_t flags;      /* IRKGL16_REPRODUCIBLE or 0                            */
+} irkgl16_server_options;
+
+typedef struct {
+  int32_t status;      /* per-request status code                              */
+  int64_t steps;       /* steps done                                           */
+  int64_t iterations;  /* sum of k                                             */
+  double submit_s;     /* seconds since server creation: submitted, admitted,  */
+  double admit_s;      /* finished                                             */
+  double done_s;
+} irkgl16_request_info;
+
+/* Start a server (creates the serving thread).  hip_stream as in
+ * irkgl16_create.  Returns IRKGL16_EDEVICE without a usable GPU and
+ * IRKGL16_ENOMEM if cap_bytes cannot be allocated. */
+int irkgl16_server_create(irkgl16_server **out, const irkgl16_server_options *opt,
+                          void *hip_stream);
+
+/* Submit one request (problem as in irkgl16_create; q0, p0: Dq host doubles;
+ * h, nsteps, out_stride as in irkgl16_integrate).  Everything is copied; the
+ * call returns at once with a ticket.  EINVAL for invalid arguments or a request
+ * larger than the whole cap. */
+int irkgl16_submit(irkgl16_server *s, const irkgl16_problem *prob, const double *q0,
+                   const double *p0, double h, int64_t nsteps, int64_t out_stride,
+                   int64_t *ticket);
+
+/* *done = 1 if the request has finished (0 otherwise).  EINVAL: unknown ticket. */
+int irkgl16_poll(irkgl16_server *s, int64_t ticket, int32_t *done);
+
+/* Block until the request finishes, copy its frames (layout as irkgl16_integrate
+ * for one instance) into q_out/p_out (host, nullable), fill info (nullable), and
+ * release the ticket.  Returns the request's status. */
+int irkgl16_wait(irkgl16_server *s, int64_t ticket, double *q_out, double *p_out,
+                 irkgl16_request_info *info);
+
+/* Stop the serving thread after the resident and pending requests finish, and
+ * release everything.  NULL-safe. */
+void irkgl16_server_destroy(irkgl16_server *s);
+
 #ifdef __cplusplus
 }
 #endif

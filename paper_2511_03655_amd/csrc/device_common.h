@@ -33,8 +33,8 @@ struct InstDesc {
   int64_t nsteps;
   int64_t stride;
   double h, G, eps, beta;
-  int32_t mass_off;      // n masses (GRAVITY, CHAIN) or -1 (all ones)
-  int32_t coupling_off;  // n+1 stiffnesses (CHAIN) or -1 (all ones)
+  int64_t mass_off;      // n masses (GRAVITY, CHAIN) or -1 (all ones)
+  int64_t coupling_off;  // n+1 stiffnesses (CHAIN) or -1 (all ones)
   int32_t kind, n, d, pad;
 };
 

@@ -239,7 +239,7 @@ __global__ __launch_bounds__(kLargeBlock) void large_kernel(LargeArgs L) {
     // ---- end of step (component lanes spread over the whole grid)
     if (dead) {
       if (gtid < dq) {
-        const int64_t nf = dsc.nsteps / dsc.stride;
+        const int64_t nf = target / dsc.stride;  // frames of this launch only
         for (int64_t f = step / dsc.stride + 1; f <= nf; ++f) {
           a.qout[dsc.out_off + f * dq + gtid] = __builtin_nan("");
           a.pout[dsc.out_off + f * dq + gtid] = __builtin_nan("");

@@ -1,4 +1,5 @@
-// Per-call setup kernel: converts the caller's initial (q0, p0) into the
+// Per-call setup kernel (one block per instance; `ids`, if given, lists the
+// instances to set up): converts the caller's initial (q0, p0) into the
 // resumable device state (q and v = fl(p / m) as two-double values with zero
 // low parts, previous-step increments R_prev = 0 so that the first initial
 // guess uses the current velocity only), writes output frame 0 (q, m v), clears
@@ -17,9 +18,10 @@ __global__ __launch_bounds__(64) void prepare_kernel(const InstDesc* __restrict_
                                                      double* __restrict__ qout,
                                                      double* __restrict__ pout,
                                                      uint8_t* __restrict__ step_iters,
-                                                     int32_t* __restrict__ heads, int n_heads) {
-  const int i = blockIdx.x;
-  if (i == 0) {
+                                                     int32_t* __restrict__ heads, int n_heads,
+                                                     const int32_t* __restrict__ ids) {
+  const int i = ids ? ids[blockIdx.x] : (int)blockIdx.x;
+  if (blockIdx.x == 0) {
     for (int t = threadIdx.x; t < n_heads; t += blockDim.x) heads[t] = 0;
   }
   const InstDesc d = desc[i];
@@ -54,10 +56,10 @@ __global__ __launch_bounds__(64) void prepare_kernel(const InstDesc* __restrict_
 hipError_t launch_prepare(const InstDesc* desc, InstStat* stat, double* state,
                           const double* params, const double* q0, const double* p0, double* qout,
                           double* pout, uint8_t* step_iters, int32_t* heads, int n_heads,
-                          int n_inst, hipStream_t st) {
+                          int n_inst, hipStream_t st, const int32_t* ids) {
   if (n_inst <= 0) return hipSuccess;
   hipLaunchKernelGGL(prepare_kernel, dim3(n_inst), dim3(64), 0, st, desc, stat, state, params, q0,
-                     p0, qout, pout, step_iters, heads, n_heads);
+                     p0, qout, pout, step_iters, heads, n_heads, ids);
   return hipGetLastError();
 }
 

@@ -288,7 +288,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
       const int kslot = M.kslot;
       const int64_t step0 = M.step, stride = M.stride, out_off = M.out_off;
       if (M.flags & 1) {  // non-finite: stop this instance, remaining frames NaN
-        const int64_t nf = M.nsteps / stride;
+        const int64_t nf = M.target / stride;  // frames of this launch only
         for (int64_t f = step0 / stride + 1; f <= nf; ++f) {
 #pragma unroll
           for (int cc = 0; cc < CPL; ++cc) {

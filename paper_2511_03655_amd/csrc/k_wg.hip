@@ -277,7 +277,7 @@ __global__ __launch_bounds__(MAXT) void wg_kernel(LaunchArgs a, int S) {
       const int dq = n * D;
       if (M.flags & 1) {
         if (mine) {
-          const int64_t nf = M.nsteps / stride;
+          const int64_t nf = M.target / stride;  // frames of this launch only
           for (int64_t f = step0 / stride + 1; f <= nf; ++f)
 #pragma unroll
             for (int d = 0; d < D; ++d) {

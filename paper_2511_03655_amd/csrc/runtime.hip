@@ -20,25 +20,8 @@
 
 #include "../../include/irkgl16.h"
 #include "device_common.h"
+#include "launch.h"
 
-namespace irk {
-hipError_t launch_prepare(const InstDesc* desc, InstStat* stat, double* state,
-                          const double* params, const double* q0, const double* p0, double* qout,
-                          double* pout, uint8_t* step_iters, int32_t* heads, int n_heads,
-                          int n_inst, hipStream_t st);
-hipError_t launch_small_class(int kind, int nb, int d, const LaunchArgs& a, int n_items,
-                              int num_cus, hipStream_t st);
-bool small_class_supported(int kind, int nb, int d);
-hipError_t launch_wg_class(int kind, int d, int S, const LaunchArgs& a, int n_items, int num_cus,
-                           hipStream_t st);
-bool wg_class_supported(int kind, int n, int d);
-int wg_slot_size(int n);
-bool large_class_supported(int kind, int n, int d);
-size_t large_scratch_bytes(int n, int nchunks);
-int large_chunks(int n, bool exact, int num_cus);
-hipError_t launch_large(const LaunchArgs& a, int inst, int n, void* scratch, int nchunks,
-                        int num_cus, hipStream_t st);
-}  // namespace irk
 
 namespace {
 
@@ -209,14 +192,13 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
     d.mass_off = -1;
     d.coupling_off = -1;
     if (p.mass && p.kind != IRKGL16_KEPLER) {
-      d.mass_off = (int32_t)params.size();
+      d.mass_off = (int64_t)params.size();
       params.insert(params.end(), p.mass, p.mass + p.n);
     }
     if (p.coupling && p.kind == IRKGL16_CHAIN) {
-      d.coupling_off = (int32_t)params.size();
+      d.coupling_off = (int64_t)params.size();
       params.insert(params.end(), p.coupling, p.coupling + p.n + 1);
     }
-    if (params.size() > (size_t)INT32_MAX) return fail(IRKGL16_EINVAL);
     const int dqi = p.n * p.d;
     c->dq[i] = dqi;
     d.in_off = c->total_dq;

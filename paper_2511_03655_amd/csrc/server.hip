@@ -1,0 +1,567 @@
+// Serving loop behind irkgl16_server_* / irkgl16_submit / irkgl16_poll /
+// irkgl16_wait (include/irkgl16.h): continuous batching of integration
+// requests on one GPU.
+//
+// A serving thread repeats: admit pending requests (first come, first served)
+// while their device memory fits under the cap; run one time slice, i.e. one
+// batched launch per kernel class over all resident requests with a step budget
+// of slice_steps (newly admitted requests are first set up by the prepare
+// kernel); copy the slice's statistics and output frames to the host; retire
+// finished requests (their frames are complete on the host) and free their
+// memory.  A resident request's state record never leaves the device between
+// slices, and the kernels resume from it exactly, so a served request is
+// bit-identical to the same request integrated alone.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/irkgl16.h"
+#include "device_common.h"
+#include "launch.h"
+
+namespace {
+
+// First-fit allocator over [0, size) (units: doubles) with coalescing.
+class Arena {
+ public:
+  explicit Arena(int64_t size) { free_[0] = size; }
+  int64_t alloc(int64_t n) {
+    n = (n + 31) / 32 * 32;  // 256-byte granules
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= n) {
+        const int64_t off = it->first, len = it->second;
+        free_.erase(it);
+        if (len > n) free_[off + n] = len - n;
+        used_[off] = n;
+        return off;
+      }
+    }
+    return -1;
+  }
+  void release(int64_t off) {
+    auto u = used_.find(off);
+    if (u == used_.end()) return;
+    int64_t len = u->second;
+    used_.erase(u);
+    auto next = free_.lower_bound(off);
+    if (next != free_.end() && off + len == next->first) {
+      len += next->second;
+      next = free_.erase(next);
+    }
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        prev->second += len;
+        return;
+      }
+    }
+    free_[off] = len;
+  }
+
+ private:
+  std::map<int64_t, int64_t> free_, used_;
+};
+
+struct Request {
+  int64_t ticket = 0;
+  int32_t kind = 0, n = 0, d = 0, dq = 0;
+  std::vector<double> mass, coupling, q0, p0;
+  double G = 1.0, eps = 0.0, beta = 0.0, h = 0.0;
+  int64_t nsteps = 0, stride = 1;
+  int cls = -1, S = 0;
+  int64_t arena_len = 0, arena_off = -1;
+  int slot = -1;
+  int64_t steps_done = 0;
+  std::vector<double> qf, pf;
+  int32_t status = IRKGL16_OK;
+  int64_t iterations = 0, nonconv = 0;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  bool fresh = false, done = false;
+  bool finish = false;  // set by the slice (worker only); published as `done` under the lock
+  int64_t stage_base = 0, f0 = 0;  // this slice's frame window
+};
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  hipError_t ensure(size_t n, bool keep = false) {
+    if (n <= bytes && p) return hipSuccess;
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(n, 256));
+    if (e != hipSuccess) return e;
+    if (keep && p && bytes) (void)hipMemcpy(q, p, bytes, hipMemcpyDeviceToDevice);
+    if (p) (void)hipFree(p);
+    p = q;
+    bytes = std::max<size_t>(n, 256);
+    return hipSuccess;
+  }
+  template <class T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+double now_s(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+struct irkgl16_server {
+  irkgl16_server_options opt{};
+  int device = 0, num_cus = 1;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::chrono::steady_clock::time_point t0;
+
+  DevBuf d_tab, d_desc, d_stat, d_arena, d_in, d_stage_q, d_stage_p, d_queue, d_heads, d_ids,
+      d_large;
+  int large_nmax = 0;
+  std::unique_ptr<Arena> arena;
+
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Request*> pending;
+  std::vector<Request*> resident;   // by slot
+  std::vector<int> free_slots;
+  std::unordered_map<int64_t, std::unique_ptr<Request>> requests;
+  int64_t next_ticket = 1;
+  bool stopping = false;
+  int device_error = 0;
+  std::thread worker;
+
+  std::vector<irk::InstDesc> h_desc;
+  std::vector<irk::InstStat> h_stat;
+  std::vector<double> h_stage_q, h_stage_p;
+
+  ~irkgl16_server() {
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+  void run();
+  int slice(std::vector<Request*>& live, std::vector<Request*>& fresh);
+};
+
+static int validate(const irkgl16_problem& p) {
+  if (p.n < 1 || p.d < 1 || p.d > 3) return IRKGL16_EINVAL;
+  int S = 0;
+  if (irk::kernel_class(p.kind, p.n, p.d, &S) < 0) return IRKGL16_EINVAL;
+  if (p.kind == IRKGL16_GRAVITY) {
+    if (!p.mass || !std::isfinite(p.G) || !std::isfinite(p.eps) || p.eps < 0) return IRKGL16_EINVAL;
+    for (int a = 0; a < p.n; ++a)
+      if (!(p.mass[a] > 0) || !std::isfinite(p.mass[a])) return IRKGL16_EINVAL;
+  } else if (p.kind == IRKGL16_KEPLER) {
+    if (!std::isfinite(p.G)) return IRKGL16_EINVAL;
+  } else if (p.kind == IRKGL16_CHAIN) {
+    if (!std::isfinite(p.beta)) return IRKGL16_EINVAL;
+    if (p.mass)
+      for (int a = 0; a < p.n; ++a)
+        if (!(p.mass[a] > 0) || !std::isfinite(p.mass[a])) return IRKGL16_EINVAL;
+    if (p.coupling)
+      for (int a = 0; a <= p.n; ++a)
+        if (!std::isfinite(p.coupling[a])) return IRKGL16_EINVAL;
+  }
+  return IRKGL16_OK;
+}
+
+// One time slice over the resident requests.  Called without the lock held.
+int irkgl16_server::slice(std::vector<Request*>& live, std::vector<Request*>& fresh) {
+  const int64_t slice_steps = opt.slice_steps;
+  // frame windows and staging layout
+  int64_t stage_total = 0, in_total = 0;
+  for (Request* r : live) {
+    const int64_t f0 = r->steps_done / r->stride;
+    const int64_t end = std::min(r->nsteps, r->steps_done + slice_steps);
+    const int64_t f1 = end / r->stride;
+    r->f0 = f0;
+    r->stage_base = stage_total;
+    stage_total += (f1 - f0 + 1) * r->dq;
+  }
+  std::vector<int64_t> in_off(live.size(), 0);
+  for (Request* r : fresh) in_total += r->dq;
+  if (d_stage_q.ensure(sizeof(double) * std::max<int64_t>(stage_total, 1)) ||
+      d_stage_p.ensure(sizeof(double) * std::max<int64_t>(stage_total, 1)) ||
+      d_in.ensure(sizeof(double) * 2 * std::max<int64_t>(in_total, 1)))
+    return IRKGL16_EDEVICE;
+  // descriptors of every resident slot, inputs of the fresh ones
+  std::vector<double> hin(2 * std::max<int64_t>(in_total, 1));
+  int64_t io = 0;
+  for (Request* r : fresh) {
+    std::copy(r->q0.begin(), r->q0.end(), hin.begin() + io);
+    std::copy(r->p0.begin(), r->p0.end(), hin.begin() + in_total + io);
+    irk::InstDesc& d = h_desc[r->slot];
+    d.in_off = io;
+    io += r->dq;
+  }
+  int max_slot = 0;
+  for (Request* r : live) {
+    irk::InstDesc& d = h_desc[r->slot];
+    d.out_off = r->stage_base - r->f0 * r->dq;
+    max_slot = std::max(max_slot, r->slot + 1);
+  }
+  std::vector<int32_t> ids;
+  for (Request* r : fresh) ids.push_back(r->slot);
+  // class queues
+  std::map<std::tuple<int, int, int, int>, std::vector<int32_t>> classes;
+  for (Request* r : live) {
+    auto key = std::make_tuple(r->cls, r->kind, r->cls == 0 ? r->n : r->S, r->d);
+    classes[key].push_back(r->slot);
+  }
+  std::vector<int32_t> queue;
+  std::vector<std::pair<std::tuple<int, int, int, int>, std::pair<int64_t, int>>> cls_list;
+  for (auto& kv : classes) {
+    cls_list.push_back({kv.first, {(int64_t)queue.size(), (int)kv.second.size()}});
+    queue.insert(queue.end(), kv.second.begin(), kv.second.end());
+  }
+  if (d_queue.ensure(sizeof(int32_t) * std::max<size_t>(queue.size(), 1)) ||
+      d_ids.ensure(sizeof(int32_t) * std::max<size_t>(ids.size(), 1)) ||
+      d_heads.ensure(sizeof(int32_t) * std::max<size_t>(cls_list.size(), 1)))
+    return IRKGL16_EDEVICE;
+  hipStream_t st = stream;
+#define SRV_TRY(x)                                   \
+  do {                                               \
+    if ((x) != hipSuccess) return IRKGL16_EDEVICE;   \
+  } while (0)
+  SRV_TRY(hipMemcpyAsync(d_desc.p, h_desc.data(), sizeof(irk::InstDesc) * max_slot,
+                         hipMemcpyHostToDevice, st));
+  SRV_TRY(hipMemcpyAsync(d_queue.p, queue.data(), sizeof(int32_t) * queue.size(),
+                         hipMemcpyHostToDevice, st));
+  SRV_TRY(hipMemsetAsync(d_heads.p, 0, sizeof(int32_t) * cls_list.size(), st));
+  if (!fresh.empty()) {
+    SRV_TRY(hipMemcpyAsync(d_in.p, hin.data(), sizeof(double) * 2 * in_total,
+                           hipMemcpyHostToDevice, st));
+    SRV_TRY(hipMemcpyAsync(d_ids.p, ids.data(), sizeof(int32_t) * ids.size(),
+                           hipMemcpyHostToDevice, st));
+    SRV_TRY(irk::launch_prepare(d_desc.as<irk::InstDesc>(), d_stat.as<irk::InstStat>(),
+                                d_arena.as<double>(), d_arena.as<double>(), d_in.as<double>(),
+                                d_in.as<double>() + in_total, d_stage_q.as<double>(),
+                                d_stage_p.as<double>(), nullptr, d_heads.as<int32_t>(),
+                                (int)cls_list.size(), (int)ids.size(), st,
+                                d_ids.as<int32_t>()));
+  }
+  irk::LaunchArgs a;
+  a.tab = d_tab.as<double>();
+  a.desc = d_desc.as<irk::InstDesc>();
+  a.stat = d_stat.as<irk::InstStat>();
+  a.state = d_arena.as<double>();
+  a.params = d_arena.as<double>();
+  a.qout = d_stage_q.as<double>();
+  a.pout = d_stage_p.as<double>();
+  a.step_iters = nullptr;
+  a.max_iter = opt.max_iter;
+  a.step_budget = slice_steps;
+  a.exact = (opt.flags & IRKGL16_REPRODUCIBLE) ? 1 : 0;
+  for (size_t k = 0; k < cls_list.size(); ++k) {
+    const auto& key = cls_list[k].first;
+    const int cls = std::get<0>(key), kind = std::get<1>(key), sz = std::get<2>(key),
+              d = std::get<3>(key);
+    a.queue = d_queue.as<int32_t>() + cls_list[k].second.first;
+    a.queue_len = cls_list[k].second.second;
+    a.queue_head = d_heads.as<int32_t>() + k;
+    if (cls == 0) {
+      SRV_TRY(irk::launch_small_class(kind, sz, d, a, a.queue_len, num_cus, st));
+    } else if (cls == 1) {
+      SRV_TRY(irk::launch_wg_class(kind, d, sz, a, a.queue_len, num_cus, st));
+    } else {
+      for (int i = 0; i < a.queue_len; ++i) {
+        const int slot = queue[cls_list[k].second.first + i];
+        Request* r = resident[slot];
+        const int ch = irk::large_chunks(r->n, a.exact != 0, num_cus);
+        SRV_TRY(irk::launch_large(a, slot, r->n, d_large.p, ch, num_cus, st));
+      }
+    }
+  }
+  if ((int64_t)h_stage_q.size() < stage_total) {
+    h_stage_q.resize(stage_total);
+    h_stage_p.resize(stage_total);
+  }
+  SRV_TRY(hipMemcpyAsync(h_stat.data(), d_stat.p, sizeof(irk::InstStat) * max_slot,
+                         hipMemcpyDeviceToHost, st));
+  if (stage_total > 0) {
+    SRV_TRY(hipMemcpyAsync(h_stage_q.data(), d_stage_q.p, sizeof(double) * stage_total,
+                           hipMemcpyDeviceToHost, st));
+    SRV_TRY(hipMemcpyAsync(h_stage_p.data(), d_stage_p.p, sizeof(double) * stage_total,
+                           hipMemcpyDeviceToHost, st));
+  }
+  SRV_TRY(hipStreamSynchronize(st));
+#undef SRV_TRY
+  // harvest frames and progress
+  for (Request* r : live) {
+    const irk::InstStat& s = h_stat[r->slot];
+    const int64_t old = r->steps_done;
+    const int64_t fa = r->fresh ? 0 : old / r->stride + 1;
+    const int64_t fb = s.steps_done / r->stride;
+    for (int64_t f = fa; f <= fb; ++f) {
+      const int64_t src = r->stage_base + (f - r->f0) * r->dq;
+      std::copy(h_stage_q.begin() + src, h_stage_q.begin() + src + r->dq,
+                r->qf.begin() + f * r->dq);
+      std::copy(h_stage_p.begin() + src, h_stage_p.begin() + src + r->dq,
+                r->pf.begin() + f * r->dq);
+    }
+    r->steps_done = s.steps_done;
+    r->iterations = s.iterations;
+    r->nonconv = s.nonconv;
+    r->fresh = false;
+    if (s.status != irk::kOk) {
+      r->status = s.status;
+      std::fill(r->qf.begin() + (fb + 1) * r->dq, r->qf.end(), std::nan(""));
+      std::fill(r->pf.begin() + (fb + 1) * r->dq, r->pf.end(), std::nan(""));
+      r->finish = true;
+    } else if (r->steps_done >= r->nsteps) {
+      r->status = r->nonconv ? IRKGL16_ENOCONV : IRKGL16_OK;
+      r->finish = true;
+    }
+  }
+  return IRKGL16_OK;
+}
+
+void irkgl16_server::run() {
+  (void)hipSetDevice(device);
+  for (;;) {
+    std::vector<Request*> live, fresh;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      // admission: first come, first served, while memory and slots allow
+      while (!pending.empty() && !free_slots.empty()) {
+        Request* r = pending.front();
+        const int64_t off = arena->alloc(r->arena_len);
+        if (off < 0) break;
+        pending.pop_front();
+        r->arena_off = off;
+        r->slot = free_slots.back();
+        free_slots.pop_back();
+        resident[r->slot] = r;
+        r->t_admit = now_s(t0);
+        r->fresh = true;
+        // descriptor of the new request
+        irk::InstDesc& d = h_desc[r->slot];
+        std::memset(&d, 0, sizeof(d));
+        d.kind = r->kind;
+        d.n = r->n;
+        d.d = r->d;
+        d.G = r->G;
+        d.eps = r->eps;
+        d.beta = r->beta;
+        d.h = r->h;
+        d.nsteps = r->nsteps;
+        d.stride = r->stride;
+        d.iters_off = -1;
+        d.state_off = off;
+        int64_t po = off + (int64_t)(4 + irk::kS) * r->dq;
+        d.mass_off = r->mass.empty() ? -1 : po;
+        po += (int64_t)r->mass.size();
+        d.coupling_off = r->coupling.empty() ? -1 : po;
+        if (r->cls == 2 && r->n > large_nmax) {
+          if (d_large.ensure(irk::large_scratch_bytes(r->n, 16))) {
+            device_error = IRKGL16_EDEVICE;
+          }
+          large_nmax = r->n;
+        }
+      }
+      for (Request* r : resident)
+        if (r) (r->fresh ? fresh : live).push_back(r);
+      if (fresh.empty() && live.empty()) {
+        if (stopping && pending.empty()) return;
+        cv_work.wait(lk);
+        continue;
+      }
+    }
+    // parameters of fresh requests into the arena
+    for (Request* r : fresh) {
+      const int64_t po = r->arena_off + (int64_t)(4 + irk::kS) * r->dq;
+      std::vector<double> prm(r->mass);
+      prm.insert(prm.end(), r->coupling.begin(), r->coupling.end());
+      if (!prm.empty())
+        (void)hipMemcpyAsync(d_arena.as<double>() + po, prm.data(), sizeof(double) * prm.size(),
+                             hipMemcpyHostToDevice, stream);
+    }
+    live.insert(live.end(), fresh.begin(), fresh.end());
+    const int rc = device_error ? device_error : slice(live, fresh);
+    std::lock_guard<std::mutex> lk(mu);
+    for (Request* r : live) {
+      if (rc != IRKGL16_OK && !r->finish) {
+        r->status = rc;
+        r->finish = true;
+      }
+      if (r->finish) {
+        r->done = true;
+        r->t_done = now_s(t0);
+        arena->release(r->arena_off);
+        resident[r->slot] = nullptr;
+        free_slots.push_back(r->slot);
+      }
+    }
+    cv_done.notify_all();
+  }
+}
+
+extern "C" {
+
+int irkgl16_server_create(irkgl16_server** out, const irkgl16_server_options* opt,
+                          void* hip_stream) {
+  if (!out || !opt || opt->cap_bytes <= 0) return IRKGL16_EINVAL;
+  *out = nullptr;
+  try {
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return IRKGL16_EDEVICE;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return IRKGL16_EDEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return IRKGL16_EDEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return IRKGL16_EDEVICE;
+    std::unique_ptr<irkgl16_server> s(new irkgl16_server());
+    s->opt = *opt;
+    if (s->opt.slice_steps <= 0) s->opt.slice_steps = 1000;
+    if (s->opt.max_iter <= 0) s->opt.max_iter = 100;
+    if (s->opt.max_resident <= 0) s->opt.max_resident = 65536;
+    s->device = dev;
+    s->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+    s->t0 = std::chrono::steady_clock::now();
+    const int64_t cap_doubles = opt->cap_bytes / (int64_t)sizeof(double);
+    if (s->d_arena.ensure(sizeof(double) * (size_t)cap_doubles) != hipSuccess)
+      return IRKGL16_ENOMEM;
+    s->arena.reset(new Arena(cap_doubles));
+    const size_t R = (size_t)s->opt.max_resident;
+    if (s->d_desc.ensure(sizeof(irk::InstDesc) * R) || s->d_stat.ensure(sizeof(irk::InstStat) * R) ||
+        s->d_tab.ensure(sizeof(double) * irk::kTabSize))
+      return IRKGL16_ENOMEM;
+    std::vector<double> tab(irk::kTabSize);
+    for (int i = 0; i < irk::kS; ++i) {
+      tab[irk::kTabC + i] = irk::kC[i];
+      tab[irk::kTabB + i] = irk::kB[i];
+      for (int j = 0; j < irk::kS; ++j) {
+        tab[irk::kTabEta + i * irk::kS + j] = irk::kEta[i][j];
+        tab[irk::kTabMu + i * irk::kS + j] = irk::kMu[i][j];
+        tab[irk::kTabNu + i * irk::kS + j] = irk::kNu[i][j];
+      }
+    }
+    if (hipMemcpy(s->d_tab.p, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice) !=
+        hipSuccess)
+      return IRKGL16_EDEVICE;
+    s->h_desc.resize(R);
+    s->h_stat.resize(R);
+    s->resident.assign(R, nullptr);
+    for (int i = (int)R - 1; i >= 0; --i) s->free_slots.push_back(i);
+    if (hip_stream) {
+      s->stream = (hipStream_t)hip_stream;
+    } else {
+      if (hipStreamCreate(&s->stream) != hipSuccess) return IRKGL16_EDEVICE;
+      s->own_stream = true;
+    }
+    irkgl16_server* raw = s.release();
+    raw->worker = std::thread([raw] { raw->run(); });
+    *out = raw;
+    return IRKGL16_OK;
+  } catch (const std::bad_alloc&) {
+    return IRKGL16_ENOMEM;
+  } catch (...) {
+    return IRKGL16_EDEVICE;
+  }
+}
+
+int irkgl16_submit(irkgl16_server* s, const irkgl16_problem* prob, const double* q0,
+                   const double* p0, double h, int64_t nsteps, int64_t out_stride,
+                   int64_t* ticket) {
+  if (!s || !prob || !q0 || !p0 || !ticket) return IRKGL16_EINVAL;
+  if (validate(*prob) != IRKGL16_OK) return IRKGL16_EINVAL;
+  if (!std::isfinite(h) || h == 0.0 || nsteps < 0 || out_stride < 1 || nsteps % out_stride)
+    return IRKGL16_EINVAL;
+  try {
+    std::unique_ptr<Request> r(new Request());
+    r->kind = prob->kind;
+    r->n = prob->n;
+    r->d = prob->d;
+    r->dq = prob->n * prob->d;
+    r->G = prob->G;
+    r->eps = prob->eps;
+    r->beta = prob->beta;
+    if (prob->mass && prob->kind != IRKGL16_KEPLER) r->mass.assign(prob->mass, prob->mass + prob->n);
+    if (prob->coupling && prob->kind == IRKGL16_CHAIN)
+      r->coupling.assign(prob->coupling, prob->coupling + prob->n + 1);
+    r->q0.assign(q0, q0 + r->dq);
+    r->p0.assign(p0, p0 + r->dq);
+    r->h = h;
+    r->nsteps = nsteps;
+    r->stride = out_stride;
+    r->cls = irk::kernel_class(r->kind, r->n, r->d, &r->S);
+    r->arena_len = (int64_t)(4 + irk::kS) * r->dq + (int64_t)r->mass.size() +
+                   (int64_t)r->coupling.size();
+    if (r->arena_len * (int64_t)sizeof(double) > s->opt.cap_bytes) return IRKGL16_EINVAL;
+    const int64_t nf = nsteps / out_stride + 1;
+    r->qf.assign((size_t)(nf * r->dq), 0.0);
+    r->pf.assign((size_t)(nf * r->dq), 0.0);
+    std::lock_guard<std::mutex> lk(s->mu);
+    r->ticket = s->next_ticket++;
+    r->t_submit = now_s(s->t0);
+    *ticket = r->ticket;
+    s->pending.push_back(r.get());
+    s->requests[r->ticket] = std::move(r);
+    s->cv_work.notify_one();
+    return IRKGL16_OK;
+  } catch (const std::bad_alloc&) {
+    return IRKGL16_ENOMEM;
+  }
+}
+
+int irkgl16_poll(irkgl16_server* s, int64_t ticket, int32_t* done) {
+  if (!s || !done) return IRKGL16_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->requests.find(ticket);
+  if (it == s->requests.end()) return IRKGL16_EINVAL;
+  *done = it->second->done ? 1 : 0;
+  return IRKGL16_OK;
+}
+
+int irkgl16_wait(irkgl16_server* s, int64_t ticket, double* q_out, double* p_out,
+                 irkgl16_request_info* info) {
+  if (!s) return IRKGL16_EINVAL;
+  std::unique_ptr<Request> r;
+  {
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->requests.find(ticket);
+    if (it == s->requests.end()) return IRKGL16_EINVAL;
+    Request* raw = it->second.get();
+    s->cv_done.wait(lk, [&] { return raw->done; });
+    r = std::move(it->second);
+    s->requests.erase(it);
+  }
+  if (q_out) std::memcpy(q_out, r->qf.data(), sizeof(double) * r->qf.size());
+  if (p_out) std::memcpy(p_out, r->pf.data(), sizeof(double) * r->pf.size());
+  if (info) {
+    info->status = r->status;
+    info->steps = r->steps_done;
+    info->iterations = r->iterations;
+    info->submit_s = r->t_submit;
+    info->admit_s = r->t_admit;
+    info->done_s = r->t_done;
+  }
+  return r->status;
+}
+
+void irkgl16_server_destroy(irkgl16_server* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stopping = true;
+    s->cv_work.notify_all();
+  }
+  if (s->worker.joinable()) s->worker.join();
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  delete s;
+}
+
+}  // extern "C"

@@ -26,7 +26,8 @@ IRKGL16_KEPLER, IRKGL16_GRAVITY, IRKGL16_CHAIN = 0, 1, 2
 IRKGL16_DEVICE_PTRS, IRKGL16_PLAIN, IRKGL16_REPRODUCIBLE = 1, 2, 4
 
 EXPORTED = ["irkgl16_create", "irkgl16_integrate", "irkgl16_last_stats", "irkgl16_destroy",
-            "irkgl16_strerror"]
+            "irkgl16_strerror", "irkgl16_server_create", "irkgl16_submit", "irkgl16_poll",
+            "irkgl16_wait", "irkgl16_server_destroy"]
 
 
 class irkgl16_problem(C.Structure):
@@ -45,6 +46,16 @@ class irkgl16_stats(C.Structure):
                 ("n_nonfinite", C.c_int32), ("device_ms", C.c_double),
                 ("inst_iterations", C.POINTER(C.c_int64)), ("inst_status", C.POINTER(C.c_int32)),
                 ("step_iters", C.POINTER(C.c_uint8))]
+
+
+class irkgl16_server_options(C.Structure):
+    _fields_ = [("cap_bytes", C.c_int64), ("slice_steps", C.c_int64), ("max_iter", C.c_int32),
+                ("max_resident", C.c_int32), ("flags", C.c_uint32)]
+
+
+class irkgl16_request_info(C.Structure):
+    _fields_ = [("status", C.c_int32), ("steps", C.c_int64), ("iterations", C.c_int64),
+                ("submit_s", C.c_double), ("admit_s", C.c_double), ("done_s", C.c_double)]
 
 
 class IRKGL16Error(RuntimeError):
@@ -76,6 +87,18 @@ def lib():
         L.irkgl16_destroy.restype = None
         L.irkgl16_strerror.argtypes = [C.c_int]
         L.irkgl16_strerror.restype = C.c_char_p
+        L.irkgl16_server_create.argtypes = [C.POINTER(C.c_void_p),
+                                            C.POINTER(irkgl16_server_options), C.c_void_p]
+        L.irkgl16_server_create.restype = C.c_int
+        L.irkgl16_submit.argtypes = [C.c_void_p, C.POINTER(irkgl16_problem), dp, dp, C.c_double,
+                                     C.c_int64, C.c_int64, C.POINTER(C.c_int64)]
+        L.irkgl16_submit.restype = C.c_int
+        L.irkgl16_poll.argtypes = [C.c_void_p, C.c_int64, C.POINTER(C.c_int32)]
+        L.irkgl16_poll.restype = C.c_int
+        L.irkgl16_wait.argtypes = [C.c_void_p, C.c_int64, dp, dp, C.POINTER(irkgl16_request_info)]
+        L.irkgl16_wait.restype = C.c_int
+        L.irkgl16_server_destroy.argtypes = [C.c_void_p]
+        L.irkgl16_server_destroy.restype = None
         _lib = L
     return _lib
 
@@ -221,3 +244,102 @@ def split_frames(flat, dq, nframes):
         out.append(np.asarray(flat[off:off + d * f]).reshape(f, d))
         off += d * f
     return out
+
+
+# ---------------------------------------------------------------- serving
+
+def _problem_struct(p, keep):
+    mass, coup = p.get("mass"), p.get("coupling")
+    m = None if mass is None else np.ascontiguousarray(mass, np.float64)
+    c = None if coup is None else np.ascontiguousarray(coup, np.float64)
+    keep += [m, c]
+    return irkgl16_problem(int(p["kind"]), int(p["n"]), int(p["d"]),
+                           m.ctypes.data_as(C.POINTER(C.c_double)) if m is not None else None,
+                           c.ctypes.data_as(C.POINTER(C.c_double)) if c is not None else None,
+                           float(p.get("G", 1.0)), float(p.get("eps", 0.0)),
+                           float(p.get("beta", 0.0)))
+
+
+def irkgl16_server_create(cap_bytes, slice_steps=0, max_iter=0, max_resident=0, flags=0,
+                          stream=None):
+    opt = irkgl16_server_options(int(cap_bytes), int(slice_steps), int(max_iter),
+                                 int(max_resident), int(flags))
+    if stream is not None and hasattr(stream, "cuda_stream"):
+        stream = stream.cuda_stream
+    srv = C.c_void_p()
+    rc = lib().irkgl16_server_create(C.byref(srv), C.byref(opt),
+                                     C.c_void_p(stream) if stream else None)
+    if rc != IRKGL16_OK:
+        raise IRKGL16Error(rc, "irkgl16_server_create")
+    return srv
+
+
+def irkgl16_submit(srv, problem, q0, p0, h, nsteps, out_stride):
+    keep = []
+    pr = _problem_struct(problem, keep)
+    q0 = np.ascontiguousarray(q0, np.float64)
+    p0 = np.ascontiguousarray(p0, np.float64)
+    t = C.c_int64()
+    rc = lib().irkgl16_submit(srv, C.byref(pr), q0.ctypes.data_as(C.POINTER(C.c_double)),
+                              p0.ctypes.data_as(C.POINTER(C.c_double)), float(h), int(nsteps),
+                              int(out_stride), C.byref(t))
+    if rc != IRKGL16_OK:
+        raise IRKGL16Error(rc, "irkgl16_submit")
+    return t.value
+
+
+def irkgl16_poll(srv, ticket):
+    done = C.c_int32()
+    rc = lib().irkgl16_poll(srv, int(ticket), C.byref(done))
+    if rc != IRKGL16_OK:
+        raise IRKGL16Error(rc, "irkgl16_poll")
+    return bool(done.value)
+
+
+def irkgl16_wait(srv, ticket, q_out=None, p_out=None):
+    info = irkgl16_request_info()
+    dp = C.POINTER(C.c_double)
+    rc = lib().irkgl16_wait(srv, int(ticket),
+                            q_out.ctypes.data_as(dp) if q_out is not None else None,
+                            p_out.ctypes.data_as(dp) if p_out is not None else None,
+                            C.byref(info))
+    return rc, dict(status=info.status, steps=info.steps, iterations=info.iterations,
+                    submit_s=info.submit_s, admit_s=info.admit_s, done_s=info.done_s)
+
+
+def irkgl16_server_destroy(srv):
+    if srv:
+        lib().irkgl16_server_destroy(srv)
+
+
+class Server:
+    """Owns one serving thread (continuous batching)."""
+
+    def __init__(self, cap_bytes=1 << 30, slice_steps=1000, max_iter=0, max_resident=0, flags=0,
+                 stream=None):
+        self.srv = irkgl16_server_create(cap_bytes, slice_steps, max_iter, max_resident, flags,
+                                         stream)
+        self._dq = {}
+
+    def submit(self, problem, q0, p0, h, nsteps, out_stride):
+        t = irkgl16_submit(self.srv, problem, q0, p0, h, nsteps, out_stride)
+        self._dq[t] = (int(problem["n"]) * int(problem["d"]), int(nsteps) // int(out_stride) + 1)
+        return t
+
+    def poll(self, ticket):
+        return irkgl16_poll(self.srv, ticket)
+
+    def wait(self, ticket, keep_frames=True):
+        dq, nf = self._dq.pop(ticket)
+        q = np.empty(dq * nf) if keep_frames else None
+        p = np.empty(dq * nf) if keep_frames else None
+        rc, info = irkgl16_wait(self.srv, ticket, q, p)
+        return q, p, info, rc
+
+    def close(self):
+        if self.srv:
+            irkgl16_server_destroy(self.srv)
+            self.srv = None
+
+    __del__ = close
+
