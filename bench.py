@@ -94,10 +94,15 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=4000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload != "c2":
+        print(json.dumps(OTHER_WORKLOADS[args.workload](args)))
+        return
 
     import torch
     from paper_2511_03655_amd import irkgl16 as K
@@ -195,6 +200,19 @@ def main():
                      sample="full workload, one call, IRKGL16_REPRODUCIBLE")
         ri.close()
 
+    served = None
+    if not args.no_served:
+        # bounded sample of the served stream: Poisson arrivals of the uneven mix
+        from paper_2511_03655_amd import serve
+        reqs = W.poisson_requests(1000.0, 400, steps_range=(1e3, 1e4), stride=100,
+                                  plummer_sizes=(64, 128))
+        so = serve.run_stream(reqs, cap_bytes=8 << 30, slice_steps=1000)
+        served = dict(rate_per_s=1000.0, requests=len(reqs), p50_latency_s=so["p50_s"],
+                      p99_latency_s=so["p99_s"], steps_per_s=so["steps_per_s"],
+                      sample="400 Poisson requests at 1000/s from the uneven mix and Plummer "
+                             "clusters of 64-128 bodies, 1e3..1e4 steps, output every 100 steps, "
+                             "time slices of 1000 steps")
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(sy, min(args.cpu_sample, n_inst), args.cpu_steps)
@@ -226,11 +244,217 @@ def main():
                      "pass_frac": gate, "median_dE": float(np.median(dE))},
         "plain": plain,
         "reproducible": repro,
+        "served": served,
         "cpu_baseline": cpu,
         "status": rc,
     }
     print(json.dumps(out))
     integ.close()
+
+
+# ---------------------------------------------------------------------------
+# The other configurations (run with --workload; the default line is c2).
+
+def _common(metric_unit, value, cfg, extra):
+    out = {"metric": METRIC, "value": value, "unit": metric_unit, "n_gpus": 1,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic", "config": cfg}
+    out.update(extra)
+    return out
+
+
+def _problem(inst):
+    p = dict(kind=inst["kind"], n=inst["n"], d=inst["d"], G=inst.get("G", 1.0),
+             eps=inst.get("eps", 0.0), beta=inst.get("beta", 0.0))
+    if inst.get("mass") is not None:
+        p["mass"] = inst["mass"]
+    return p
+
+
+def _flops_inst_step(inst, k):
+    """Algorithmic flops of one step with k iterations (same convention as c2)."""
+    n, dq = inst["n"], inst["n"] * inst["d"]
+    if inst["kind"] == 0:
+        fg = 10
+    elif inst["kind"] == 1:
+        fg = 20 * n * (n - 1)
+    else:
+        fg = 6 * n
+    return k * (8 * fg + 8 * dq * 21) + 8 * dq * 36 + 50 * dq
+
+
+def _timed_gpu(integ, q0, p0, h, ns, sd, reps=1):
+    import torch
+    from paper_2511_03655_amd import irkgl16 as K
+    dev = torch.device("cuda:0")
+    q0d = torch.from_numpy(np.ascontiguousarray(q0)).to(dev)
+    p0d = torch.from_numpy(np.ascontiguousarray(p0)).to(dev)
+    total = int(np.sum(integ.dq * (np.asarray(ns) // np.asarray(sd) + 1)))
+    qo = torch.empty(total, dtype=torch.float64, device=dev)
+    po = torch.empty_like(qo)
+    ones = np.ones(len(np.atleast_1d(ns)), np.int64)
+    K.irkgl16_integrate(integ.ctx, q0d, p0d, h, ones, ones, qo, po)  # warm-up: one step
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        rc = K.irkgl16_integrate(integ.ctx, q0d, p0d, h, ns, sd, qo, po)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    st, rc2 = integ.last_stats()
+    return dt, st, rc2, qo, po
+
+
+def run_c1(args):
+    import torch
+    from paper_2511_03655_amd import irkgl16 as K
+    from paper_2511_03655_amd import workloads as W
+    from oracle import oracle as orc
+    c1 = W.kepler_c1()
+    n = c1["nsteps"]
+    stream = torch.cuda.Stream()
+    prob = [dict(kind=0, n=1, d=2, G=1.0)]
+    integ = K.Integrator(prob, flags=K.IRKGL16_DEVICE_PTRS, stream=stream)
+    dt, st, rc, qo, po = _timed_gpu(integ, c1["q"], c1["p"], np.array([c1["h"]]),
+                                    np.array([n]), np.array([1]), reps=3)
+    plain = K.Integrator(prob, flags=K.IRKGL16_PLAIN)
+    t = time.perf_counter()
+    plain.integrate(c1["q"], c1["p"], c1["h"], 2000, 2000)
+    dtp = (time.perf_counter() - t) / 2000
+    sp = orc.Spec(orc.KEPLER, 1, 2, G=1.0)
+    t = time.perf_counter()
+    r = orc.integrate(sp, c1["q"], c1["p"], c1["h"], n, 1)
+    dtc = time.perf_counter() - t
+    q = qo.cpu().numpy().reshape(-1, 2)
+    rel = float(np.max(np.abs(q - r["q"])) / np.max(np.abs(r["q"])))
+    return _common("steps/s", n / dt,
+                   {"workload": "planar Kepler a=1 e=0.6, 1 instance, h=2pi/128, 1e4 steps, "
+                                "every step output"},
+                   {"ms_per_step": dt * 1e3, "mean_iterations_per_step": st["iterations"] / n,
+                    "max_rel_diff_vs_oracle_all_frames": rel,
+                    "plain": {"value": 1.0 / dtp, "unit": "steps/s",
+                              "sample": "2000 steps, one launch per step"},
+                    "cpu_baseline": {"value": n / dtc, "unit": "steps/s", "cores": 1,
+                                     "kind": "oracle", "sample": "the full 1e4 steps"}})
+
+
+def run_c3(args):
+    import torch
+    from paper_2511_03655_amd import irkgl16 as K
+    from paper_2511_03655_amd import workloads as W
+    from oracle import oracle as orc
+    inst = W.plummer(2048)
+    n = 1000
+    stream = torch.cuda.Stream()
+    integ = K.Integrator([_problem(inst)], flags=K.IRKGL16_DEVICE_PTRS, stream=stream)
+    dt, st, rc, qo, po = _timed_gpu(integ, inst["q"], inst["p"], np.array([inst["h"]]),
+                                    np.array([n]), np.array([n]), reps=2)
+    k = st["iterations"] / n
+    flops = st["iterations"] * (8 * 20 * 2048 * 2047 + 8 * 6144 * 21) + n * (8 * 6144 * 36 + 50 * 6144)
+    pairs = st["iterations"] * 8 * 2048 * 2047
+    plain = K.Integrator([_problem(inst)], flags=K.IRKGL16_PLAIN)
+    t = time.perf_counter()
+    plain.integrate(inst["q"], inst["p"], inst["h"], 50, 50)
+    dtp = (time.perf_counter() - t) / 50
+    sp = orc.Spec(orc.GRAVITY, 2048, 3, mass=inst["mass"], eps=inst["eps"])
+    t = time.perf_counter()
+    orc.integrate(sp, inst["q"], inst["p"], inst["h"], 10, 10)
+    dtc = (time.perf_counter() - t) / 10
+    return _common("steps/s", n / dt,
+                   {"workload": "Plummer N=2048, eps=1e-2, h=1e-3, 1e3 steps, final state"},
+                   {"ms_per_step": dt / n * 1e3, "mean_iterations_per_step": k,
+                    "pair_interactions_per_s": pairs / dt,
+                    "roofline": {"bound": "alu", "achieved": flops / dt / 1e12,
+                                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                 "frac": flops / dt / 1e12 / FP64_PEAK_TFLOPS, "traffic": None},
+                    "plain": {"value": 1.0 / dtp, "unit": "steps/s",
+                              "sample": "50 steps, one launch per step"},
+                    "cpu_baseline": {"value": 1.0 / dtc, "unit": "steps/s", "cores": 1,
+                                     "kind": "oracle", "sample": "10 steps (single instance, "
+                                                                 "one thread)"}})
+
+
+def run_c4(args):
+    import torch
+    from paper_2511_03655_amd import irkgl16 as K
+    from paper_2511_03655_amd import workloads as W
+    from oracle import oracle as orc
+    t0 = time.perf_counter()
+    mix = W.uneven_mix(4096)
+    print(f"c4: generated {len(mix)} instances in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    probs = [_problem(m) for m in mix]
+    h = np.array([m["h"] for m in mix])
+    ns = np.array([m["nsteps"] for m in mix], np.int64)
+    q0 = np.concatenate([m["q"] for m in mix])
+    p0 = np.concatenate([m["p"] for m in mix])
+    stream = torch.cuda.Stream()
+    integ = K.Integrator(probs, flags=K.IRKGL16_DEVICE_PTRS, stream=stream)
+    dt, st, rc, qo, po = _timed_gpu(integ, q0, p0, h, ns, ns, reps=1)
+    print(f"c4: batched run {dt:.2f} s", file=sys.stderr, flush=True)
+    its = st["inst_iterations"]
+    flops = sum(_flops_inst_step(m, it / m["nsteps"]) * m["nsteps"] for m, it in zip(mix, its))
+    total_steps = int(ns.sum())
+    # plain form on a sample: 2 instances of every class, 100 steps each
+    sample = []
+    seen = {}
+    for i, m in enumerate(mix):
+        if seen.get(m["cls"], 0) < 2:
+            seen[m["cls"]] = seen.get(m["cls"], 0) + 1
+            sample.append(i)
+    pp = [probs[i] for i in sample]
+    pq = np.concatenate([mix[i]["q"] for i in sample])
+    pv = np.concatenate([mix[i]["p"] for i in sample])
+    plain = K.Integrator(pp, flags=K.IRKGL16_PLAIN)
+    t = time.perf_counter()
+    plain.integrate(pq, pv, h[sample], 100, 100)
+    dtp = time.perf_counter() - t
+    bat = K.Integrator(pp)
+    bat.integrate(pq, pv, h[sample], 20, 20)
+    t = time.perf_counter()
+    bat.integrate(pq, pv, h[sample], 100, 100)
+    dtb = time.perf_counter() - t
+    specs = [orc.Spec(mix[i]["kind"], mix[i]["n"], mix[i]["d"], mass=mix[i].get("mass"),
+                      G=mix[i].get("G", 1.0), beta=mix[i].get("beta", 0.0)) for i in sample]
+    t = time.perf_counter()
+    orc.integrate_batch(specs, pq, pv, h[sample], 100, 100)
+    dtc = time.perf_counter() - t
+    return _common("instance-steps/s", total_steps / dt,
+                   {"workload": "4096 uneven instances: gravity 3/6/16/64 bodies and FPU-beta "
+                                "chains 32/256/1024 sites, per-instance h, 1e3..1e5 steps"},
+                   {"seconds": dt, "instance_steps": total_steps,
+                    "roofline": {"bound": "alu", "achieved": flops / dt / 1e12,
+                                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                 "frac": flops / dt / 1e12 / FP64_PEAK_TFLOPS, "traffic": None},
+                    "plain": {"value": len(sample) * 100 / dtp, "unit": "instance-steps/s",
+                              "batched_same_sample": len(sample) * 100 / dtb,
+                              "sample": f"{len(sample)} instances (2 per class) x 100 steps"},
+                    "cpu_baseline": {"value": len(sample) * 100 / dtc, "unit": "instance-steps/s",
+                                     "cores": int(os.environ.get("OMP_NUM_THREADS",
+                                                                 os.cpu_count() or 1)),
+                                     "kind": "oracle", "sample": "same 14 instances x 100 steps"}})
+
+
+def run_c5(args):
+    from paper_2511_03655_amd import serve
+    from paper_2511_03655_amd import workloads as W
+    rows = []
+    for rate, nreq in ((10.0, 60), (100.0, 300), (1000.0, 600), (10000.0, 1000)):
+        reqs = W.poisson_requests(rate, nreq, steps_range=(1e3, 1e5), stride=100,
+                                  plummer_sizes=(64, 128, 256))
+        so = serve.run_stream(reqs, cap_bytes=64 << 30, slice_steps=1000)
+        print(f"c5: rate {rate}/s done in {so['wall_s']:.1f} s", file=sys.stderr, flush=True)
+        rows.append(dict(rate_per_s=rate, requests=nreq, p50_latency_s=so["p50_s"],
+                         p99_latency_s=so["p99_s"], steps_per_s=so["steps_per_s"],
+                         wall_s=so["wall_s"]))
+    best = max(r["steps_per_s"] for r in rows)
+    return _common("instance-steps/s", best,
+                   {"workload": "served Poisson stream of the uneven mix plus Plummer clusters "
+                                "(64-256 bodies), 1e3..1e5 steps, output every 100 steps, "
+                                "64 GB admission cap, slices of 1000 steps"},
+                   {"rates": rows})
+
+
+OTHER_WORKLOADS = {"c1": run_c1, "c3": run_c3, "c4": run_c4, "c5": run_c5}
 
 
 if __name__ == "__main__":

@@ -182,6 +182,15 @@ def fpu_chain(n, seed=BASE_SEED + 4, beta=1.0, energy_density=0.01, noise=1e-6, 
     return dict(kind=CHAIN, n=n, d=1, mass=None, G=1.0, eps=0.0, beta=beta, q=q, p=p, h=h)
 
 
+def _max_pair_frequency(inst):
+    q = inst["q"].reshape(-1, 3)
+    m = inst["mass"]
+    d = q[:, None, :] - q[None, :, :]
+    r = np.sqrt(np.sum(d * d, -1))
+    iu = np.triu_indices(len(m), 1)
+    return float(np.max(np.sqrt(inst["G"] * (m[:, None] + m[None, :])[iu] / r[iu] ** 3)))
+
+
 MIX_CLASSES = [("gravity", 3), ("gravity", 6), ("gravity", 16), ("gravity", 64),
                ("chain", 32), ("chain", 256), ("chain", 1024)]
 
@@ -190,9 +199,10 @@ def uneven_mix(n_inst=4096, seed=BASE_SEED + 4, steps_range=(1e3, 1e5), classes=
     """The uneven batch: classes uniform over MIX_CLASSES, per-instance h and steps.
 
     Gravity systems are generated as planetary_systems with the class's body
-    count; their step is h = U(0.05, 1) x 0.5 / w_max with w_max =
-    sqrt(1 / a_min^3) (the fastest orbit).  Steps are log-uniform in
-    steps_range.
+    count; their step is h = U(0.05, 1) x 0.5 / w_max with w_max the fastest
+    pairwise frequency max_{a<b} sqrt(G (m_a + m_b) / r_ab^3) of the initial
+    configuration (star-planet and planet-planet pairs alike).  Steps are
+    log-uniform in steps_range.
     """
     classes = classes or MIX_CLASSES
     out = []
@@ -201,8 +211,7 @@ def uneven_mix(n_inst=4096, seed=BASE_SEED + 4, steps_range=(1e3, 1e5), classes=
         sub = int(g.integers(2 ** 62))
         if kind == "gravity":
             inst = planetary_systems(1, n_bodies=size, seed=sub)[0]
-            scale = 0.5 * inst["a_min"] ** 1.5
-            inst["h"] = float(g.uniform(0.05, 1.0) * scale)
+            inst["h"] = float(g.uniform(0.05, 1.0) * 0.5 / _max_pair_frequency(inst))
         else:
             inst = fpu_chain(size, seed=sub)
         inst["nsteps"] = int(round(math.exp(g.uniform(math.log(steps_range[0]),
