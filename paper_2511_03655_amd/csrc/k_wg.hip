@@ -36,21 +36,19 @@ __device__ __forceinline__ void unit_increments(const double* __restrict__ Qs,
   // them there), so they need not stay in registers across the force loop.
   const double* qa = Qs + (size_t)(base + u) * kS * D;
   if constexpr (KIND == kGravity) {
-    // One stage at a time, sources b ascending: only the stage's own position
-    // and accumulator stay live across the source loop.
+    // Sources b ascending; the 8 stages of a source are 8 independent chains
+    // (instruction-level parallelism); each stage's sum keeps the b order.
     const double eps2 = M.eps2;
+    double acc[D][kS] = {};
+    for (int b = 0; b < n; ++b) {
+      if (b == u) continue;
+      const double* qb = Qs + (size_t)(base + b) * kS * D;
+      const double mb = Ms[base + b];
 #pragma unroll
-    for (int s = 0; s < kS; ++s) {
-      double acc[D];
-#pragma unroll
-      for (int d = 0; d < D; ++d) acc[d] = 0.0;
-      for (int b = 0; b < n; ++b) {
-        if (b == u) continue;
-        const double* qb = Qs + (size_t)(base + b) * kS * D + s * D;
-        const double mb = Ms[base + b];
+      for (int s = 0; s < kS; ++s) {
         double dx[D];
 #pragma unroll
-        for (int d = 0; d < D; ++d) dx[d] = qb[d] - qa[s * D + d];
+        for (int d = 0; d < D; ++d) dx[d] = qb[s * D + d] - qa[s * D + d];
         if constexpr (EXACT) {
           double r2 = 0.0;
 #pragma unroll
@@ -58,23 +56,26 @@ __device__ __forceinline__ void unit_increments(const double* __restrict__ Qs,
           r2 = r2 + eps2;
           const double w = pair_weight<true>(r2, mb);
 #pragma unroll
-          for (int d = 0; d < D; ++d) acc[d] = acc[d] + w * dx[d];
+          for (int d = 0; d < D; ++d) acc[d][s] = acc[d][s] + w * dx[d];
         } else {
           double r2 = dx[0] * dx[0];
 #pragma unroll
           for (int d = 1; d < D; ++d) r2 = fma(dx[d], dx[d], r2);
           const double w = mb * rinv3(r2 + eps2);
 #pragma unroll
-          for (int d = 0; d < D; ++d) acc[d] = fma(w, dx[d], acc[d]);
+          for (int d = 0; d < D; ++d) acc[d][s] = fma(w, dx[d], acc[d][s]);
         }
       }
+    }
+#pragma unroll
+    for (int s = 0; s < kS; ++s) {
       const double hb = h * T[kTabB + s];
 #pragma unroll
       for (int d = 0; d < D; ++d) {
         if constexpr (EXACT)
-          R[d][s] = hb * (M.G * acc[d]);
+          R[d][s] = hb * (M.G * acc[d][s]);
         else
-          R[d][s] = (hb * M.G) * acc[d];
+          R[d][s] = (hb * M.G) * acc[d][s];
       }
     }
   } else {  // chain, D == 1: F = k_r V'(q_{i+1} - q_i) - k_l V'(q_i - q_{i-1})
