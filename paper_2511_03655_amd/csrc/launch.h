@@ -23,17 +23,46 @@ size_t large_scratch_bytes(int n, int nchunks);
 int large_chunks(int n, bool exact, int num_cus);
 hipError_t launch_large(const LaunchArgs& a, int inst, int n, void* scratch, int nchunks,
                         int num_cus, hipStream_t st);
+bool stage_class_supported(int kind, int n, int d);
+int stage_np(int n);
+hipError_t launch_stage_class(int d, int np, const LaunchArgs& a, int n_items, int num_cus,
+                              hipStream_t st);
 
-// Kernel class of a problem: 0 small-system kernel, 1 workgroup kernel,
-// 2 whole-GPU kernel, -1 unsupported.  S: slot width for class 1.
-inline int kernel_class(int kind, int n, int d, int* S) {
-  *S = 0;
-  if (small_class_supported(kind, n, d)) return 0;
-  if (wg_class_supported(kind, n, d)) {
-    *S = wg_slot_size(n);
-    return 1;
+// Kernel classes.
+constexpr int kClassSmall = 0;  // several systems per wavefront (few bodies)
+constexpr int kClassWg = 1;     // one lane per body or site, systems in workgroup slots
+constexpr int kClassLarge = 2;  // one system on the whole GPU (cooperative launch)
+constexpr int kClassStage = 3;  // one lane per (body, stage), one system per workgroup
+
+// Kernel class of a problem, or -1 if unsupported.  *size: the class's size
+// parameter (bodies for the small kernel, slot width for the workgroup kernel,
+// padded body count for the stage-parallel kernel).
+inline int kernel_class(int kind, int n, int d, int* size) {
+  *size = 0;
+  if (small_class_supported(kind, n, d)) {
+    *size = n;
+    return kClassSmall;
   }
-  if (large_class_supported(kind, n, d)) return 2;
+  if (stage_class_supported(kind, n, d)) {
+    *size = stage_np(n);
+    return kClassStage;
+  }
+  if (wg_class_supported(kind, n, d)) {
+    *size = wg_slot_size(n);
+    return kClassWg;
+  }
+  if (large_class_supported(kind, n, d)) return kClassLarge;
   return -1;
+}
+
+// Launches the persistent kernel of a batched class over the queue in `a`.
+inline hipError_t launch_batched(int cls, int kind, int size, int d, const LaunchArgs& a,
+                                 int n_items, int num_cus, hipStream_t st) {
+  switch (cls) {
+    case kClassSmall: return launch_small_class(kind, size, d, a, n_items, num_cus, st);
+    case kClassWg: return launch_wg_class(kind, d, size, a, n_items, num_cus, st);
+    case kClassStage: return launch_stage_class(d, size, a, n_items, num_cus, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 }  // namespace irk

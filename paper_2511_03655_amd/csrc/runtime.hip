@@ -26,13 +26,18 @@
 namespace {
 
 struct KernelClass {
-  int kind, nb, d;
-  int S = 0;  // slot width of the workgroup-tile kernel
-  bool small;
-  bool large = false;  // one whole-GPU cooperative launch per instance
+  int cls = -1;   // irk::kClass*
+  int kind = 0, size = 0, d = 0;  // size: see irk::kernel_class
   std::vector<int32_t> ids;
   int64_t queue_off = 0;
 };
+
+// Work of one step of an instance, up to a constant factor (orders a class's
+// queue so that the longest integrations start first).
+double step_work(const irk::InstDesc& d) {
+  const double n = d.n;
+  return d.kind == IRKGL16_GRAVITY ? n * n * d.d : n * d.d;
+}
 
 struct DevBuf {
   void* p = nullptr;
@@ -104,6 +109,12 @@ struct irkgl16_ctx {
   DevBuf d_q0, d_p0, d_qout, d_pout, d_iters, d_large;
   int large_nmax = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // concurrent class launches: fork event on `stream`, one stream + join event per class slot
+  static constexpr int kMaxAux = 4;
+  std::vector<hipStream_t> aux;
+  std::vector<hipEvent_t> aux_done;
+  hipEvent_t ev_fork = nullptr;
+  std::vector<int32_t> h_queue;
 
   // last call
   bool have_last = false;
@@ -116,6 +127,9 @@ struct irkgl16_ctx {
   ~irkgl16_ctx() {
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
+    for (hipEvent_t e : aux_done) (void)hipEventDestroy(e);
+    for (hipStream_t sk : aux) (void)hipStreamDestroy(sk);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
 };
@@ -206,41 +220,32 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
     d.state_off = state_off;
     state_off += (int64_t)(4 + irk::kS) * dqi;
     // kernel class
-    const bool small = irk::small_class_supported(p.kind, p.n, p.d);
-    const bool wg = !small && irk::wg_class_supported(p.kind, p.n, p.d);
-    const bool large = !small && !wg && irk::large_class_supported(p.kind, p.n, p.d);
-    if (!small && !wg && !large) return fail(IRKGL16_EINVAL);
-    if (large) c->large_nmax = std::max(c->large_nmax, (int)p.n);
-    const int slot_w = wg ? irk::wg_slot_size(p.n) : 0;
-    auto key = small ? std::make_tuple(1, p.kind, p.n, p.d)
-                     : (wg ? std::make_tuple(0, p.kind, slot_w, p.d) : std::make_tuple(2, p.kind, 0, p.d));
+    int size = 0;
+    const int cl = irk::kernel_class(p.kind, p.n, p.d, &size);
+    if (cl < 0) return fail(IRKGL16_EINVAL);
+    if (cl == irk::kClassLarge) c->large_nmax = std::max(c->large_nmax, (int)p.n);
+    auto key = std::make_tuple(cl, (int)p.kind, size, (int)p.d);
     auto it = cls_index.find(key);
     int ci;
     if (it == cls_index.end()) {
       ci = (int)c->classes.size();
       cls_index[key] = ci;
       KernelClass kc;
+      kc.cls = cl;
       kc.kind = p.kind;
-      kc.nb = small ? p.n : 0;
+      kc.size = size;
       kc.d = p.d;
-      kc.S = slot_w;
-      kc.small = small;
-      kc.large = large;
       c->classes.push_back(kc);
     } else {
       ci = it->second;
     }
     c->classes[ci].ids.push_back(i);
   }
-  // Generic classes process larger systems first (longest-processing-time order).
-  for (auto& kc : c->classes)
-    if (!kc.small)
-      std::stable_sort(kc.ids.begin(), kc.ids.end(),
-                       [&](int32_t x, int32_t y) { return c->dq[x] > c->dq[y]; });
-  std::vector<int32_t> queue;
+  // Queue storage (filled per call, in longest-integration-first order).
+  size_t queue_len = 0;
   for (auto& kc : c->classes) {
-    kc.queue_off = (int64_t)queue.size();
-    queue.insert(queue.end(), kc.ids.begin(), kc.ids.end());
+    kc.queue_off = (int64_t)queue_len;
+    queue_len += kc.ids.size();
   }
   std::vector<int32_t> plainq(n_inst);
   for (int32_t i = 0; i < n_inst; ++i) plainq[i] = i;
@@ -262,7 +267,7 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
       (rc = alloc_try(c->d_stat, sizeof(irk::InstStat) * (size_t)std::max(n_inst, 1))) ||
       (rc = alloc_try(c->d_state, sizeof(double) * (size_t)std::max<int64_t>(state_off, 1))) ||
       (rc = alloc_try(c->d_params, sizeof(double) * std::max<size_t>(params.size(), 1))) ||
-      (rc = alloc_try(c->d_queue, sizeof(int32_t) * std::max<size_t>(queue.size(), 1))) ||
+      (rc = alloc_try(c->d_queue, sizeof(int32_t) * std::max<size_t>(queue_len, 1))) ||
       (rc = alloc_try(c->d_plainq, sizeof(int32_t) * std::max<size_t>(plainq.size(), 1))) ||
       (rc = alloc_try(c->d_heads, sizeof(int32_t) * std::max<size_t>(c->classes.size(), 1))))
     return fail(rc);
@@ -287,11 +292,21 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
       hipMemcpy(c->d_params.p, params.data(), sizeof(double) * params.size(),
                 hipMemcpyHostToDevice) != hipSuccess)
     return fail(IRKGL16_EDEVICE);
-  if (!queue.empty() &&
-      (hipMemcpy(c->d_queue.p, queue.data(), sizeof(int32_t) * queue.size(),
-                 hipMemcpyHostToDevice) != hipSuccess ||
-       hipMemcpy(c->d_plainq.p, plainq.data(), sizeof(int32_t) * plainq.size(),
-                 hipMemcpyHostToDevice) != hipSuccess))
+  if (!plainq.empty() &&
+      hipMemcpy(c->d_plainq.p, plainq.data(), sizeof(int32_t) * plainq.size(),
+                hipMemcpyHostToDevice) != hipSuccess)
+    return fail(IRKGL16_EDEVICE);
+  // Auxiliary streams: the classes' persistent kernels run concurrently.
+  const int n_aux = std::min<int>((int)c->classes.size(), irkgl16_ctx::kMaxAux);
+  for (int k = 0; k < n_aux; ++k) {
+    hipStream_t sk;
+    hipEvent_t ek;
+    if (hipStreamCreateWithFlags(&sk, hipStreamNonBlocking) != hipSuccess) return fail(IRKGL16_EDEVICE);
+    c->aux.push_back(sk);
+    if (hipEventCreateWithFlags(&ek, hipEventDisableTiming) != hipSuccess) return fail(IRKGL16_EDEVICE);
+    c->aux_done.push_back(ek);
+  }
+  if (hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess)
     return fail(IRKGL16_EDEVICE);
   *out = c;
   return IRKGL16_OK;
@@ -317,9 +332,8 @@ static irk::LaunchArgs base_args(irkgl16_ctx* c, double* qout, double* pout) {
 }
 
 static hipError_t launch_class(irkgl16_ctx* c, const KernelClass& kc, const irk::LaunchArgs& a,
-                               int n_items) {
-  if (kc.small) return irk::launch_small_class(kc.kind, kc.nb, kc.d, a, n_items, c->num_cus, c->stream);
-  if (kc.large) {
+                               int n_items, hipStream_t st) {
+  if (kc.cls == irk::kClassLarge) {
     // One cooperative whole-GPU launch per instance, in queue order.
     std::vector<int32_t> ids;
     if (a.queue_head)
@@ -329,12 +343,12 @@ static hipError_t launch_class(irkgl16_ctx* c, const KernelClass& kc, const irk:
     for (int32_t id : ids) {
       const int n = c->desc[id].n;
       const int ch = irk::large_chunks(n, a.exact != 0, c->num_cus);
-      hipError_t e = irk::launch_large(a, id, n, c->d_large.p, ch, c->num_cus, c->stream);
+      hipError_t e = irk::launch_large(a, id, n, c->d_large.p, ch, c->num_cus, st);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
   }
-  return irk::launch_wg_class(kc.kind, kc.d, kc.S, a, n_items, c->num_cus, c->stream);
+  return irk::launch_batched(kc.cls, kc.kind, kc.size, kc.d, a, n_items, c->num_cus, st);
 }
 
 static int integrate_impl(irkgl16_ctx* c, const double* q0, const double* p0, const double* h,
@@ -379,6 +393,17 @@ static int integrate_impl(irkgl16_ctx* c, const double* q0, const double* p0, co
   c->last_synced = false;
   if (n == 0) return IRKGL16_OK;
 
+  // Class queues, longest integrations first (estimated work nsteps x step cost).
+  c->h_queue.resize(n);
+  for (auto& kc : c->classes) {
+    std::vector<int32_t> ids = kc.ids;
+    std::stable_sort(ids.begin(), ids.end(), [&](int32_t x, int32_t y) {
+      return (double)nsteps[x] * step_work(c->desc[x]) > (double)nsteps[y] * step_work(c->desc[y]);
+    });
+    std::copy(ids.begin(), ids.end(), c->h_queue.begin() + kc.queue_off);
+  }
+  HIP_TRY(hipMemcpyAsync(c->d_queue.p, c->h_queue.data(), sizeof(int32_t) * n,
+                         hipMemcpyHostToDevice, c->stream));
   HIP_TRY(hipMemcpyAsync(c->d_desc.p, c->desc.data(), sizeof(irk::InstDesc) * n,
                          hipMemcpyHostToDevice, c->stream));
   if (!dev) {
@@ -402,17 +427,41 @@ static int integrate_impl(irkgl16_ctx* c, const double* q0, const double* p0, co
         pa.queue_len = 1;
         pa.queue_head = nullptr;
         pa.step_budget = 1;
-        for (int64_t s = 0; s < nsteps[id]; ++s) HIP_TRY(launch_class(c, kc, pa, 1));
+        for (int64_t s = 0; s < nsteps[id]; ++s) HIP_TRY(launch_class(c, kc, pa, 1, c->stream));
       }
     }
   } else {
+    // The whole-GPU class (cooperative launches) runs alone on the main
+    // stream after the others; the batched classes run concurrently, one
+    // auxiliary stream per class (round robin), joined back into the stream.
+    HIP_TRY(hipEventRecord(c->ev_fork, c->stream));
+    std::vector<char> used(c->aux.size(), 0);
+    int slot = 0;
     for (size_t k = 0; k < c->classes.size(); ++k) {
       const auto& kc = c->classes[k];
+      if (kc.cls == irk::kClassLarge) continue;
       irk::LaunchArgs ca = a;
       ca.queue = c->d_queue.as<int32_t>() + kc.queue_off;
       ca.queue_len = (int32_t)kc.ids.size();
       ca.queue_head = c->d_heads.as<int32_t>() + k;
-      HIP_TRY(launch_class(c, kc, ca, (int)kc.ids.size()));
+      const int j = slot++ % (int)c->aux.size();
+      if (!used[j]) HIP_TRY(hipStreamWaitEvent(c->aux[j], c->ev_fork, 0));
+      used[j] = 1;
+      HIP_TRY(launch_class(c, kc, ca, (int)kc.ids.size(), c->aux[j]));
+    }
+    for (size_t j = 0; j < c->aux.size(); ++j) {
+      if (!used[j]) continue;
+      HIP_TRY(hipEventRecord(c->aux_done[j], c->aux[j]));
+      HIP_TRY(hipStreamWaitEvent(c->stream, c->aux_done[j], 0));
+    }
+    for (size_t k = 0; k < c->classes.size(); ++k) {
+      const auto& kc = c->classes[k];
+      if (kc.cls != irk::kClassLarge) continue;
+      irk::LaunchArgs ca = a;
+      ca.queue = c->d_queue.as<int32_t>() + kc.queue_off;
+      ca.queue_len = (int32_t)kc.ids.size();
+      ca.queue_head = c->d_heads.as<int32_t>() + k;
+      HIP_TRY(launch_class(c, kc, ca, (int)kc.ids.size(), c->stream));
     }
   }
   HIP_TRY(hipEventRecord(c->ev1, c->stream));

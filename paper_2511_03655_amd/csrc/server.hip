@@ -127,6 +127,11 @@ struct irkgl16_server {
   int device = 0, num_cus = 1;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // concurrent class launches within a slice (fork on `stream`, join back)
+  static constexpr int kMaxAux = 4;
+  std::vector<hipStream_t> aux;
+  std::vector<hipEvent_t> aux_done;
+  hipEvent_t ev_fork = nullptr;
   std::chrono::steady_clock::time_point t0;
 
   DevBuf d_tab, d_desc, d_stat, d_arena, d_in, d_stage_q, d_stage_p, d_queue, d_heads, d_ids,
@@ -150,6 +155,9 @@ struct irkgl16_server {
   std::vector<double> h_stage_q, h_stage_p;
 
   ~irkgl16_server() {
+    for (hipEvent_t e : aux_done) (void)hipEventDestroy(e);
+    for (hipStream_t sk : aux) (void)hipStreamDestroy(sk);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
   void run();
@@ -218,9 +226,18 @@ int irkgl16_server::slice(std::vector<Request*>& live, std::vector<Request*>& fr
   // class queues
   std::map<std::tuple<int, int, int, int>, std::vector<int32_t>> classes;
   for (Request* r : live) {
-    auto key = std::make_tuple(r->cls, r->kind, r->cls == 0 ? r->n : r->S, r->d);
+    auto key = std::make_tuple(r->cls, r->kind, r->S, r->d);
     classes[key].push_back(r->slot);
   }
+  // longest remaining integration first within each class
+  for (auto& kv : classes)
+    std::stable_sort(kv.second.begin(), kv.second.end(), [&](int32_t x, int32_t y) {
+      const Request* rx = resident[x];
+      const Request* ry = resident[y];
+      const double wx = (double)(rx->nsteps - rx->steps_done) * rx->n * rx->n;
+      const double wy = (double)(ry->nsteps - ry->steps_done) * ry->n * ry->n;
+      return wx > wy;
+    });
   std::vector<int32_t> queue;
   std::vector<std::pair<std::tuple<int, int, int, int>, std::pair<int64_t, int>>> cls_list;
   for (auto& kv : classes) {
@@ -265,18 +282,36 @@ int irkgl16_server::slice(std::vector<Request*>& live, std::vector<Request*>& fr
   a.max_iter = opt.max_iter;
   a.step_budget = slice_steps;
   a.exact = (opt.flags & IRKGL16_REPRODUCIBLE) ? 1 : 0;
+  // batched classes concurrently on the auxiliary streams, then the
+  // whole-GPU (cooperative) class alone on the slice stream
+  SRV_TRY(hipEventRecord(ev_fork, st));
+  std::vector<char> used(aux.size(), 0);
+  int aux_next = 0;
   for (size_t k = 0; k < cls_list.size(); ++k) {
     const auto& key = cls_list[k].first;
     const int cls = std::get<0>(key), kind = std::get<1>(key), sz = std::get<2>(key),
               d = std::get<3>(key);
+    if (cls == irk::kClassLarge) continue;
     a.queue = d_queue.as<int32_t>() + cls_list[k].second.first;
     a.queue_len = cls_list[k].second.second;
     a.queue_head = d_heads.as<int32_t>() + k;
-    if (cls == 0) {
-      SRV_TRY(irk::launch_small_class(kind, sz, d, a, a.queue_len, num_cus, st));
-    } else if (cls == 1) {
-      SRV_TRY(irk::launch_wg_class(kind, d, sz, a, a.queue_len, num_cus, st));
-    } else {
+    const int j = aux_next++ % (int)aux.size();
+    if (!used[j]) SRV_TRY(hipStreamWaitEvent(aux[j], ev_fork, 0));
+    used[j] = 1;
+    SRV_TRY(irk::launch_batched(cls, kind, sz, d, a, a.queue_len, num_cus, aux[j]));
+  }
+  for (size_t j = 0; j < aux.size(); ++j) {
+    if (!used[j]) continue;
+    SRV_TRY(hipEventRecord(aux_done[j], aux[j]));
+    SRV_TRY(hipStreamWaitEvent(st, aux_done[j], 0));
+  }
+  for (size_t k = 0; k < cls_list.size(); ++k) {
+    const int cls = std::get<0>(cls_list[k].first);
+    if (cls != irk::kClassLarge) continue;
+    a.queue = d_queue.as<int32_t>() + cls_list[k].second.first;
+    a.queue_len = cls_list[k].second.second;
+    a.queue_head = d_heads.as<int32_t>() + k;
+    {
       for (int i = 0; i < a.queue_len; ++i) {
         const int slot = queue[cls_list[k].second.first + i];
         Request* r = resident[slot];
@@ -365,7 +400,7 @@ void irkgl16_server::run() {
         d.mass_off = r->mass.empty() ? -1 : po;
         po += (int64_t)r->mass.size();
         d.coupling_off = r->coupling.empty() ? -1 : po;
-        if (r->cls == 2 && r->n > large_nmax) {
+        if (r->cls == irk::kClassLarge && r->n > large_nmax) {
           if (d_large.ensure(irk::large_scratch_bytes(r->n, 16))) {
             device_error = IRKGL16_EDEVICE;
           }
@@ -462,6 +497,16 @@ int irkgl16_server_create(irkgl16_server** out, const irkgl16_server_options* op
       if (hipStreamCreate(&s->stream) != hipSuccess) return IRKGL16_EDEVICE;
       s->own_stream = true;
     }
+    for (int k = 0; k < irkgl16_server::kMaxAux; ++k) {
+      hipStream_t sk;
+      hipEvent_t ek;
+      if (hipStreamCreateWithFlags(&sk, hipStreamNonBlocking) != hipSuccess) return IRKGL16_EDEVICE;
+      s->aux.push_back(sk);
+      if (hipEventCreateWithFlags(&ek, hipEventDisableTiming) != hipSuccess) return IRKGL16_EDEVICE;
+      s->aux_done.push_back(ek);
+    }
+    if (hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming) != hipSuccess)
+      return IRKGL16_EDEVICE;
     irkgl16_server* raw = s.release();
     raw->worker = std::thread([raw] { raw->run(); });
     *out = raw;

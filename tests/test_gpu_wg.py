@@ -63,18 +63,27 @@ def test_fast_within_tolerance(orc, name, inst, nsteps):
     # 1-ulp perturbations of every initial coordinate (chaos amplifies it)
     rng = np.random.default_rng(1)
     sens_q = sens_p = 0.0
+    dks = []
     for _ in range(2):
         q0 = inst["q"] + rng.choice([-1.0, 1.0], inst["q"].size) * np.spacing(np.abs(inst["q"]))
         p0 = inst["p"] + rng.choice([-1.0, 1.0], inst["p"].size) * np.spacing(np.abs(inst["p"]))
-        rp = orc.integrate(spec(orc, inst), q0, p0, inst["h"], nsteps, nsteps)
+        rp = orc.integrate(spec(orc, inst), q0, p0, inst["h"], nsteps, nsteps, want_iters=True)
         sens_q = max(sens_q, relmax(rp["q"][1], r["q"][1]))
         sens_p = max(sens_p, relmax(rp["p"][1], r["p"][1]))
+        dks.append(np.abs(rp["iters"].astype(int) - r["iters"]))
     assert relmax(q[1], r["q"][1]) <= max(1e-12, 30 * sens_q), (name, sens_q)
     assert relmax(p[1], r["p"][1]) <= max(1e-12, 30 * sens_p), (name, sens_p)
+    # Iteration counts: within +-1 on at least 99% of the steps, unless the
+    # oracle's own counts move further under the 1-ulp perturbations (the
+    # stopping rule compares increments at rounding level); then no worse than
+    # that.
     dk = np.abs(st["step_iters"].astype(int) - r["iters"])
-    if max(sens_q, sens_p) > 1e-13:
-        dk = dk[:20]  # chaotic: compare counts only before the trajectories separate
-    assert np.mean(dk <= 1) >= 0.99 and dk.max() <= 3
+    cut = 20 if max(sens_q, sens_p) > 1e-13 else len(dk)  # chaotic: before separation
+    dk = dk[:cut]
+    own_frac = min(float(np.mean(d[:cut] <= 1)) for d in dks)
+    own_max = max(int(d[:cut].max()) for d in dks)
+    assert np.mean(dk <= 1) >= min(0.99, own_frac), (name, own_frac)
+    assert dk.max() <= max(3, own_max), (name, own_max)
 
 
 def test_mixed_batch_equals_alone(orc):
