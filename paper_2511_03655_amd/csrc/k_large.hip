@@ -1,77 +1,269 @@
-// IRKGL16 for one large gravitational system (N > 512 bodies, e.g. a 2048-body
-// Plummer cluster): the whole GPU works on one system.
+// IRKGL16 for one large gravitational system (more than 512 bodies, up to
+// 8192, e.g. a 2048-body Plummer cluster): the whole GPU works on one system.
 //
-// One cooperative persistent launch per integration call.  Workgroups are
-// (stage s, block of 256 targets, source chunk c).  Per fixed-point iteration:
-//  * force: each workgroup stages its chunk of source positions at stage s in
-//    LDS and accumulates, for its 256 targets, sum_b m_b (q_b - q_a) r^-3 over
-//    the chunk (sources ascending); partial sums go to HBM;
-//  * update: the last workgroup to finish a target block (atomic arrival
-//    counter with release/acquire fences) sums the chunk partials in chunk order,
-//    forms R_i = h b_i G g_i, the new stage values (eq. IRK_FP2), the per
-//    component max-norm increment and the stopping rule (eqs. Delta_n,
-//    stopping) for that block, and raises a global "not converged" flag;
-//  * one grid barrier, then every workgroup reads the flag.
-// Stage positions are double-buffered by iteration parity (a block may be
-// updated while other blocks still read the previous positions); flags rotate
-// over three slots so that a reset never races a reader.  After convergence the
-// component lanes perform the compensated update (eq. qnvn2), outputs and the
-// next initial guess (eq. IRK_init2); one more grid barrier ends the step.
-// With EXACT (reproducible mode) a single chunk is used, so every sum runs in
+// One cooperative persistent launch per integration call.  The bodies are cut
+// into groups of 8 targets; workgroup w owns groups w*gpw .. w*gpw+gpw-1 and
+// wavefront g of the workgroup is the state wavefront of group g: lane
+// (t, s) = 8 t + s stands for target t at stage s.  Per fixed-point iteration:
+//  * force: for each owned group, the NCH wavefronts of the workgroup split the
+//    sources into NCH interleaved chunks (b = c mod NCH, ascending within a
+//    chunk); source stage positions are staged tile by tile in LDS, split into
+//    (x, y) and (z, m) arrays [b][stage] so that the 8 stage entries a
+//    wavefront reads at once are 128 contiguous bytes; chunk partial sums are
+//    reduced in chunk order through LDS;
+//  * update (state wavefront): R_s = h b_s G g_s, stage values
+//    Q_s = q + h (c_s v + sum_j eta_sj R_j) (eq. IRK_FP2) with the body's R_j
+//    exchanged inside the wavefront, max-norm increments per component
+//    (eq. Delta_n) by butterfly over the stage lanes, stopping rule
+//    (eq. stopping); "not converged" / "non-finite" are OR-ed into a global
+//    flag word.  The new stage positions go to the next position buffer, and
+//    the next step's initial guess (eq. IRK_init2), formed after a tentative
+//    compensated update (eq. qnvn2), to a third buffer;
+//  * one grid barrier, whose last arriver publishes the flag word with the
+//    release; every workgroup then either iterates again from the new stage
+//    positions or commits the tentative update and starts the next step from
+//    the guess buffer, so a step costs exactly k grid barriers.
+// The per-target state (q, v as two-double values, the stopping-rule history)
+// lives in LDS, so the force loop runs without register spills.  Three
+// position buffers rotate so that no buffer is written while it is read.
+// With EXACT (reproducible mode) a single chunk is used and every sum runs in
 // the reference order.
-#include <hip/hip_cooperative_groups.h>
-
 #include "device_common.h"
-
-namespace cg = cooperative_groups;
 
 namespace irk {
 
+constexpr int kLgT = 8;  // targets per group
+constexpr int kLgMaxBodies = 8192;
+constexpr int kBarSub = 16;  // first-level barrier counters
+
 struct LargeArgs {
   LaunchArgs a;
-  int32_t inst;       // instance id
-  int32_t n;          // bodies
-  int32_t nchunks;    // source chunks
-  int32_t ntb;        // target blocks of 256
-  double* pos;        // [2][8][n][3]
-  double* part;       // [nchunks][8][n][3]
-  double* rbuf;       // [3n][8]   increments R of the last iteration
-  double* hist;       // [3n][2]   mind, prev
-  int32_t* arrive;    // [ntb]     arrival counters
-  int32_t* flags;     // [3][2]    notok, bad by iteration % 3
-  int64_t* ctl;       // [4]       scratch for the final statistics
+  int32_t inst;     // instance id
+  int32_t n;        // bodies
+  int32_t ngroups;  // ceil(n / 8)
+  int32_t gpw;      // groups per workgroup
+  double* pos;      // [3][n][8] x (x, y, z, m)
+  // barrier control words (see grid_barrier); the release word carries the
+  // generation << 2 | flags (bit 0 not converged, bit 1 non-finite)
+  unsigned* ctl;
 };
 
-constexpr int kLargeBlock = 256;
-constexpr int kLargeTile = 1024;  // sources staged in LDS at a time
+template <int NCH>
+struct LargeCfg {
+  static constexpr int kThreads = 64 * NCH;
+  static constexpr int kTile = NCH > 1 ? 256 : 64;    // sources per LDS tile
+  static constexpr int kMaxGroups = NCH > 1 ? 4 : 1;  // groups per workgroup
+};
+
+// Control words, one 128-byte line each: kBarSub first-level arrival
+// counters, the top counter, the release word.
+constexpr int kLine = 32;  // unsigned words per line
+constexpr int kCtlWords = (kBarSub + 2) * kLine;
+// Arrival increment: count in bits 0..15, "not converged" contributions in
+// bits 16..23, "non-finite" contributions in bits 24..31 (at most 16
+// arrivals per counter, so the fields never overflow).
+__device__ __forceinline__ unsigned arrival_word(unsigned flags) {
+  return 1u | ((flags & 1u) << 16) | ((flags & 2u) << 23);
+}
+__device__ __forceinline__ unsigned arrival_flags(unsigned total) {
+  return ((total >> 16) & 0xFFu ? 1u : 0u) | ((total >> 24) ? 2u : 0u);
+}
+
+// Grid-wide barrier over co-resident workgroups (cooperative launch), two
+// levels of arrival counters (16 first-level counters, then one top counter)
+// so that no counter takes more than 16 arrivals, each counter on its own
+// cache line.  A workgroup's flags (`*blk_flags`, OR-ed in LDS by its state
+// wavefronts) ride on its arrival increment; the last arriver publishes the
+// OR over all workgroups with the new generation in the release word, and the
+// barrier returns it (through the LDS word `*res`, which no thread writes
+// again before the next barrier).  `gen` counts this workgroup's barriers (identical in all
+// threads).  Ordering: each arrival is preceded by a release fence; a
+// workgroup that completes a counter acquires before resetting it and
+// releases before passing on; waiters poll with plain atomic loads (no cache
+// invalidation per poll) and acquire once.
+__device__ __forceinline__ unsigned grid_barrier(unsigned* ctl, unsigned& gen, unsigned nblocks,
+                                                 const unsigned* blk_flags, unsigned* res) {
+  constexpr unsigned kMask = 0x3FFFFFFFu;
+  unsigned* top = ctl + kBarSub * kLine;
+  unsigned* rel = ctl + (kBarSub + 1) * kLine;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned j = blockIdx.x % kBarSub;
+    const unsigned nsub = nblocks < (unsigned)kBarSub ? nblocks : (unsigned)kBarSub;
+    const unsigned members = nblocks / kBarSub + (j < nblocks % kBarSub ? 1u : 0u);
+    const unsigned mine = arrival_word(*blk_flags);
+    unsigned* sub = ctl + j * kLine;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned old = __hip_atomic_fetch_add(sub, mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((old & 0xFFFFu) == members - 1) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __hip_atomic_store(sub, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned up = arrival_word(arrival_flags(old + mine));
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      const unsigned old2 = __hip_atomic_fetch_add(top, up, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if ((old2 & 0xFFFFu) == nsub - 1) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned f = arrival_flags(old2 + up);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(rel, (((gen + 1) & kMask) << 2) | f, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    unsigned v;
+    while (((v = __hip_atomic_load(rel, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >> 2) ==
+           (gen & kMask))
+      __builtin_amdgcn_s_sleep(1);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *res = v & 3u;
+  }
+  ++gen;
+  __syncthreads();
+  return *res;
+}
+
+// NaN-keeping maximum over the 8 stage lanes of a target.
+__device__ __forceinline__ double lg_group_max(double x) {
+#pragma unroll
+  for (int m = 1; m < kS; m <<= 1) x = max_keep_nan(x, __shfl_xor(x, m, kS));
+  return x;
+}
+
+__device__ __forceinline__ void lg_wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Own stage s of the initial guess (eq. IRK_init2) from increments Rp.
+template <bool EXACT>
+__device__ __forceinline__ double lg_guess(ConstTab T, int s, double q, double v,
+                                           const double (&Rp)[kS], double h) {
+  double L0[kS];
+#pragma unroll
+  for (int j = 0; j < kS; ++j) {
+    const ConstTab r = row_tab(T);
+    const double hb = h * r[kTabB + j];
+    L0[j] = hb * (v + row_dot<EXACT>(r, kTabNu + j * kS, Rp));
+  }
+  return q + row_dot<EXACT>(T, kTabMu + s * kS, L0);
+}
+
+// Weight m (r2 + eps2)^(-3/2) of one source (eps2 already in r2).
+template <bool EXACT>
+__device__ __forceinline__ double lg_weight(double r2, double m) {
+  return pair_weight<EXACT>(r2, m);
+}
+
+// Squared distance in the reference order (EXACT) or with fused products.
+template <bool EXACT>
+__device__ __forceinline__ double lg_r2(double dx, double dy, double dz, double eps2) {
+  if constexpr (EXACT) {
+    double r2 = 0.0;
+    r2 = r2 + dx * dx;
+    r2 = r2 + dy * dy;
+    r2 = r2 + dz * dz;
+    return r2 + eps2;
+  } else {
+    return fma(dz, dz, fma(dy, dy, dx * dx)) + eps2;
+  }
+}
 
 template <bool EXACT>
-__global__ __launch_bounds__(kLargeBlock) void large_kernel(LargeArgs L) {
-  cg::grid_group grid = cg::this_grid();
+__device__ __forceinline__ void lg_acc(double w, double dx, double dy, double dz, double& acc0,
+                                       double& acc1, double& acc2) {
+  if constexpr (EXACT) {
+    acc0 = acc0 + w * dx;
+    acc1 = acc1 + w * dy;
+    acc2 = acc2 + w * dz;
+  } else {
+    acc0 = fma(w, dx, acc0);
+    acc1 = fma(w, dy, acc1);
+    acc2 = fma(w, dz, acc2);
+  }
+}
+
+// Accumulates the stage-s force on target `tgt` from the sources of one LDS
+// tile that belong to chunk `c` (local indices c, c + NCH, ...), in ascending
+// order.  Two sources are evaluated as independent chains per loop trip (their
+// contributions are still added in source order).  SEL: replace the self
+// distance (unsoftened forces); the self term then contributes w * 0 = 0.
+template <bool EXACT, int NCH, bool SEL>
+__device__ __forceinline__ void lg_force_tile(const double2* __restrict__ sxy,
+                                              const double2* __restrict__ szm, int c, int nb,
+                                              int s, int b0, int tgt, double qx, double qy,
+                                              double qz, double eps2, double& acc0, double& acc1,
+                                              double& acc2) {
+  int bl = c;
+  for (; bl + NCH < nb; bl += 2 * NCH) {
+    const double2 xa = sxy[bl * kS + s], za = szm[bl * kS + s];
+    const double2 xb = sxy[(bl + NCH) * kS + s], zb = szm[(bl + NCH) * kS + s];
+    const double dxa = xa.x - qx, dya = xa.y - qy, dza = za.x - qz;
+    const double dxb = xb.x - qx, dyb = xb.y - qy, dzb = zb.x - qz;
+    double r2a = lg_r2<EXACT>(dxa, dya, dza, eps2);
+    double r2b = lg_r2<EXACT>(dxb, dyb, dzb, eps2);
+    if constexpr (SEL) {
+      r2a = (b0 + bl == tgt) ? 1.0 : r2a;
+      r2b = (b0 + bl + NCH == tgt) ? 1.0 : r2b;
+    }
+    const double wa = lg_weight<EXACT>(r2a, za.y);
+    const double wb = lg_weight<EXACT>(r2b, zb.y);
+    lg_acc<EXACT>(wa, dxa, dya, dza, acc0, acc1, acc2);
+    lg_acc<EXACT>(wb, dxb, dyb, dzb, acc0, acc1, acc2);
+  }
+  if (bl < nb) {
+    const double2 xa = sxy[bl * kS + s], za = szm[bl * kS + s];
+    const double dxa = xa.x - qx, dya = xa.y - qy, dza = za.x - qz;
+    double r2a = lg_r2<EXACT>(dxa, dya, dza, eps2);
+    if constexpr (SEL) r2a = (b0 + bl == tgt) ? 1.0 : r2a;
+    lg_acc<EXACT>(lg_weight<EXACT>(r2a, za.y), dxa, dya, dza, acc0, acc1, acc2);
+  }
+}
+
+// Per-target state of a group in LDS (identical for the 8 stage lanes of a
+// target, so stored once per target and component).
+struct LgTargetState {
+  double qh[kLgT][3], ql[kLgT][3], vh[kLgT][3], vl[kLgT][3];
+  double mind[kLgT][3], prv[kLgT][3];  // stopping-rule history
+};
+
+template <bool EXACT, int NCH>
+__global__ __launch_bounds__(LargeCfg<NCH>::kThreads) void large_kernel(LargeArgs L) {
+  constexpr int TB = LargeCfg<NCH>::kTile;
+  constexpr int NT = LargeCfg<NCH>::kThreads;
+  constexpr int GM = LargeCfg<NCH>::kMaxGroups;
+  constexpr int ENT = (TB * kS + NT - 1) / NT;  // tile entries staged per thread
+  __shared__ double2 sxy[TB * kS];            // [b][s] (x, y)
+  __shared__ double2 szm[TB * kS];            // [b][s] (z, m)
+  __shared__ double part[NCH][3][64];         // chunk partial sums
+  __shared__ double tq[GM][3][64];            // current stage positions of the owned groups
+  __shared__ double rt[GM][3][64];            // increments R of the owned groups
+  __shared__ double gq[GM][3][64];            // tentative next-step initial guess
+  __shared__ LgTargetState ts[GM];            // per-target state
+  __shared__ double coef[kS][kS + 2];         // eta row, c, b per stage
+  __shared__ unsigned blk_flags;  // this workgroup's flags for the next barrier
+  __shared__ unsigned bar_res;    // flags returned by the last barrier
+
   const LaunchArgs& a = L.a;
   const ConstTab T = const_tab(a.tab);
-  const InstDesc dsc = a.desc[L.inst];
+  const InstDesc& dsc = a.desc[L.inst];
   const int n = L.n;
   const int dq = 3 * n;
   const int tid = threadIdx.x;
-  const int bid = blockIdx.x;
-  const int nblocks = gridDim.x;
-  // block -> (stage, target block, chunk)
-  const int s = bid % kS;
-  const int tb = (bid / kS) % L.ntb;
-  const int c = bid / (kS * L.ntb);
-  const int chunk = (n + L.nchunks - 1) / L.nchunks;
-  const int src0 = c * chunk;
-  const int src1 = min(n, src0 + chunk);
-  const int tgt = tb * kLargeBlock + tid;
-  const int gtid = bid * kLargeBlock + tid;  // component lane for the step end
-
-  __shared__ double src[kLargeTile * 3];
-  __shared__ double msrc[kLargeTile];
-  __shared__ int32_t last_flag;
+  const int wave = tid >> 6;
+  const int lane = tid & 63;
+  const int t = lane >> 3, s = lane & 7;
+  const unsigned nblocks = gridDim.x;
+  const int gpw = L.gpw;
+  const int g0 = blockIdx.x * gpw;
+  // this wavefront's group, as state owner
+  const int my_group = g0 + wave;
+  const bool owner = wave < gpw && my_group < L.ngroups;
+  const int my_tgt = my_group * kLgT + t;
+  const bool mine = owner && my_tgt < n;
 
   const double* mass = a.params + dsc.mass_off;
-  double* S = a.state + dsc.state_off;
+  double* Sp = a.state + dsc.state_off;
   const double h = dsc.h;
   const double G = dsc.G;
   const double eps2 = dsc.eps * dsc.eps;
@@ -82,281 +274,322 @@ __global__ __launch_bounds__(kLargeBlock) void large_kernel(LargeArgs L) {
   if (st0.status != kOk) target = step;
   int64_t it_sum = st0.iterations, nonconv = st0.nonconv;
   int32_t maxk = st0.max_k;
+  unsigned gen = 0;
+
+  for (int e = tid; e < kS * kS; e += NT) coef[e / kS][e % kS] = a.tab[kTabEta + e];
+  if (tid < kS) {
+    coef[tid][kS] = a.tab[kTabC + tid];
+    coef[tid][kS + 1] = a.tab[kTabB + tid];
+  }
+  const size_t bufsz = (size_t)n * kS;  // entries (4 doubles) per position buffer
+  double* pos = L.pos;
+  int rbuf = 0;
+
+  // ---- state and the first initial guess (into position buffer 0)
+  if (owner) {
+    LgTargetState& S = ts[wave];
+#pragma unroll 1
+    for (int d = 0; d < 3; ++d) {
+      double q0 = 0.0, r0 = 0.0;
+      if (mine && step < target) {
+        const int c = my_tgt * 3 + d;
+        const double qh = Sp[c], vh = Sp[2 * dq + c];
+        S.qh[t][d] = qh;
+        S.ql[t][d] = Sp[dq + c];
+        S.vh[t][d] = vh;
+        S.vl[t][d] = Sp[3 * dq + c];
+        S.mind[t][d] = __builtin_inf();
+        S.prv[t][d] = __builtin_inf();
+        double Rp[kS];
+#pragma unroll
+        for (int j = 0; j < kS; ++j) Rp[j] = Sp[4 * dq + c * kS + j];
+        r0 = Rp[s];
+        q0 = lg_guess<EXACT>(T, s, qh, vh, Rp, h);
+        pos[((size_t)my_tgt * kS + s) * 4 + d] = q0;
+      }
+      tq[wave][d][lane] = q0;
+      rt[wave][d][lane] = r0;
+    }
+    if (mine && step < target) pos[((size_t)my_tgt * kS + s) * 4 + 3] = mass[my_tgt];
+  }
+  if (tid == 0) blk_flags = 0;
+  __threadfence();
+  grid_barrier(L.ctl, gen, nblocks, &blk_flags, &bar_res);
+
+  int k = 0;
   bool dead = false;
-  int64_t it = 0;  // global iteration counter (parity of the position buffers)
+  while (step < target) {
+    ++k;
+    const int wb = (rbuf + 1) % 3, gb = (rbuf + 2) % 3;  // new stage values, next guess
+    const double* P = pos + (size_t)rbuf * bufsz * 4;
+    if (tid == 0) blk_flags = 0;  // last read by thread 0 inside the previous barrier
 
-  // Initial guess of the first step from the stored state, into pos[0].
-  if (gtid < dq && step < target) {
-    const double qh = S[gtid], vh = S[2 * dq + gtid];
-    double Rp[1][kS], Q0[1][kS];
-#pragma unroll
-    for (int j = 0; j < kS; ++j) Rp[0][j] = S[4 * dq + gtid * kS + j];
-    const double qa[1] = {qh}, va[1] = {vh};
-    initial_guess<1, EXACT>(T, qa, va, Rp, h, Q0);
-    const int body = gtid / 3, d = gtid % 3;
-#pragma unroll
-    for (int j = 0; j < kS; ++j) L.pos[((size_t)j * n + body) * 3 + d] = Q0[0][j];
-    L.hist[2 * gtid] = __builtin_inf();
-    L.hist[2 * gtid + 1] = __builtin_inf();
-  }
-  if (bid == 0 && tid < 9) L.flags[tid] = 0;
-  if (bid == 0 && tid == 0) {
-    for (int t = 0; t < L.ntb; ++t) L.arrive[t] = 0;
-  }
-  grid.sync();
-
-  while (step < target && !dead) {
-    int k = 0;
-    bool conv = false, capped = false;
-    for (;;) {
-      ++k;
-      const double* P = L.pos + (size_t)(it & 1) * kS * n * 3;
-      double* Pn = L.pos + (size_t)((it + 1) & 1) * kS * n * 3;
-      const int fl = (int)(it % 3);
-      // ---- force partial sums for (stage s, targets of block tb, chunk c)
+    for (int g = 0; g < gpw; ++g) {
+      const int grp = g0 + g;
+      if (grp >= L.ngroups) break;  // uniform over the workgroup
+      const int tgt = grp * kLgT + t;
+      // ---- force on the group's targets: this wavefront's source chunk.
+      // The next tile is fetched into registers while the current one is
+      // being used (ENT entries per thread).
       double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
-      double qa0 = 0.0, qa1 = 0.0, qa2 = 0.0;
-      if (tgt < n) {
-        qa0 = P[((size_t)s * n + tgt) * 3 + 0];
-        qa1 = P[((size_t)s * n + tgt) * 3 + 1];
-        qa2 = P[((size_t)s * n + tgt) * 3 + 2];
+      double pre[ENT][4];
+#pragma unroll
+      for (int e = 0; e < ENT; ++e) {
+        const int idx = tid + e * NT;
+        if (idx < min(TB, n) * kS) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) pre[e][c] = P[(size_t)idx * 4 + c];
+        }
       }
-      for (int t0 = src0; t0 < src1; t0 += kLargeTile) {
-        const int t1 = min(src1, t0 + kLargeTile);
+      for (int b0 = 0; b0 < n; b0 += TB) {
+        const int nb = min(TB, n - b0);
         __syncthreads();
-        for (int b = t0 + tid; b < t1; b += kLargeBlock) {
-          src[(b - t0) * 3 + 0] = P[((size_t)s * n + b) * 3 + 0];
-          src[(b - t0) * 3 + 1] = P[((size_t)s * n + b) * 3 + 1];
-          src[(b - t0) * 3 + 2] = P[((size_t)s * n + b) * 3 + 2];
-          msrc[b - t0] = mass[b];
+#pragma unroll
+        for (int e = 0; e < ENT; ++e) {
+          const int idx = tid + e * NT;
+          if (idx < nb * kS) {
+            sxy[idx] = make_double2(pre[e][0], pre[e][1]);
+            szm[idx] = make_double2(pre[e][2], pre[e][3]);
+          }
         }
         __syncthreads();
-        if (tgt < n) {
-          for (int b = t0; b < t1; ++b) {
-            if (b == tgt) continue;
-            const double dx = src[(b - t0) * 3 + 0] - qa0;
-            const double dy = src[(b - t0) * 3 + 1] - qa1;
-            const double dz = src[(b - t0) * 3 + 2] - qa2;
-            if constexpr (EXACT) {
-              double r2 = 0.0;
-              r2 = r2 + dx * dx;
-              r2 = r2 + dy * dy;
-              r2 = r2 + dz * dz;
-              r2 = r2 + eps2;
-              const double w = pair_weight<true>(r2, msrc[b - t0]);
-              acc0 = acc0 + w * dx;
-              acc1 = acc1 + w * dy;
-              acc2 = acc2 + w * dz;
-            } else {
-              const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-              const double w = msrc[b - t0] * rinv3(r2 + eps2);
-              acc0 = fma(w, dx, acc0);
-              acc1 = fma(w, dy, acc1);
-              acc2 = fma(w, dz, acc2);
+        const int b1 = b0 + TB;
+        if (b1 < n) {
+          const int nb1 = min(TB, n - b1);
+#pragma unroll
+          for (int e = 0; e < ENT; ++e) {
+            const int idx = tid + e * NT;
+            if (idx < nb1 * kS) {
+#pragma unroll
+              for (int c = 0; c < 4; ++c) pre[e][c] = P[((size_t)b1 * kS + idx) * 4 + c];
             }
           }
         }
-      }
-      if (tgt < n) {
-        double* pp = L.part + (((size_t)c * kS + s) * n + tgt) * 3;
-        pp[0] = acc0;
-        pp[1] = acc1;
-        pp[2] = acc2;
-      }
-      // ---- arrival; the last workgroup of this target block does its update
-      __threadfence();
-      __syncthreads();
-      if (tid == 0) {
-        const int prev = atomicAdd(&L.arrive[tb], 1);
-        last_flag = (prev == kS * L.nchunks - 1) ? 1 : 0;
-        if (last_flag) L.arrive[tb] = 0;
-      }
-      __syncthreads();
-      if (last_flag) {
-        __threadfence();
         if (tgt < n) {
-          bool ok = true, bad = false;
-#pragma unroll
-          for (int d = 0; d < 3; ++d) {
-            const int comp = tgt * 3 + d;
-            const double qh = S[comp], vh = S[2 * dq + comp];
-            double R[kS];
-#pragma unroll
-            for (int j = 0; j < kS; ++j) {
-              double g;
-              if constexpr (EXACT) {
-                g = L.part[((size_t)j * n + tgt) * 3 + d];  // single chunk
-                R[j] = (h * T[kTabB + j]) * (G * g);
-              } else {
-                g = 0.0;
-                for (int cc = 0; cc < L.nchunks; ++cc)
-                  g += L.part[(((size_t)cc * kS + j) * n + tgt) * 3 + d];
-                R[j] = ((h * T[kTabB + j]) * G) * g;
-              }
-            }
-            double dmax = 0.0;
-#pragma unroll
-            for (int j = 0; j < kS; ++j) {
-              const ConstTab r = row_tab(T);
-              const double qn = stage_value<EXACT>(r, j, qh, vh, h, R);
-              dmax = max_keep_nan(dmax, fabs(qn - P[((size_t)j * n + tgt) * 3 + d]));
-              Pn[((size_t)j * n + tgt) * 3 + d] = qn;
-            }
-#pragma unroll
-            for (int j = 0; j < kS; ++j) L.rbuf[(size_t)comp * kS + j] = R[j];
-            double mind = L.hist[2 * comp], prv = L.hist[2 * comp + 1];
-            bad |= !finite(dmax);
-            ok &= stop_component(dmax, mind, prv);
-            L.hist[2 * comp] = mind;
-            L.hist[2 * comp + 1] = prv;
-          }
-          if (!ok) atomicOr(&L.flags[fl * 2 + 0], 1);
-          if (bad) atomicOr(&L.flags[fl * 2 + 1], 1);
+          const double qx = tq[g][0][lane], qy = tq[g][1][lane], qz = tq[g][2][lane];
+          // with softening the self term needs no special case (w finite,
+          // displacement 0); without it the self distance is replaced
+          if (eps2 > 0.0)
+            lg_force_tile<EXACT, NCH, false>(sxy, szm, wave, nb, s, b0, tgt, qx, qy, qz, eps2,
+                                             acc0, acc1, acc2);
+          else
+            lg_force_tile<EXACT, NCH, true>(sxy, szm, wave, nb, s, b0, tgt, qx, qy, qz, eps2,
+                                            acc0, acc1, acc2);
         }
       }
-      // reset the flags of iteration it + 1 (last read two barriers ago)
-      if (bid == 0 && tid < 2) L.flags[((it + 1) % 3) * 2 + tid] = 0;
-      __threadfence();
-      grid.sync();
-      const int notok = __hip_atomic_load(&L.flags[fl * 2 + 0], __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-      const int badf = __hip_atomic_load(&L.flags[fl * 2 + 1], __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT);
-      ++it;
-      if (badf) {
-        dead = true;
-        break;
+      if constexpr (NCH > 1) {
+        part[wave][0][lane] = acc0;
+        part[wave][1][lane] = acc1;
+        part[wave][2][lane] = acc2;
+        __syncthreads();
       }
-      if (!notok) {
-        conv = true;
-        break;
-      }
-      if (k >= a.max_iter) {
-        capped = true;
-        break;
+      if (wave == g && tgt < n) {
+        // ---- update of group g by its state wavefront, one component at a time
+        const double hb = h * coef[s][kS + 1];
+        const double cs = coef[s][kS];
+        LgTargetState& S = ts[g];
+        bool ok = true, bad = false;
+#pragma unroll 1
+        for (int d = 0; d < 3; ++d) {
+          double gsum;
+          if constexpr (NCH > 1) {
+            gsum = part[0][d][lane];
+#pragma unroll
+            for (int c = 1; c < NCH; ++c) gsum += part[c][d][lane];
+          } else {
+            gsum = d == 0 ? acc0 : (d == 1 ? acc1 : acc2);
+          }
+          double Rn;
+          if constexpr (EXACT)
+            Rn = hb * (G * gsum);
+          else
+            Rn = (hb * G) * gsum;
+          rt[g][d][lane] = Rn;
+        }
+        lg_wave_lds_sync();
+#pragma unroll 1
+        for (int d = 0; d < 3; ++d) {
+          double Rj[kS];
+#pragma unroll
+          for (int j = 0; j < kS; ++j) Rj[j] = rt[g][d][t * kS + j];
+          const double qh = S.qh[t][d], vh = S.vh[t][d];
+          double qn;
+          if constexpr (EXACT) {
+            double sm = 0.0;
+#pragma unroll
+            for (int j = 0; j < kS; ++j) sm = sm + coef[s][j] * Rj[j];
+            qn = qh + h * (cs * vh + sm);
+          } else {
+            double acc = cs * vh;
+#pragma unroll
+            for (int j = 0; j < kS; ++j) acc = fma(coef[s][j], Rj[j], acc);
+            qn = fma(h, acc, qh);
+          }
+          const double dmax = lg_group_max(fabs(qn - tq[g][d][lane]));
+          bad |= !finite(dmax);
+          double mind = S.mind[t][d], prv = S.prv[t][d];
+          ok &= stop_component(dmax, mind, prv);
+          // tentative compensated update and the next step's initial guess
+          double sv, sc;
+          step_sums<EXACT>(row_tab(T), Rj, sv, sc);
+          double vh2 = vh, vl2 = S.vl[t][d], qh2 = qh, ql2 = S.ql[t][d];
+          dw_add(vh2, vl2, sv);
+          dw_add(qh2, ql2, h * (vh2 - sc));
+          const double qg = lg_guess<EXACT>(T, s, qh2, vh2, Rj, h);
+          // all 8 stage lanes hold the same history; they store equal values
+          S.mind[t][d] = mind;
+          S.prv[t][d] = prv;
+          tq[g][d][lane] = qn;
+          gq[g][d][lane] = qg;
+          pos[((size_t)wb * bufsz + (size_t)tgt * kS + s) * 4 + d] = qn;
+          pos[((size_t)gb * bufsz + (size_t)tgt * kS + s) * 4 + d] = qg;
+        }
+        const double m = mass[tgt];
+        pos[((size_t)wb * bufsz + (size_t)tgt * kS + s) * 4 + 3] = m;
+        pos[((size_t)gb * bufsz + (size_t)tgt * kS + s) * 4 + 3] = m;
+        const uint64_t notok = __ballot(!ok), badm = __ballot(bad);
+        if (lane == 0 && (notok | badm))  // target 0 of a group always exists
+          atomicOr(&blk_flags, (notok ? 1u : 0u) | (badm ? 2u : 0u));
       }
     }
-    // ---- end of step (component lanes spread over the whole grid)
-    if (dead) {
-      if (gtid < dq) {
-        const int64_t nf = target / dsc.stride;  // frames of this launch only
-        for (int64_t f = step / dsc.stride + 1; f <= nf; ++f) {
-          a.qout[dsc.out_off + f * dq + gtid] = __builtin_nan("");
-          a.pout[dsc.out_off + f * dq + gtid] = __builtin_nan("");
-        }
-      }
-      if (bid == 0 && tid == 0 && dsc.iters_off >= 0) a.step_iters[dsc.iters_off + step] = (uint8_t)k;
+    const unsigned bits = grid_barrier(L.ctl, gen, nblocks, &blk_flags, &bar_res);
+    if (bits & 2u) {
+      dead = true;
       break;
     }
-    (void)conv;
+    const bool notok = (bits & 1u) != 0;
+    const bool capped = notok && k >= a.max_iter;
+    if (notok && !capped) {  // iterate again from the new stage positions (in tq)
+      rbuf = wb;
+      continue;
+    }
+    // ---- step accepted: commit the compensated update, outputs
     ++step;
     it_sum += k;
     nonconv += capped ? 1 : 0;
     maxk = k > maxk ? k : maxk;
-    if (gtid < dq) {
-      double qh = S[gtid], ql = S[dq + gtid], vh = S[2 * dq + gtid], vl = S[3 * dq + gtid];
-      double R[1][kS];
+    if (blockIdx.x == 0 && tid == 0 && dsc.iters_off >= 0)
+      a.step_iters[dsc.iters_off + step - 1] = (uint8_t)k;
+    k = 0;
+    rbuf = gb;
+    if (mine) {
+      LgTargetState& S = ts[wave];
+      const bool frame = s == 0 && step % dsc.stride == 0;
+      const int64_t fo = dsc.out_off + (step / dsc.stride) * dq + my_tgt * 3;
+#pragma unroll 1
+      for (int d = 0; d < 3; ++d) {
+        double Rj[kS];
 #pragma unroll
-      for (int j = 0; j < kS; ++j) R[0][j] = L.rbuf[(size_t)gtid * kS + j];
-      double sv, sc;
-      step_sums<EXACT>(T, R[0], sv, sc);
-      dw_add(vh, vl, sv);
-      dw_add(qh, ql, h * (vh - sc));
-      S[gtid] = qh;
-      S[dq + gtid] = ql;
-      S[2 * dq + gtid] = vh;
-      S[3 * dq + gtid] = vl;
-#pragma unroll
-      for (int j = 0; j < kS; ++j) S[4 * dq + gtid * kS + j] = R[0][j];
-      if (step % dsc.stride == 0) {
-        const int64_t f = step / dsc.stride;
-        a.qout[dsc.out_off + f * dq + gtid] = qh;
-        a.pout[dsc.out_off + f * dq + gtid] = mass[gtid / 3] * vh;
-      }
-      if (step < target) {
-        double Q0[1][kS];
-        const double qa[1] = {qh}, va[1] = {vh};
-        initial_guess<1, EXACT>(T, qa, va, R, h, Q0);
-        double* Pn = L.pos + (size_t)(it & 1) * kS * n * 3;
-        const int body = gtid / 3, d = gtid % 3;
-#pragma unroll
-        for (int j = 0; j < kS; ++j) Pn[((size_t)j * n + body) * 3 + d] = Q0[0][j];
-        L.hist[2 * gtid] = __builtin_inf();
-        L.hist[2 * gtid + 1] = __builtin_inf();
+        for (int j = 0; j < kS; ++j) Rj[j] = rt[wave][d][t * kS + j];
+        double sv, sc;
+        step_sums<EXACT>(row_tab(T), Rj, sv, sc);
+        double vh = S.vh[t][d], vl = S.vl[t][d], qh = S.qh[t][d], ql = S.ql[t][d];
+        dw_add(vh, vl, sv);
+        dw_add(qh, ql, h * (vh - sc));
+        // every stage lane of the target computed the same values
+        S.qh[t][d] = qh;
+        S.ql[t][d] = ql;
+        S.vh[t][d] = vh;
+        S.vl[t][d] = vl;
+        S.mind[t][d] = __builtin_inf();
+        S.prv[t][d] = __builtin_inf();
+        tq[wave][d][lane] = gq[wave][d][lane];
+        if (frame) {
+          a.qout[fo + d] = qh;
+          a.pout[fo + d] = mass[my_tgt] * vh;
+        }
       }
     }
-    if (bid == 0 && tid == 0 && dsc.iters_off >= 0) a.step_iters[dsc.iters_off + step - 1] = (uint8_t)k;
-    __threadfence();
-    grid.sync();
   }
-  if (bid == 0 && tid == 0) {
+
+  // ---- end of launch
+  if (dead) {
+    if (mine && s == 0) {
+      const int64_t nf = target / dsc.stride;  // frames of this launch only
+      for (int64_t f = step / dsc.stride + 1; f <= nf; ++f)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          a.qout[dsc.out_off + f * dq + my_tgt * 3 + d] = __builtin_nan("");
+          a.pout[dsc.out_off + f * dq + my_tgt * 3 + d] = __builtin_nan("");
+        }
+    }
+    if (blockIdx.x == 0 && tid == 0 && dsc.iters_off >= 0)
+      a.step_iters[dsc.iters_off + step] = (uint8_t)k;
+  } else if (mine && step > st0.steps_done) {
+    const LgTargetState& S = ts[wave];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int c = my_tgt * 3 + d;
+      if (s == 0) {
+        Sp[c] = S.qh[t][d];
+        Sp[dq + c] = S.ql[t][d];
+        Sp[2 * dq + c] = S.vh[t][d];
+        Sp[3 * dq + c] = S.vl[t][d];
+      }
+      Sp[4 * dq + c * kS + s] = rt[wave][d][lane];
+    }
+  }
+  if (blockIdx.x == 0 && tid == 0) {
     InstStat st;
     st.steps_done = step;
     st.iterations = it_sum;
     st.nonconv = nonconv;
     st.max_k = maxk;
-    st.status = dead ? kNonFinite : (st0.status != kOk ? st0.status : kOk);
+    st.status = dead ? kNonFinite : st0.status;
     a.stat[L.inst] = st;
   }
-  (void)nblocks;
 }
 
-bool large_class_supported(int kind, int n, int d) { return kind == kGravity && d == 3 && n > 1; }
-
-// Device scratch needed for a system of n bodies with the given chunk count.
-size_t large_scratch_bytes(int n, int nchunks) {
-  const int ntb = (n + kLargeBlock - 1) / kLargeBlock;
-  return sizeof(double) * ((size_t)2 * kS * n * 3 + (size_t)nchunks * kS * n * 3 +
-                            (size_t)3 * n * kS + (size_t)3 * n * 2) +
-         sizeof(int32_t) * (ntb + 9) + sizeof(int64_t) * 4 + 256;
+bool large_class_supported(int kind, int n, int d) {
+  return kind == kGravity && d == 3 && n > 1 && n <= kLgMaxBodies;
 }
 
-// Chunk count: the largest power of two (<= 16, chunks of >= 64 sources) whose
-// grid still fits co-resident; 1 in reproducible mode.
-int large_chunks(int n, bool exact, int num_cus) {
-  if (exact) return 1;
+// Device scratch for a system of n bodies: three position buffers and the
+// control words.
+size_t large_scratch_bytes(int n, int /*nchunks*/) {
+  return sizeof(double) * (size_t)3 * n * kS * 4 + sizeof(unsigned) * kCtlWords;
+}
+
+// Source chunks (wavefronts per workgroup): 16, or 1 in reproducible mode.
+int large_chunks(int /*n*/, bool exact, int /*num_cus*/) { return exact ? 1 : 16; }
+
+template <bool EXACT, int NCH>
+static hipError_t launch_large_t(LargeArgs& L, int num_cus, hipStream_t st) {
+  auto kern = large_kernel<EXACT, NCH>;
+  constexpr int NT = LargeCfg<NCH>::kThreads;
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, large_kernel<false>, kLargeBlock, 0) !=
-          hipSuccess ||
-      per_cu < 1)
-    return 1;
-  const int ntb = (n + kLargeBlock - 1) / kLargeBlock;
-  int ch = 1;
-  while (ch < 16 && n / (2 * ch) >= 64 && kS * ntb * (2 * ch) <= per_cu * num_cus) ch *= 2;
-  return ch;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, 0);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) return hipErrorCooperativeLaunchTooLarge;
+  const int cap = per_cu * num_cus;
+  // fewest groups per workgroup such that the grid is co-resident
+  int gpw = (L.ngroups + cap - 1) / cap;
+  if (gpw < 1) gpw = 1;
+  if (gpw > LargeCfg<NCH>::kMaxGroups) return hipErrorCooperativeLaunchTooLarge;
+  L.gpw = gpw;
+  const int grid = (L.ngroups + gpw - 1) / gpw;
+  void* args[] = {&L};
+  return hipLaunchCooperativeKernel((const void*)kern, dim3(grid), dim3(NT), args, 0, st);
 }
 
-hipError_t launch_large(const LaunchArgs& a, int inst, int n, void* scratch, int nchunks,
+hipError_t launch_large(const LaunchArgs& a, int inst, int n, void* scratch, int /*nchunks*/,
                         int num_cus, hipStream_t st) {
+  if (n < 2 || n > kLgMaxBodies) return hipErrorInvalidValue;
   LargeArgs L;
   L.a = a;
   L.inst = inst;
   L.n = n;
-  L.nchunks = nchunks;
-  L.ntb = (n + kLargeBlock - 1) / kLargeBlock;
+  L.ngroups = (n + kLgT - 1) / kLgT;
+  L.gpw = 1;
   char* p = static_cast<char*>(scratch);
-  auto take = [&](size_t bytes) {
-    char* r = p;
-    p += (bytes + 255) / 256 * 256;
-    return r;
-  };
-  L.pos = reinterpret_cast<double*>(take(sizeof(double) * 2 * kS * n * 3));
-  L.part = reinterpret_cast<double*>(take(sizeof(double) * (size_t)nchunks * kS * n * 3));
-  L.rbuf = reinterpret_cast<double*>(take(sizeof(double) * 3 * n * kS));
-  L.hist = reinterpret_cast<double*>(take(sizeof(double) * 3 * n * 2));
-  L.arrive = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * L.ntb));
-  L.flags = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * 9));
-  L.ctl = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * 4));
-  const int grid = kS * L.ntb * nchunks;
-  int per_cu = 0;
-  auto kern = a.exact ? large_kernel<true> : large_kernel<false>;
-  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kLargeBlock, 0);
+  L.pos = reinterpret_cast<double*>(p);
+  p += sizeof(double) * (size_t)3 * n * kS * 4;
+  L.ctl = reinterpret_cast<unsigned*>(p);
+  // barrier counters and the release word start from zero for every launch
+  hipError_t e = hipMemsetAsync(p, 0, sizeof(unsigned) * kCtlWords, st);
   if (e != hipSuccess) return e;
-  if (grid > per_cu * num_cus) return hipErrorCooperativeLaunchTooLarge;
-  // the step-end lanes must cover all 3n components
-  if ((size_t)grid * kLargeBlock < (size_t)3 * n) return hipErrorInvalidConfiguration;
-  void* args[] = {&L};
-  return hipLaunchCooperativeKernel((const void*)kern, dim3(grid), dim3(kLargeBlock), args, 0, st);
+  if (a.exact) return launch_large_t<true, 1>(L, num_cus, st);
+  return launch_large_t<false, 16>(L, num_cus, st);
 }
 
 }  // namespace irk

@@ -66,3 +66,37 @@ def test_large_nonfinite_stops_cleanly():
     qo, po, st, rc = run(inst, 4, 1)
     assert rc == K.IRKGL16_ENONFINITE
     assert np.all(np.isnan(qo.reshape(5, -1)[1:]))
+
+
+@pytest.mark.parametrize("n", [513, 1001])
+def test_large_ragged_last_group_reproducible(orc, n):
+    """Body counts that leave a partial last group of 8 targets."""
+    inst = W.plummer(n, seed=17)
+    q, p, st, rc = run(inst, 3, 1, flags=K.IRKGL16_REPRODUCIBLE)
+    r = oracle_run(orc, inst, 3, 1)
+    assert rc == 0
+    assert np.array_equal(q, r["q"].ravel()) and np.array_equal(p, r["p"].ravel())
+    assert np.array_equal(st["step_iters"].astype(np.int32), r["iters"])
+
+
+def test_large_several_groups_per_workgroup(orc):
+    """4100 bodies: more target groups than co-resident workgroups, so a
+    workgroup integrates several groups (one state wavefront each)."""
+    inst = W.plummer(4100, seed=19)
+    q, p, st, rc = run(inst, 2, 2)
+    r = oracle_run(orc, inst, 2, 2)
+    assert rc == 0
+    q, p = q.reshape(2, -1), p.reshape(2, -1)
+    assert relmax(q[1], r["q"][1]) <= 1e-14
+    assert relmax(p[1], r["p"][1]) <= 1e-12
+    assert np.abs(st["step_iters"].astype(int) - r["iters"]).max() <= 1
+
+
+def test_large_resumed_launches_equal_one_launch():
+    """Integrating 6 steps as 6 one-step launches (state, increments and
+    counters resumed from device memory) gives the bits of one 6-step launch."""
+    inst = W.plummer(1500, seed=23)
+    a = run(inst, 6, 2)
+    b = run(inst, 6, 2, flags=K.IRKGL16_PLAIN)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert a[2]["iterations"] == b[2]["iterations"]
