@@ -165,7 +165,7 @@ __device__ __forceinline__ double lg_r2(double dx, double dy, double dz, double 
     r2 = r2 + dz * dz;
     return r2 + eps2;
   } else {
-    return fma(dz, dz, fma(dy, dy, dx * dx)) + eps2;
+    return fma(dz, dz, fma(dy, dy, fma(dx, dx, eps2)));
   }
 }
 

@@ -93,10 +93,10 @@ __device__ __forceinline__ void stage_increment(double* __restrict__ Xs, int sub
         double dx[D];
 #pragma unroll
         for (int k = 0; k < D; ++k) dx[k] = Xs[(b * D + k) * kS + sub] - Xs[(a * D + k) * kS + sub];
-        double r2 = dx[0] * dx[0];
+        double r2 = fma(dx[0], dx[0], eps2);
 #pragma unroll
         for (int k = 1; k < D; ++k) r2 = fma(dx[k], dx[k], r2);
-        const double w = rinv3(r2 + eps2);
+        const double w = rinv3(r2);
         const double wa = m[a] * w, wb = m[b] * w;
 #pragma unroll
         for (int k = 0; k < D; ++k) {

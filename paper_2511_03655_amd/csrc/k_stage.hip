@@ -208,10 +208,9 @@ __global__ __launch_bounds__(8 * NPMAX) void stage_kernel(LaunchArgs a, int np) 
               for (int d = 0; d < D; ++d) r2 = r2 + dx[d] * dx[d];
               r2 = r2 + eps2;
             } else {
-              r2 = dx[0] * dx[0];
+              r2 = fma(dx[0], dx[0], eps2);
 #pragma unroll
               for (int d = 1; d < D; ++d) r2 = fma(dx[d], dx[d], r2);
-              r2 = r2 + eps2;
             }
             // the self term contributes w * 0 = 0; its r2 is replaced so that
             // an unsoftened self distance does not produce 0 * inf

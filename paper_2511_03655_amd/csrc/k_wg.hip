@@ -58,10 +58,10 @@ __device__ __forceinline__ void unit_increments(const double* __restrict__ Qs,
 #pragma unroll
           for (int d = 0; d < D; ++d) acc[d][s] = acc[d][s] + w * dx[d];
         } else {
-          double r2 = dx[0] * dx[0];
+          double r2 = fma(dx[0], dx[0], eps2);
 #pragma unroll
           for (int d = 1; d < D; ++d) r2 = fma(dx[d], dx[d], r2);
-          const double w = mb * rinv3(r2 + eps2);
+          const double w = mb * rinv3(r2);
 #pragma unroll
           for (int d = 0; d < D; ++d) acc[d][s] = fma(w, dx[d], acc[d][s]);
         }
