@@ -83,6 +83,53 @@ def cpu_baseline(sy, n_sample, nsteps):
                 rc=int(r["rc"]))
 
 
+PROFILES = os.path.join(ROOT, "profiles")
+CSRC = os.path.join(ROOT, "paper_2511_03655_amd", "csrc")
+
+
+def source_digest(files):
+    """sha256 over kernel source files (the ones a traffic measurement covers)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_from_profile(name, files):
+    """HBM bytes per launch recorded in profiles/<name>.md by two rocprofv3
+    --pmc passes (FETCH_SIZE, WRITE_SIZE) scaled by a copy-kernel calibration;
+    None if the profile is missing or the kernel sources changed since."""
+    path = os.path.join(PROFILES, name + ".md")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and line.startswith(("traffic_bytes_per_launch", "source_sha256")):
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip().strip("`")
+    if rec.get("source_sha256") != source_digest(files):
+        return None
+    try:
+        return float(rec["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration():
+    """A plain device copy of known size (the FETCH_SIZE / WRITE_SIZE scale)."""
+    import torch
+    n = 1 << 27  # doubles: 1 GiB per buffer
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,10 +143,15 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.workload != "c2":
         print(json.dumps(OTHER_WORKLOADS[args.workload](args)))
         return
@@ -237,7 +289,11 @@ def main():
         "force_evals_per_s": 8 * iters * args.steps / elapsed,
         "mean_iterations_per_step": iters / inst_steps,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": traffic_from_profile(
+                         "small_kernel_c2_65536x6body",
+                         ["k_small.hip", "device_common.h", "k_prepare.hip"]),
+                     "kernel": "small_kernel<gravity, 6 bodies, d=3>",
                      "kernel_ms": float(np.mean(kernel_ms)),
                      "algorithmic_flops_per_launch": flops},
         "accuracy": {"gate": "relative energy error first->last frame <= 1e-12",
@@ -365,7 +421,11 @@ def run_c3(args):
                     "pair_interactions_per_s": pairs / dt,
                     "roofline": {"bound": "alu", "achieved": flops / dt / 1e12,
                                  "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                                 "frac": flops / dt / 1e12 / FP64_PEAK_TFLOPS, "traffic": None},
+                                 "frac": flops / dt / 1e12 / FP64_PEAK_TFLOPS,
+                                 "traffic": traffic_from_profile(
+                                     "large_kernel_c3_plummer2048",
+                                     ["k_large.hip", "device_common.h"]),
+                                 "kernel": "large_kernel (cooperative, whole GPU)"},
                     "plain": {"value": 1.0 / dtp, "unit": "steps/s",
                               "sample": "50 steps, one launch per step"},
                     "cpu_baseline": {"value": 1.0 / dtc, "unit": "steps/s", "cores": 1,
