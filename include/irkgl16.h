@@ -137,8 +137,9 @@ const char *irkgl16_strerror(int status);
 /* ---- serving ------------------------------------------------------------
  * A server integrates requests that arrive over time with continuous batching:
  * a serving thread admits pending requests (first come, first served) whenever
- * their device memory fits under cap_bytes, advances every resident request by
- * up to slice_steps steps in one batched launch per kernel class, streams the
+ * their device memory fits under cap_bytes, advances every resident request in
+ * one batched launch per kernel class (classes concurrently; each class by the
+ * number of steps that fits the target slice time, at most slice_steps), streams the
  * finished output frames of the slice to host memory, retires finished requests
  * and admits new ones before the next slice.  A request's resumable state
  * (two-double q and v, previous-step increments, counters) stays on the device
@@ -148,10 +149,13 @@ typedef struct irkgl16_server irkgl16_server;
 
 typedef struct {
   int64_t cap_bytes;   /* device memory for resident requests (> 0)            */
-  int64_t slice_steps; /* steps per request per slice (<= 0 means 1000)        */
+  int64_t slice_steps; /* steps per request per slice at most (<= 0: 1000)     */
   int32_t max_iter;    /* as in irkgl16_options                                */
   int32_t max_resident;/* resident requests at most (<= 0 means 65536)         */
   uint32_t flags;      /* IRKGL16_REPRODUCIBLE or 0                            */
+  double slice_ms;     /* target slice duration in ms (<= 0 means 20): each    */
+                       /* kernel class advances its requests by the steps that */
+                       /* fit, from that class's measured time per step        */
 } irkgl16_server_options;
 
 typedef struct {

@@ -4,9 +4,11 @@
 //
 // A serving thread repeats: admit pending requests (first come, first served)
 // while their device memory fits under the cap; run one time slice, i.e. one
-// batched launch per kernel class over all resident requests with a step budget
-// of slice_steps (newly admitted requests are first set up by the prepare
-// kernel); copy the slice's statistics and output frames to the host; retire
+// batched launch per kernel class over all resident requests, the classes
+// concurrently, each with a step budget sized to the target slice time from
+// that class's measured time per step (newly admitted requests are first set
+// up by the prepare kernel); copy the slice's statistics and output frames to
+// the host; retire
 // finished requests (their frames are complete on the host) and free their
 // memory.  A resident request's state record never leaves the device between
 // slices, and the kernels resume from it exactly, so a served request is
@@ -91,6 +93,7 @@ struct Request {
   bool fresh = false, done = false;
   bool finish = false;  // set by the slice (worker only); published as `done` under the lock
   int64_t stage_base = 0, f0 = 0;  // this slice's frame window
+  int64_t budget = 0, old_steps = 0;  // this slice's step budget, steps done before it
 };
 
 struct DevBuf {
@@ -132,6 +135,10 @@ struct irkgl16_server {
   std::vector<hipStream_t> aux;
   std::vector<hipEvent_t> aux_done;
   hipEvent_t ev_fork = nullptr;
+  // per-class step time (microseconds per step of a slice), measured with
+  // events around each class launch and smoothed over slices
+  std::map<std::tuple<int, int, int, int>, double> step_us;
+  std::vector<hipEvent_t> cls_ev;  // pairs: start, end
   std::chrono::steady_clock::time_point t0;
 
   DevBuf d_tab, d_desc, d_stat, d_arena, d_in, d_stage_q, d_stage_p, d_queue, d_heads, d_ids,
@@ -156,6 +163,7 @@ struct irkgl16_server {
 
   ~irkgl16_server() {
     for (hipEvent_t e : aux_done) (void)hipEventDestroy(e);
+    for (hipEvent_t e : cls_ev) (void)hipEventDestroy(e);
     for (hipStream_t sk : aux) (void)hipStreamDestroy(sk);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -186,14 +194,49 @@ static int validate(const irkgl16_problem& p) {
   return IRKGL16_OK;
 }
 
+// First estimate of a class's time per step (microseconds), before any slice
+// of that class has been measured.
+static double model_step_us(int cls, int kind, int size) {
+  switch (cls) {
+    case irk::kClassSmall: return 10.0;
+    case irk::kClassStage: return 8.0 + 0.6 * size;
+    case irk::kClassWg:
+      return kind == IRKGL16_GRAVITY ? 8.0 + (double)size * size / 150.0 : 8.0 + size / 40.0;
+    default: return 200.0;
+  }
+}
+
 // One time slice over the resident requests.  Called without the lock held.
+// Each kernel class advances its requests by the number of steps expected to
+// take opt.slice_ms (from that class's measured time per step), at least 1 and
+// at most opt.slice_steps, so that fast classes are not held back by slow ones.
 int irkgl16_server::slice(std::vector<Request*>& live, std::vector<Request*>& fresh) {
   const int64_t slice_steps = opt.slice_steps;
+  // class of every request and the class budgets
+  std::map<std::tuple<int, int, int, int>, std::vector<int32_t>> classes;
+  for (Request* r : live) {
+    auto key = std::make_tuple(r->cls, r->kind, r->S, r->d);
+    classes[key].push_back(r->slot);
+  }
+  std::map<std::tuple<int, int, int, int>, int64_t> budget;
+  for (auto& kv : classes) {
+    const auto& key = kv.first;
+    auto it = step_us.find(key);
+    const double us = it != step_us.end() ? it->second
+                                          : model_step_us(std::get<0>(key), std::get<1>(key),
+                                                          std::get<2>(key));
+    const double fit = opt.slice_ms * 1e3 / std::max(us, 1e-3);
+    budget[key] = std::max<int64_t>(1, std::min<int64_t>(slice_steps, (int64_t)fit));
+  }
+  for (Request* r : live) {
+    r->budget = budget[std::make_tuple(r->cls, r->kind, r->S, r->d)];
+    r->old_steps = r->steps_done;
+  }
   // frame windows and staging layout
   int64_t stage_total = 0, in_total = 0;
   for (Request* r : live) {
     const int64_t f0 = r->steps_done / r->stride;
-    const int64_t end = std::min(r->nsteps, r->steps_done + slice_steps);
+    const int64_t end = std::min(r->nsteps, r->steps_done + r->budget);
     const int64_t f1 = end / r->stride;
     r->f0 = f0;
     r->stage_base = stage_total;
@@ -223,12 +266,6 @@ int irkgl16_server::slice(std::vector<Request*>& live, std::vector<Request*>& fr
   }
   std::vector<int32_t> ids;
   for (Request* r : fresh) ids.push_back(r->slot);
-  // class queues
-  std::map<std::tuple<int, int, int, int>, std::vector<int32_t>> classes;
-  for (Request* r : live) {
-    auto key = std::make_tuple(r->cls, r->kind, r->S, r->d);
-    classes[key].push_back(r->slot);
-  }
   // longest remaining integration first within each class
   for (auto& kv : classes)
     std::stable_sort(kv.second.begin(), kv.second.end(), [&](int32_t x, int32_t y) {
@@ -280,10 +317,15 @@ int irkgl16_server::slice(std::vector<Request*>& live, std::vector<Request*>& fr
   a.pout = d_stage_p.as<double>();
   a.step_iters = nullptr;
   a.max_iter = opt.max_iter;
-  a.step_budget = slice_steps;
   a.exact = (opt.flags & IRKGL16_REPRODUCIBLE) ? 1 : 0;
   // batched classes concurrently on the auxiliary streams, then the
   // whole-GPU (cooperative) class alone on the slice stream
+  // timing events around every class launch (pairs: start, end)
+  while (cls_ev.size() < 2 * cls_list.size()) {
+    hipEvent_t e;
+    SRV_TRY(hipEventCreate(&e));
+    cls_ev.push_back(e);
+  }
   SRV_TRY(hipEventRecord(ev_fork, st));
   std::vector<char> used(aux.size(), 0);
   int aux_next = 0;
@@ -295,10 +337,13 @@ int irkgl16_server::slice(std::vector<Request*>& live, std::vector<Request*>& fr
     a.queue = d_queue.as<int32_t>() + cls_list[k].second.first;
     a.queue_len = cls_list[k].second.second;
     a.queue_head = d_heads.as<int32_t>() + k;
+    a.step_budget = budget[key];
     const int j = aux_next++ % (int)aux.size();
     if (!used[j]) SRV_TRY(hipStreamWaitEvent(aux[j], ev_fork, 0));
     used[j] = 1;
+    SRV_TRY(hipEventRecord(cls_ev[2 * k], aux[j]));
     SRV_TRY(irk::launch_batched(cls, kind, sz, d, a, a.queue_len, num_cus, aux[j]));
+    SRV_TRY(hipEventRecord(cls_ev[2 * k + 1], aux[j]));
   }
   for (size_t j = 0; j < aux.size(); ++j) {
     if (!used[j]) continue;
@@ -311,14 +356,15 @@ int irkgl16_server::slice(std::vector<Request*>& live, std::vector<Request*>& fr
     a.queue = d_queue.as<int32_t>() + cls_list[k].second.first;
     a.queue_len = cls_list[k].second.second;
     a.queue_head = d_heads.as<int32_t>() + k;
-    {
-      for (int i = 0; i < a.queue_len; ++i) {
-        const int slot = queue[cls_list[k].second.first + i];
-        Request* r = resident[slot];
-        const int ch = irk::large_chunks(r->n, a.exact != 0, num_cus);
-        SRV_TRY(irk::launch_large(a, slot, r->n, d_large.p, ch, num_cus, st));
-      }
+    a.step_budget = budget[cls_list[k].first];
+    SRV_TRY(hipEventRecord(cls_ev[2 * k], st));
+    for (int i = 0; i < a.queue_len; ++i) {
+      const int slot = queue[cls_list[k].second.first + i];
+      Request* r = resident[slot];
+      const int ch = irk::large_chunks(r->n, a.exact != 0, num_cus);
+      SRV_TRY(irk::launch_large(a, slot, r->n, d_large.p, ch, num_cus, st));
     }
+    SRV_TRY(hipEventRecord(cls_ev[2 * k + 1], st));
   }
   if ((int64_t)h_stage_q.size() < stage_total) {
     h_stage_q.resize(stage_total);
@@ -359,6 +405,21 @@ int irkgl16_server::slice(std::vector<Request*>& live, std::vector<Request*>& fr
     } else if (r->steps_done >= r->nsteps) {
       r->status = r->nonconv ? IRKGL16_ENOCONV : IRKGL16_OK;
       r->finish = true;
+    }
+  }
+  // measured time per step of each class (the longest advance in the class)
+  for (size_t k = 0; k < cls_list.size(); ++k) {
+    const auto& key = cls_list[k].first;
+    int64_t adv = 0;
+    for (int i = 0; i < cls_list[k].second.second; ++i) {
+      const Request* r = resident[queue[cls_list[k].second.first + i]];
+      adv = std::max<int64_t>(adv, r->steps_done - r->old_steps);
+    }
+    float ms = 0.f;
+    if (adv > 0 && hipEventElapsedTime(&ms, cls_ev[2 * k], cls_ev[2 * k + 1]) == hipSuccess) {
+      const double us = 1e3 * ms / (double)adv;
+      auto it = step_us.find(key);
+      step_us[key] = it == step_us.end() ? us : 0.5 * (it->second + us);
     }
   }
   return IRKGL16_OK;
@@ -461,6 +522,7 @@ int irkgl16_server_create(irkgl16_server** out, const irkgl16_server_options* op
     std::unique_ptr<irkgl16_server> s(new irkgl16_server());
     s->opt = *opt;
     if (s->opt.slice_steps <= 0) s->opt.slice_steps = 1000;
+    if (!(s->opt.slice_ms > 0.0)) s->opt.slice_ms = 20.0;
     if (s->opt.max_iter <= 0) s->opt.max_iter = 100;
     if (s->opt.max_resident <= 0) s->opt.max_resident = 65536;
     s->device = dev;

@@ -50,7 +50,7 @@ class irkgl16_stats(C.Structure):
 
 class irkgl16_server_options(C.Structure):
     _fields_ = [("cap_bytes", C.c_int64), ("slice_steps", C.c_int64), ("max_iter", C.c_int32),
-                ("max_resident", C.c_int32), ("flags", C.c_uint32)]
+                ("max_resident", C.c_int32), ("flags", C.c_uint32), ("slice_ms", C.c_double)]
 
 
 class irkgl16_request_info(C.Structure):
@@ -261,9 +261,9 @@ def _problem_struct(p, keep):
 
 
 def irkgl16_server_create(cap_bytes, slice_steps=0, max_iter=0, max_resident=0, flags=0,
-                          stream=None):
+                          stream=None, slice_ms=0.0):
     opt = irkgl16_server_options(int(cap_bytes), int(slice_steps), int(max_iter),
-                                 int(max_resident), int(flags))
+                                 int(max_resident), int(flags), float(slice_ms))
     if stream is not None and hasattr(stream, "cuda_stream"):
         stream = stream.cuda_stream
     srv = C.c_void_p()
@@ -316,9 +316,9 @@ class Server:
     """Owns one serving thread (continuous batching)."""
 
     def __init__(self, cap_bytes=1 << 30, slice_steps=1000, max_iter=0, max_resident=0, flags=0,
-                 stream=None):
+                 stream=None, slice_ms=0.0):
         self.srv = irkgl16_server_create(cap_bytes, slice_steps, max_iter, max_resident, flags,
-                                         stream)
+                                         stream, slice_ms)
         self._dq = {}
 
     def submit(self, problem, q0, p0, h, nsteps, out_stride):

@@ -23,10 +23,11 @@ def _problem(inst):
     return p
 
 
-def run_stream(requests, cap_bytes=64 << 30, slice_steps=1000, keep_frames=False, flags=0):
+def run_stream(requests, cap_bytes=64 << 30, slice_steps=1000, keep_frames=False, flags=0,
+               slice_ms=0.0):
     """requests: list of (arrival_time_s, instance) with instance['nsteps'],
     ['stride'], ['h'].  Returns dict with per-request latency and totals."""
-    srv = K.Server(cap_bytes=cap_bytes, slice_steps=slice_steps, flags=flags)
+    srv = K.Server(cap_bytes=cap_bytes, slice_steps=slice_steps, flags=flags, slice_ms=slice_ms)
     tickets = [None] * len(requests)
     results = [None] * len(requests)
     t0 = time.perf_counter()
