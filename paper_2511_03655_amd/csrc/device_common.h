@@ -50,9 +50,10 @@ struct InstStat {
 // Coefficient table in device memory, read with wave-uniform (scalar) loads so
 // that the 8x8 tables live in SGPRs/scalar cache rather than as materialised
 // 64-bit immediates in vector registers.  Layout (doubles):
-// [0,8) c, [8,16) b, [16,80) eta, [80,144) mu, [144,208) nu (row-major, row =
-// stage formed, column = stage summed over).
-constexpr int kTabC = 0, kTabB = 8, kTabEta = 16, kTabMu = 80, kTabNu = 144, kTabSize = 208;
+// [0,8) c, [8,16) b, [16,80) eta, [80,144) mu, [144,208) nu, [208,272) K
+// (row-major, row = stage formed, column = stage summed over).
+constexpr int kTabC = 0, kTabB = 8, kTabEta = 16, kTabMu = 80, kTabNu = 144, kTabK = 208,
+              kTabSize = 272;
 
 // Pointer into the constant address space: loads through it with uniform
 // indices become scalar (SMEM) loads.
@@ -124,12 +125,28 @@ __device__ __forceinline__ bool stop_component(double delta, double& mind, doubl
   return ok;
 }
 
+__device__ __forceinline__ bool finite(double x) { return x - x == 0.0; }
+
 // NaN-keeping running maximum of |differences|.
 __device__ __forceinline__ double max_keep_nan(double acc, double a) {
   return (a != a || a > acc) ? a : acc;
 }
 
-__device__ __forceinline__ bool finite(double x) { return x - x == 0.0; }
+// Running maximum of non-negative increments with non-finite tracking: fmax
+// (one instruction) drops a NaN operand, so non-finite increments are recorded
+// in `nf` instead (d * 0 is NaN exactly when d is not finite; otherwise nf
+// stays +0).  The maximum of finite increments is exact, as with
+// max_keep_nan.
+__device__ __forceinline__ void max_track(double& acc, double& nf, double d) {
+  acc = fmax(acc, d);
+  nf = fma(d, 0.0, nf);
+}
+
+// True when the tracked maximum is finite and no non-finite increment occurred.
+__device__ __forceinline__ bool track_finite(double acc, double nf) {
+  return finite(acc) && nf == 0.0;
+}
+
 
 // ---------------------------------------------------------------------------
 // Arithmetic policies.  EXACT = false: fused multiply-adds and the refined
@@ -155,16 +172,17 @@ __device__ __forceinline__ double row_dot(ConstTab w, int off, const double (&x)
   }
 }
 
-// Stage value q + h (c_s v + sum_j eta_sj R_j)  (eqs. Qi2 / IRK_FP2).
+// Stage value q + h (c_s v + sum_j M_sj R_j) with M = eta (eqs. Qi2 /
+// IRK_FP2), or M = K for the folded initial guess.
 template <bool EXACT>
 __device__ __forceinline__ double stage_value(ConstTab w, int s, double q, double v, double h,
-                                              const double (&R)[kS]) {
+                                              const double (&R)[kS], int mat = kTabEta) {
   if constexpr (EXACT) {
-    return q + h * (w[kTabC + s] * v + row_dot<true>(w, kTabEta + s * kS, R));
+    return q + h * (w[kTabC + s] * v + row_dot<true>(w, mat + s * kS, R));
   } else {
     double acc = w[kTabC + s] * v;
 #pragma unroll
-    for (int j = 0; j < kS; ++j) acc = fma(w[kTabEta + s * kS + j], R[j], acc);
+    for (int j = 0; j < kS; ++j) acc = fma(w[mat + s * kS + j], R[j], acc);
     return fma(h, acc, q);
   }
 }
@@ -199,11 +217,23 @@ __device__ __forceinline__ double pair_weight(double r2, double m) {
 
 // Initial guess for the owned components from their previous-step increments
 // Rp (eq. IRK_init2): V0_i = v + sum_j nu_ij Rp_j, L0_j = h b_j V0_j,
-// Q_i = q + sum_j mu_ij L0_j.  Rows of nu and mu are fetched one at a time.
+// Q_i = q + sum_j mu_ij L0_j, in that order with EXACT.  The fused mode
+// evaluates the same linear map folded into one matrix,
+// Q_i = q + h (c_i v + sum_j K_ij Rp_j) with K = A W diag(1/b) (80 instead of
+// 144 operations per component).  Rows are fetched one at a time.
 template <int CPL, bool EXACT>
 __device__ __forceinline__ void initial_guess(ConstTab T, const double (&qh)[CPL],
                                               const double (&vh)[CPL], const double (&Rp)[CPL][kS],
                                               double h, double (&Q)[CPL][kS]) {
+  if constexpr (!EXACT) {
+#pragma unroll
+    for (int s = 0; s < kS; ++s) {
+      const ConstTab r = row_tab(T);
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc) Q[cc][s] = stage_value<false>(r, s, qh[cc], vh[cc], h, Rp[cc], kTabK);
+    }
+    return;
+  }
   double L0[CPL][kS];
 #pragma unroll
   for (int s = 0; s < kS; ++s) {

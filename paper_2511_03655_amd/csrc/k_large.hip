@@ -122,10 +122,11 @@ __device__ __forceinline__ unsigned grid_barrier(unsigned* ctl, unsigned& gen, u
   return *res;
 }
 
-// NaN-keeping maximum over the 8 stage lanes of a target.
+// Maximum over the 8 stage lanes of a target; a non-finite operand is
+// detected by the caller (finite() of its own increment), since fmax drops NaN.
 __device__ __forceinline__ double lg_group_max(double x) {
 #pragma unroll
-  for (int m = 1; m < kS; m <<= 1) x = max_keep_nan(x, __shfl_xor(x, m, kS));
+  for (int m = 1; m < kS; m <<= 1) x = fmax(x, __shfl_xor(x, m, kS));
   return x;
 }
 
@@ -139,6 +140,12 @@ __device__ __forceinline__ void lg_wave_lds_sync() {
 template <bool EXACT>
 __device__ __forceinline__ double lg_guess(ConstTab T, int s, double q, double v,
                                            const double (&Rp)[kS], double h) {
+  if constexpr (!EXACT) {  // folded matrix K, as initial_guess
+    double acc = T[kTabC + s] * v;
+#pragma unroll
+    for (int j = 0; j < kS; ++j) acc = fma(T[kTabK + s * kS + j], Rp[j], acc);
+    return fma(h, acc, q);
+  }
   double L0[kS];
 #pragma unroll
   for (int j = 0; j < kS; ++j) {
@@ -425,8 +432,9 @@ __global__ __launch_bounds__(LargeCfg<NCH>::kThreads) void large_kernel(LargeArg
             for (int j = 0; j < kS; ++j) acc = fma(coef[s][j], Rj[j], acc);
             qn = fma(h, acc, qh);
           }
-          const double dmax = lg_group_max(fabs(qn - tq[g][d][lane]));
-          bad |= !finite(dmax);
+          const double dd = fabs(qn - tq[g][d][lane]);
+          bad |= !finite(dd);
+          const double dmax = lg_group_max(dd);
           double mind = S.mind[t][d], prv = S.prv[t][d];
           ok &= stop_component(dmax, mind, prv);
           // tentative compensated update and the next step's initial guess

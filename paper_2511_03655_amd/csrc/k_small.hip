@@ -243,10 +243,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
       __syncthreads();
       bool ok = true, bad = false;
       if (!conv) {
-        double R[CPL][kS], dmax[CPL];
+        double R[CPL][kS], dmax[CPL], nf[CPL];
 #pragma unroll
         for (int cc = 0; cc < CPL; ++cc) {
           dmax[cc] = 0.0;
+          nf[cc] = 0.0;
 #pragma unroll
           for (int s = 0; s < kS; ++s) R[cc][s] = Xs[cidx(cc) * kS + s];
         }
@@ -256,14 +257,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
 #pragma unroll
           for (int cc = 0; cc < CPL; ++cc) {
             const double qn = stage_value<EXACT>(r, s, qh[cc], vh[cc], h, R[cc]);
-            dmax[cc] = max_keep_nan(dmax[cc], fabs(qn - Qc[cc][s]));
+            max_track(dmax[cc], nf[cc], fabs(qn - Qc[cc][s]));
             Qc[cc][s] = qn;
           }
         }
 #pragma unroll
         for (int cc = 0; cc < CPL; ++cc) {
           if (owns(cc)) {
-            bad |= !finite(dmax[cc]);
+            bad |= !track_finite(dmax[cc], nf[cc]);
             ok &= stop_component(dmax[cc], mind[cc], prv[cc]);
           }
         }

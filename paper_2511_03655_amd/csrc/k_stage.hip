@@ -42,10 +42,12 @@ size_t stage_lds_doubles(int np) {
   return (size_t)3 * np * kS * P + np;
 }
 
-// NaN-keeping maximum over the 8 stage lanes of a body (lanes 8u .. 8u+7).
+// Maximum over the 8 stage lanes of a body (lanes 8u .. 8u+7); a non-finite
+// operand is detected by the caller (finite() of its own increment), since
+// fmax drops NaN.
 __device__ __forceinline__ double stage_group_max(double x) {
 #pragma unroll
-  for (int m = 1; m < kS; m <<= 1) x = max_keep_nan(x, __shfl_xor(x, m, kS));
+  for (int m = 1; m < kS; m <<= 1) x = fmax(x, __shfl_xor(x, m, kS));
   return x;
 }
 
@@ -59,10 +61,17 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // Own stage of the initial guess (eq. IRK_init2): L0_j = h b_j (v + sum_i nu_ji
 // Rp_i) for all j, then Q_s = q + sum_j mu_sj L0_j; the same operations as the
-// all-stage form, evaluated for one s.
+// all-stage form, evaluated for one s (the fused mode uses the folded matrix K
+// as initial_guess does).
 template <bool EXACT>
 __device__ __forceinline__ double stage_guess(ConstTab T, int s, double q, double v,
                                               const double (&Rp)[kS], double h) {
+  if constexpr (!EXACT) {
+    double acc = T[kTabC + s] * v;
+#pragma unroll
+    for (int j = 0; j < kS; ++j) acc = fma(T[kTabK + s * kS + j], Rp[j], acc);
+    return fma(h, acc, q);
+  }
   double L0[kS];
 #pragma unroll
   for (int j = 0; j < kS; ++j) {
@@ -244,10 +253,11 @@ __global__ __launch_bounds__(8 * NPMAX) void stage_kernel(LaunchArgs a, int np) 
 #pragma unroll
             for (int j = 0; j < kS; ++j) Rj[j] = Rt[(u * kS + j) * P + d];
             const double qn = stage_value_row<EXACT>(eta, cs, qh[d], vh[d], h, Rj);
-            const double dmax = stage_group_max(fabs(qn - Qo[d]));
+            const double dd = fabs(qn - Qo[d]);
+            nf |= !finite(dd);
+            const double dmax = stage_group_max(dd);
             Qo[d] = qn;
             Qn_t[((size_t)u * kS + s) * P + d] = qn;
-            nf |= !finite(dmax);
             ok &= stop_component(dmax, mind[d], prv[d]);
           }
           if (!ok) ctl[1 + (int)(gk % 3)] = 1;

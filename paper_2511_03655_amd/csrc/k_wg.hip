@@ -230,21 +230,21 @@ __global__ __launch_bounds__(MAXT) void wg_kernel(LaunchArgs a, int S) {
         unit_increments<KIND, D, EXACT>(Qs, Ms, base, u, n, M, kl, kr, T, h, R);
         const double* qa = Qs + (size_t)(base + u) * kS * D;
         bool ok = true, bad = false;
-        double dmax[D];
+        double dmax[D], nf[D];
 #pragma unroll
-        for (int d = 0; d < D; ++d) dmax[d] = 0.0;
+        for (int d = 0; d < D; ++d) dmax[d] = nf[d] = 0.0;
 #pragma unroll
         for (int s = 0; s < kS; ++s) {
           const ConstTab r = row_tab(T);
 #pragma unroll
           for (int d = 0; d < D; ++d) {
             Qn[d][s] = stage_value<EXACT>(r, s, qh[d], vh[d], h, R[d]);
-            dmax[d] = max_keep_nan(dmax[d], fabs(Qn[d][s] - qa[s * D + d]));
+            max_track(dmax[d], nf[d], fabs(Qn[d][s] - qa[s * D + d]));
           }
         }
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-          bad |= !finite(dmax[d]);
+          bad |= !track_finite(dmax[d], nf[d]);
           ok &= stop_component(dmax[d], mind[d], prv[d]);
         }
         if (!ok) M.notok = 1;

@@ -281,6 +281,7 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
         tab[irk::kTabEta + i * irk::kS + j] = irk::kEta[i][j];
         tab[irk::kTabMu + i * irk::kS + j] = irk::kMu[i][j];
         tab[irk::kTabNu + i * irk::kS + j] = irk::kNu[i][j];
+        tab[irk::kTabK + i * irk::kS + j] = irk::kK[i][j];
       }
     }
     if ((rc = alloc_try(c->d_tab, sizeof(double) * tab.size()))) return fail(rc);

@@ -544,6 +544,7 @@ int irkgl16_server_create(irkgl16_server** out, const irkgl16_server_options* op
         tab[irk::kTabEta + i * irk::kS + j] = irk::kEta[i][j];
         tab[irk::kTabMu + i * irk::kS + j] = irk::kMu[i][j];
         tab[irk::kTabNu + i * irk::kS + j] = irk::kNu[i][j];
+        tab[irk::kTabK + i * irk::kS + j] = irk::kK[i][j];
       }
     }
     if (hipMemcpy(s->d_tab.p, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice) !=

@@ -88,6 +88,25 @@ def test_product_table_matches_oracle_table(orc):
         assert np.array_equal(grab(name), t[key].ravel()), key
 
 
+def test_folded_guess_matrix_matches_oracle_tableau():
+    """The product's folded initial-guess matrix K = A W diag(1/b) (fused
+    arithmetic mode) equals, entry by entry, the correctly rounded value of the
+    same product formed from the oracle's independent high-precision tableau
+    (eq. IRK_init2 with mu_sj b_j = a_sj and row sums of A equal to c)."""
+    import mpmath
+    from oracle import tableau as T
+    src = open(os.path.join(ROOT, "paper_2511_03655_amd", "csrc", "irkgl16_coeffs.h")).read()
+    m = re.search(r"kK\[8\]\[8\] = \{(.*?)\};", src, re.S)
+    k = np.array([float.fromhex(x) for x in re.findall(r"-?0x[0-9a-fp.+-]+", m.group(1))])
+    ex = T.exact_tableau()
+    with mpmath.workdps(T.DPS):
+        want = [T.rne(mpmath.fsum(ex["A"][s][j] * ex["W"][j][i] for j in range(8)) / ex["b"][i])
+                for s in range(8) for i in range(8)]
+        rows = [mpmath.fsum(ex["A"][s][j] for j in range(8)) - ex["c"][s] for s in range(8)]
+    assert np.array_equal(k, np.array(want, dtype=np.float64))
+    assert max(abs(float(r)) for r in rows) < 1e-90  # row sums of A are c
+
+
 def test_graft_entry_build_compiles_everything(tmp_path):
     import importlib
     ge = importlib.import_module("__graft_entry__")
