@@ -224,6 +224,11 @@ def main():
         t = time.perf_counter()
         _, _, pst, _ = pi.integrate(q0[:n_p * dq], p0[:n_p * dq], H, s_p, s_p)
         dtp = time.perf_counter() - t
+        gi = K.Integrator(probs[:n_p], flags=K.IRKGL16_PLAIN | K.IRKGL16_GRAPH)
+        gi.integrate(q0[:n_p * dq], p0[:n_p * dq], H, 20, 20)
+        t = time.perf_counter()
+        gi.integrate(q0[:n_p * dq], p0[:n_p * dq], H, s_p, s_p)
+        dtg = time.perf_counter() - t
         bi = K.Integrator(probs[:n_p])
         bi.integrate(q0[:n_p * dq], p0[:n_p * dq], H, 20, 20)
         t = time.perf_counter()
@@ -231,9 +236,11 @@ def main():
         dtb = time.perf_counter() - t
         plain = dict(value=n_p * s_p / dtp, unit="instance-steps/s",
                      sample=f"{n_p} instances x {s_p} steps, one launch per step per instance",
+                     graph_replay=n_p * s_p / dtg,
                      batched_same_sample=n_p * s_p / dtb,
                      full_batch_speedup=value / (n_p * s_p / dtp))
         pi.close()
+        gi.close()
         bi.close()
 
     repro = None

@@ -59,6 +59,12 @@ extern "C" {
  * level, and the fixed-point iteration counts, which are decided at rounding
  * level, may differ). */
 #define IRKGL16_REPRODUCIBLE 4u
+/* With IRKGL16_PLAIN: the launches of one step (one per instance) are
+ * captured once into a HIP graph and the graph is replayed once per step
+ * (instances that have finished do no work in later replays); launches of
+ * whole-GPU (cooperative) instances stay outside the graph.  Results are
+ * bit-identical to IRKGL16_PLAIN. */
+#define IRKGL16_GRAPH 8u
 
 typedef struct irkgl16_ctx irkgl16_ctx;
 

@@ -281,7 +281,12 @@ __global__ __launch_bounds__(LargeCfg<NCH>::kThreads) void large_kernel(LargeArg
   if (st0.status != kOk) target = step;
   int64_t it_sum = st0.iterations, nonconv = st0.nonconv;
   int32_t maxk = st0.max_k;
+  // barrier generation: continue from the release word left by the previous
+  // launch (nobody can advance it before every workgroup has arrived once)
   unsigned gen = 0;
+  if (tid == 0)
+    gen = __hip_atomic_load(L.ctl + (kBarSub + 1) * kLine, __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_AGENT) >> 2;
 
   for (int e = tid; e < kS * kS; e += NT) coef[e / kS][e % kS] = a.tab[kTabEta + e];
   if (tid < kS) {
@@ -552,11 +557,16 @@ bool large_class_supported(int kind, int n, int d) {
   return kind == kGravity && d == 3 && n > 1 && n <= kLgMaxBodies;
 }
 
-// Device scratch for a system of n bodies: three position buffers and the
-// control words.
+// Device scratch for a system of n bodies: the control words (at a fixed
+// offset, zeroed once when the buffer is allocated: every barrier leaves its
+// counters at zero and the release word carries over between launches), then
+// three position buffers.
+constexpr size_t kCtlBytes = 4096;
+static_assert(sizeof(unsigned) * kCtlWords <= kCtlBytes, "control block");
 size_t large_scratch_bytes(int n, int /*nchunks*/) {
-  return sizeof(double) * (size_t)3 * n * kS * 4 + sizeof(unsigned) * kCtlWords;
+  return kCtlBytes + sizeof(double) * (size_t)3 * n * kS * 4;
 }
+size_t large_control_bytes() { return kCtlBytes; }
 
 // Source chunks (wavefronts per workgroup): 16, or 1 in reproducible mode.
 int large_chunks(int /*n*/, bool exact, int /*num_cus*/) { return exact ? 1 : 16; }
@@ -590,12 +600,8 @@ hipError_t launch_large(const LaunchArgs& a, int inst, int n, void* scratch, int
   L.ngroups = (n + kLgT - 1) / kLgT;
   L.gpw = 1;
   char* p = static_cast<char*>(scratch);
-  L.pos = reinterpret_cast<double*>(p);
-  p += sizeof(double) * (size_t)3 * n * kS * 4;
   L.ctl = reinterpret_cast<unsigned*>(p);
-  // barrier counters and the release word start from zero for every launch
-  hipError_t e = hipMemsetAsync(p, 0, sizeof(unsigned) * kCtlWords, st);
-  if (e != hipSuccess) return e;
+  L.pos = reinterpret_cast<double*>(p + kCtlBytes);
   if (a.exact) return launch_large_t<true, 1>(L, num_cus, st);
   return launch_large_t<false, 16>(L, num_cus, st);
 }

@@ -20,6 +20,7 @@ bool wg_class_supported(int kind, int n, int d);
 int wg_slot_size(int n);
 bool large_class_supported(int kind, int n, int d);
 size_t large_scratch_bytes(int n, int nchunks);
+size_t large_control_bytes();  // leading bytes of the scratch to zero once at allocation
 int large_chunks(int n, bool exact, int num_cus);
 hipError_t launch_large(const LaunchArgs& a, int inst, int n, void* scratch, int nchunks,
                         int num_cus, hipStream_t st);

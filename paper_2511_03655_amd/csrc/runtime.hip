@@ -260,9 +260,11 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
     return fail(IRKGL16_EDEVICE);
 
   int rc;
-  if (c->large_nmax > 0 &&
-      (rc = alloc_try(c->d_large, irk::large_scratch_bytes(c->large_nmax, 16))))
-    return fail(rc);
+  if (c->large_nmax > 0) {
+    if ((rc = alloc_try(c->d_large, irk::large_scratch_bytes(c->large_nmax, 16)))) return fail(rc);
+    if (hipMemset(c->d_large.p, 0, irk::large_control_bytes()) != hipSuccess)
+      return fail(IRKGL16_EDEVICE);
+  }
   if ((rc = alloc_try(c->d_desc, sizeof(irk::InstDesc) * (size_t)std::max(n_inst, 1))) ||
       (rc = alloc_try(c->d_stat, sizeof(irk::InstStat) * (size_t)std::max(n_inst, 1))) ||
       (rc = alloc_try(c->d_state, sizeof(double) * (size_t)std::max<int64_t>(state_off, 1))) ||
@@ -298,7 +300,7 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
                 hipMemcpyHostToDevice) != hipSuccess)
     return fail(IRKGL16_EDEVICE);
   // Auxiliary streams: the classes' persistent kernels run concurrently.
-  const int n_aux = std::min<int>((int)c->classes.size(), irkgl16_ctx::kMaxAux);
+  const int n_aux = irkgl16_ctx::kMaxAux;
   for (int k = 0; k < n_aux; ++k) {
     hipStream_t sk;
     hipEvent_t ek;
@@ -350,6 +352,86 @@ static hipError_t launch_class(irkgl16_ctx* c, const KernelClass& kc, const irk:
     return hipSuccess;
   }
   return irk::launch_batched(kc.cls, kc.kind, kc.size, kc.d, a, n_items, c->num_cus, st);
+}
+
+// Plain form, graph replay: capture one single-step launch per instance (all
+// batched classes, as parallel branches), then replay the graph once per step;
+// the kernels read each instance's progress from device memory and do nothing
+// for an instance that has reached its step count.  Cooperative (whole-GPU)
+// launches are issued directly after each replay.
+static hipError_t plain_graph_steps(irkgl16_ctx* c, const irk::LaunchArgs& a,
+                                    const int64_t* nsteps) {
+  int64_t smax = 0;
+  bool any_batched = false, any_large = false;
+  for (const auto& kc : c->classes)
+    for (int32_t id : kc.ids) {
+      smax = std::max(smax, nsteps[id]);
+      (kc.cls == irk::kClassLarge ? any_large : any_batched) = true;
+    }
+  if (smax == 0) return hipSuccess;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipError_t e = hipSuccess;
+  if (any_batched) {
+    // The step's launches are independent of each other: they are captured as
+    // parallel branches (round robin over the auxiliary streams, forked from
+    // and joined back into the context stream).
+    e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return e;
+    const int nb = std::max<int>(1, (int)c->aux.size());
+    std::vector<char> used(c->aux.size(), 0);
+    if (!c->aux.empty()) e = hipEventRecord(c->ev_fork, c->stream);
+    int next = 0;
+    for (const auto& kc : c->classes) {
+      if (kc.cls == irk::kClassLarge) continue;
+      for (int32_t id : kc.ids) {
+        irk::LaunchArgs pa = a;
+        pa.queue = c->d_plainq.as<int32_t>() + id;
+        pa.queue_len = 1;
+        pa.queue_head = nullptr;
+        pa.step_budget = 1;
+        hipStream_t sj = c->stream;
+        if (!c->aux.empty()) {
+          const int j = next++ % nb;
+          sj = c->aux[j];
+          if (e == hipSuccess && !used[j]) e = hipStreamWaitEvent(sj, c->ev_fork, 0);
+          used[j] = 1;
+        }
+        if (e == hipSuccess) e = launch_class(c, kc, pa, 1, sj);
+      }
+    }
+    for (size_t j = 0; j < c->aux.size(); ++j) {
+      if (!used[j] || e != hipSuccess) continue;
+      e = hipEventRecord(c->aux_done[j], c->aux[j]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, c->aux_done[j], 0);
+    }
+    const hipError_t ec = hipStreamEndCapture(c->stream, &graph);
+    if (e == hipSuccess) e = ec;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  }
+  for (int64_t s = 0; s < smax && e == hipSuccess; ++s) {
+    if (exec) e = hipGraphLaunch(exec, c->stream);
+    if (!any_large) continue;
+    for (const auto& kc : c->classes) {
+      if (kc.cls != irk::kClassLarge) continue;
+      for (int32_t id : kc.ids) {
+        if (s >= nsteps[id] || e != hipSuccess) continue;
+        irk::LaunchArgs pa = a;
+        pa.queue = c->d_plainq.as<int32_t>() + id;
+        pa.queue_len = 1;
+        pa.queue_head = nullptr;
+        pa.step_budget = 1;
+        e = launch_class(c, kc, pa, 1, c->stream);
+      }
+    }
+  }
+  if (exec) {
+    const hipError_t es = hipStreamSynchronize(c->stream);  // graph done before destroy
+    if (e == hipSuccess) e = es;
+    (void)hipGraphExecDestroy(exec);
+  }
+  if (graph) (void)hipGraphDestroy(graph);
+  return e;
 }
 
 static int integrate_impl(irkgl16_ctx* c, const double* q0, const double* p0, const double* h,
@@ -419,7 +501,11 @@ static int integrate_impl(irkgl16_ctx* c, const double* q0, const double* p0, co
                               dpo, c->record ? c->d_iters.as<uint8_t>() : nullptr,
                               c->d_heads.as<int32_t>(), (int)c->classes.size(), n, c->stream));
   irk::LaunchArgs a = base_args(c, dqo, dpo);
-  if (c->flags & IRKGL16_PLAIN) {
+  if ((c->flags & IRKGL16_PLAIN) && (c->flags & IRKGL16_GRAPH)) {
+    // Plain form with the step loop in a graph: one step's launches (one per
+    // instance, single-step budget) captured once, replayed max(nsteps) times.
+    HIP_TRY(plain_graph_steps(c, a, nsteps));
+  } else if (c->flags & IRKGL16_PLAIN) {
     // Plain form: one launch per step per instance, instances in turn.
     for (const auto& kc : c->classes) {
       for (int32_t id : kc.ids) {

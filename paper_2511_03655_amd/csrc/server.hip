@@ -462,7 +462,8 @@ void irkgl16_server::run() {
         po += (int64_t)r->mass.size();
         d.coupling_off = r->coupling.empty() ? -1 : po;
         if (r->cls == irk::kClassLarge && r->n > large_nmax) {
-          if (d_large.ensure(irk::large_scratch_bytes(r->n, 16))) {
+          if (d_large.ensure(irk::large_scratch_bytes(r->n, 16)) ||
+              hipMemset(d_large.p, 0, irk::large_control_bytes()) != hipSuccess) {
             device_error = IRKGL16_EDEVICE;
           }
           large_nmax = r->n;

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "libirkgl16.so")
 IRKGL16_OK, IRKGL16_EINVAL, IRKGL16_ENOMEM, IRKGL16_EDEVICE = 0, -1, -2, -3
 IRKGL16_ENONFINITE, IRKGL16_ENOCONV = -4, 1
 IRKGL16_KEPLER, IRKGL16_GRAVITY, IRKGL16_CHAIN = 0, 1, 2
-IRKGL16_DEVICE_PTRS, IRKGL16_PLAIN, IRKGL16_REPRODUCIBLE = 1, 2, 4
+IRKGL16_DEVICE_PTRS, IRKGL16_PLAIN, IRKGL16_REPRODUCIBLE, IRKGL16_GRAPH = 1, 2, 4, 8
 
 EXPORTED = ["irkgl16_create", "irkgl16_integrate", "irkgl16_last_stats", "irkgl16_destroy",
             "irkgl16_strerror", "irkgl16_server_create", "irkgl16_submit", "irkgl16_poll",
