@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libirkgl16.so")
-SOURCES = ["runtime.hip", "server.hip", "k_prepare.hip", "k_small.hip", "k_wg.hip", "k_stage.hip",
+SOURCES = ["runtime.hip", "server.hip", "tuning.cpp", "k_prepare.hip", "k_small.hip", "k_wg.hip", "k_stage.hip",
            "k_large.hip"]
 OBJDIR = os.path.join(HERE, "_build")
 

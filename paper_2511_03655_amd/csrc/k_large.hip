@@ -48,10 +48,10 @@ struct LargeArgs {
   unsigned* ctl;
 };
 
-template <int NCH>
+template <int NCH, int TILE>
 struct LargeCfg {
   static constexpr int kThreads = 64 * NCH;
-  static constexpr int kTile = NCH > 1 ? 256 : 64;    // sources per LDS tile
+  static constexpr int kTile = TILE;                  // sources per LDS tile
   static constexpr int kMaxGroups = NCH > 1 ? 4 : 1;  // groups per workgroup
 };
 
@@ -234,11 +234,11 @@ struct LgTargetState {
   double mind[kLgT][3], prv[kLgT][3];  // stopping-rule history
 };
 
-template <bool EXACT, int NCH>
-__global__ __launch_bounds__(LargeCfg<NCH>::kThreads) void large_kernel(LargeArgs L) {
-  constexpr int TB = LargeCfg<NCH>::kTile;
-  constexpr int NT = LargeCfg<NCH>::kThreads;
-  constexpr int GM = LargeCfg<NCH>::kMaxGroups;
+template <bool EXACT, int NCH, int TILE>
+__global__ __launch_bounds__(64 * NCH) void large_kernel(LargeArgs L) {
+  constexpr int TB = LargeCfg<NCH, TILE>::kTile;
+  constexpr int NT = LargeCfg<NCH, TILE>::kThreads;
+  constexpr int GM = LargeCfg<NCH, TILE>::kMaxGroups;
   constexpr int ENT = (TB * kS + NT - 1) / NT;  // tile entries staged per thread
   __shared__ double2 sxy[TB * kS];            // [b][s] (x, y)
   __shared__ double2 szm[TB * kS];            // [b][s] (z, m)
@@ -571,10 +571,10 @@ size_t large_control_bytes() { return kCtlBytes; }
 // Source chunks (wavefronts per workgroup): 16, or 1 in reproducible mode.
 int large_chunks(int /*n*/, bool exact, int /*num_cus*/) { return exact ? 1 : 16; }
 
-template <bool EXACT, int NCH>
+template <bool EXACT, int NCH, int TILE>
 static hipError_t launch_large_t(LargeArgs& L, int num_cus, hipStream_t st) {
-  auto kern = large_kernel<EXACT, NCH>;
-  constexpr int NT = LargeCfg<NCH>::kThreads;
+  auto kern = large_kernel<EXACT, NCH, TILE>;
+  constexpr int NT = LargeCfg<NCH, TILE>::kThreads;
   int per_cu = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, 0);
   if (e != hipSuccess) return e;
@@ -583,7 +583,7 @@ static hipError_t launch_large_t(LargeArgs& L, int num_cus, hipStream_t st) {
   // fewest groups per workgroup such that the grid is co-resident
   int gpw = (L.ngroups + cap - 1) / cap;
   if (gpw < 1) gpw = 1;
-  if (gpw > LargeCfg<NCH>::kMaxGroups) return hipErrorCooperativeLaunchTooLarge;
+  if (gpw > LargeCfg<NCH, TILE>::kMaxGroups) return hipErrorCooperativeLaunchTooLarge;
   L.gpw = gpw;
   const int grid = (L.ngroups + gpw - 1) / gpw;
   void* args[] = {&L};
@@ -591,7 +591,7 @@ static hipError_t launch_large_t(LargeArgs& L, int num_cus, hipStream_t st) {
 }
 
 hipError_t launch_large(const LaunchArgs& a, int inst, int n, void* scratch, int /*nchunks*/,
-                        int num_cus, hipStream_t st) {
+                        int num_cus, hipStream_t st, int tile) {
   if (n < 2 || n > kLgMaxBodies) return hipErrorInvalidValue;
   LargeArgs L;
   L.a = a;
@@ -602,8 +602,9 @@ hipError_t launch_large(const LaunchArgs& a, int inst, int n, void* scratch, int
   char* p = static_cast<char*>(scratch);
   L.ctl = reinterpret_cast<unsigned*>(p);
   L.pos = reinterpret_cast<double*>(p + kCtlBytes);
-  if (a.exact) return launch_large_t<true, 1>(L, num_cus, st);
-  return launch_large_t<false, 16>(L, num_cus, st);
+  if (a.exact) return launch_large_t<true, 1, 64>(L, num_cus, st);
+  if (tile == 128) return launch_large_t<false, 16, 128>(L, num_cus, st);
+  return launch_large_t<false, 16, 256>(L, num_cus, st);
 }
 
 }  // namespace irk

@@ -387,10 +387,14 @@ bool wg_class_supported(int kind, int n, int d) {
 }
 
 template <int KIND, int D>
-hipError_t launch_wg(const LaunchArgs& a, int S, int n_items, int num_cus, hipStream_t st) {
-  const int TT = wg_block_size(S);
-  const size_t lds = wg_lds_bytes(TT, S, D);
+hipError_t launch_wg(const LaunchArgs& a, int S, int n_items, int num_cus, hipStream_t st,
+                     int block) {
+  // tuned block: a multiple of the slot width and of 64, at least the slot
   constexpr int MAXT = (KIND == kGravity) ? 512 : 1024;
+  const int TT = (block >= S && block % S == 0 && block % 64 == 0 && block <= MAXT)
+                     ? block
+                     : wg_block_size(S);
+  const size_t lds = wg_lds_bytes(TT, S, D);
   if (TT > MAXT) return hipErrorInvalidConfiguration;
   auto kern = a.exact ? wg_kernel<KIND, D, true, MAXT> : wg_kernel<KIND, D, false, MAXT>;
   hipError_t e = hipFuncSetAttribute((const void*)kern,
@@ -410,10 +414,10 @@ hipError_t launch_wg(const LaunchArgs& a, int S, int n_items, int num_cus, hipSt
 
 // Class key: (kind, d, S).  n_items instances, all with slot size S.
 hipError_t launch_wg_class(int kind, int d, int S, const LaunchArgs& a, int n_items, int num_cus,
-                           hipStream_t st) {
+                           hipStream_t st, int block) {
   if (n_items <= 0) return hipSuccess;
-  if (kind == kGravity && d == 3) return launch_wg<kGravity, 3>(a, S, n_items, num_cus, st);
-  if (kind == kChain && d == 1) return launch_wg<kChain, 1>(a, S, n_items, num_cus, st);
+  if (kind == kGravity && d == 3) return launch_wg<kGravity, 3>(a, S, n_items, num_cus, st, block);
+  if (kind == kChain && d == 1) return launch_wg<kChain, 1>(a, S, n_items, num_cus, st, block);
   return hipErrorInvalidValue;
 }
 

@@ -4,9 +4,25 @@
 
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <string>
+
 #include "device_common.h"
 
 namespace irk {
+
+// Launch shapes picked by the autotuner (tuning.cpp); 0 = built-in default.
+struct LaunchTune {
+  int wg_block = 0;    // workgroup kernel: lanes per workgroup (systems per workgroup = block / slot)
+  int large_tile = 0;  // whole-GPU kernel: sources per LDS tile (128 or 256)
+};
+struct TuneTable {
+  std::map<std::string, int> values;
+  int get(const std::string& key, int dflt) const;
+};
+TuneTable load_tune_table();
+std::string wg_tune_key(int kind, int d, int S);
+std::string large_tune_key(int n);
 hipError_t launch_prepare(const InstDesc* desc, InstStat* stat, double* state,
                           const double* params, const double* q0, const double* p0, double* qout,
                           double* pout, uint8_t* step_iters, int32_t* heads, int n_heads,
@@ -15,7 +31,7 @@ hipError_t launch_small_class(int kind, int nb, int d, const LaunchArgs& a, int 
                               int num_cus, hipStream_t st);
 bool small_class_supported(int kind, int nb, int d);
 hipError_t launch_wg_class(int kind, int d, int S, const LaunchArgs& a, int n_items, int num_cus,
-                           hipStream_t st);
+                           hipStream_t st, int block = 0);
 bool wg_class_supported(int kind, int n, int d);
 int wg_slot_size(int n);
 bool large_class_supported(int kind, int n, int d);
@@ -23,7 +39,7 @@ size_t large_scratch_bytes(int n, int nchunks);
 size_t large_control_bytes();  // leading bytes of the scratch to zero once at allocation
 int large_chunks(int n, bool exact, int num_cus);
 hipError_t launch_large(const LaunchArgs& a, int inst, int n, void* scratch, int nchunks,
-                        int num_cus, hipStream_t st);
+                        int num_cus, hipStream_t st, int tile = 0);
 bool stage_class_supported(int kind, int n, int d);
 int stage_np(int n);
 hipError_t launch_stage_class(int d, int np, const LaunchArgs& a, int n_items, int num_cus,
@@ -58,10 +74,11 @@ inline int kernel_class(int kind, int n, int d, int* size) {
 
 // Launches the persistent kernel of a batched class over the queue in `a`.
 inline hipError_t launch_batched(int cls, int kind, int size, int d, const LaunchArgs& a,
-                                 int n_items, int num_cus, hipStream_t st) {
+                                 int n_items, int num_cus, hipStream_t st,
+                                 const LaunchTune& tune = LaunchTune()) {
   switch (cls) {
     case kClassSmall: return launch_small_class(kind, size, d, a, n_items, num_cus, st);
-    case kClassWg: return launch_wg_class(kind, d, size, a, n_items, num_cus, st);
+    case kClassWg: return launch_wg_class(kind, d, size, a, n_items, num_cus, st, tune.wg_block);
     case kClassStage: return launch_stage_class(d, size, a, n_items, num_cus, st);
     default: return hipErrorInvalidValue;
   }

@@ -28,6 +28,7 @@ namespace {
 struct KernelClass {
   int cls = -1;   // irk::kClass*
   int kind = 0, size = 0, d = 0;  // size: see irk::kernel_class
+  irk::LaunchTune tune;           // launch shape from the tuning table
   std::vector<int32_t> ids;
   int64_t queue_off = 0;
 };
@@ -115,6 +116,7 @@ struct irkgl16_ctx {
   std::vector<hipEvent_t> aux_done;
   hipEvent_t ev_fork = nullptr;
   std::vector<int32_t> h_queue;
+  irk::TuneTable tune;  // launch shapes (read at creation)
 
   // last call
   bool have_last = false;
@@ -241,6 +243,11 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
     }
     c->classes[ci].ids.push_back(i);
   }
+  // Launch shapes from the tuning table.
+  c->tune = irk::load_tune_table();
+  for (auto& kc : c->classes)
+    if (kc.cls == irk::kClassWg)
+      kc.tune.wg_block = c->tune.get(irk::wg_tune_key(kc.kind, kc.d, kc.size), 0);
   // Queue storage (filled per call, in longest-integration-first order).
   size_t queue_len = 0;
   for (auto& kc : c->classes) {
@@ -346,12 +353,13 @@ static hipError_t launch_class(irkgl16_ctx* c, const KernelClass& kc, const irk:
     for (int32_t id : ids) {
       const int n = c->desc[id].n;
       const int ch = irk::large_chunks(n, a.exact != 0, c->num_cus);
-      hipError_t e = irk::launch_large(a, id, n, c->d_large.p, ch, c->num_cus, st);
+      hipError_t e = irk::launch_large(a, id, n, c->d_large.p, ch, c->num_cus, st,
+                                       c->tune.get(irk::large_tune_key(n), 0));
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
   }
-  return irk::launch_batched(kc.cls, kc.kind, kc.size, kc.d, a, n_items, c->num_cus, st);
+  return irk::launch_batched(kc.cls, kc.kind, kc.size, kc.d, a, n_items, c->num_cus, st, kc.tune);
 }
 
 // Plain form, graph replay: capture one single-step launch per instance (all

@@ -139,6 +139,7 @@ struct irkgl16_server {
   // events around each class launch and smoothed over slices
   std::map<std::tuple<int, int, int, int>, double> step_us;
   std::vector<hipEvent_t> cls_ev;  // pairs: start, end
+  irk::TuneTable tune;             // launch shapes (read at creation)
   std::chrono::steady_clock::time_point t0;
 
   DevBuf d_tab, d_desc, d_stat, d_arena, d_in, d_stage_q, d_stage_p, d_queue, d_heads, d_ids,
@@ -342,7 +343,9 @@ int irkgl16_server::slice(std::vector<Request*>& live, std::vector<Request*>& fr
     if (!used[j]) SRV_TRY(hipStreamWaitEvent(aux[j], ev_fork, 0));
     used[j] = 1;
     SRV_TRY(hipEventRecord(cls_ev[2 * k], aux[j]));
-    SRV_TRY(irk::launch_batched(cls, kind, sz, d, a, a.queue_len, num_cus, aux[j]));
+    irk::LaunchTune tn;
+    if (cls == irk::kClassWg) tn.wg_block = tune.get(irk::wg_tune_key(kind, d, sz), 0);
+    SRV_TRY(irk::launch_batched(cls, kind, sz, d, a, a.queue_len, num_cus, aux[j], tn));
     SRV_TRY(hipEventRecord(cls_ev[2 * k + 1], aux[j]));
   }
   for (size_t j = 0; j < aux.size(); ++j) {
@@ -362,7 +365,8 @@ int irkgl16_server::slice(std::vector<Request*>& live, std::vector<Request*>& fr
       const int slot = queue[cls_list[k].second.first + i];
       Request* r = resident[slot];
       const int ch = irk::large_chunks(r->n, a.exact != 0, num_cus);
-      SRV_TRY(irk::launch_large(a, slot, r->n, d_large.p, ch, num_cus, st));
+      SRV_TRY(irk::launch_large(a, slot, r->n, d_large.p, ch, num_cus, st,
+                                tune.get(irk::large_tune_key(r->n), 0)));
     }
     SRV_TRY(hipEventRecord(cls_ev[2 * k + 1], st));
   }
@@ -524,6 +528,7 @@ int irkgl16_server_create(irkgl16_server** out, const irkgl16_server_options* op
     s->opt = *opt;
     if (s->opt.slice_steps <= 0) s->opt.slice_steps = 1000;
     if (!(s->opt.slice_ms > 0.0)) s->opt.slice_ms = 20.0;
+    s->tune = irk::load_tune_table();
     if (s->opt.max_iter <= 0) s->opt.max_iter = 100;
     if (s->opt.max_resident <= 0) s->opt.max_resident = 65536;
     s->device = dev;
