@@ -70,6 +70,19 @@ __device__ __forceinline__ ConstTab row_tab(ConstTab p) {
   return p;
 }
 
+// Wavefronts per CU that one batched class's persistent grid may occupy (the
+// classes of a call run concurrently; a class that filled every CU with its
+// own workgroups would lock the others out of LDS and wave slots).
+constexpr int kClassWavesPerCu = 8;
+
+// Workgroups per CU for a persistent grid of `waves_per_wg`-wave workgroups:
+// at most what the occupancy calculator allows and within the class budget.
+inline int class_blocks_per_cu(int occupancy_per_cu, int waves_per_wg) {
+  int b = kClassWavesPerCu / (waves_per_wg > 0 ? waves_per_wg : 1);
+  if (b < 1) b = 1;
+  return b < occupancy_per_cu ? b : occupancy_per_cu;
+}
+
 struct LaunchArgs {
   const double* tab;
   const InstDesc* desc;

@@ -382,7 +382,7 @@ hipError_t launch_small(const LaunchArgs& a, int n_items, int num_cus, hipStream
   if (e != hipSuccess) return e;
   if (per_cu < 1) per_cu = 1;
   const int want = (n_items + 7) / 8;
-  const int cap = per_cu * num_cus;
+  const int cap = class_blocks_per_cu(per_cu, 1) * num_cus;
   const int grid = want < cap ? want : cap;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(64), 0, st, a);
   return hipGetLastError();

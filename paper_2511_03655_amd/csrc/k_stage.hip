@@ -371,7 +371,7 @@ static hipError_t launch_stage_t(const LaunchArgs& a, int np, int n_items, int n
   e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, TT, lds);
   if (e != hipSuccess) return e;
   if (per_cu < 1) return hipErrorInvalidConfiguration;
-  const int cap = per_cu * num_cus;
+  const int cap = class_blocks_per_cu(per_cu, TT / 64) * num_cus;
   const int grid = n_items < cap ? n_items : cap;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(TT), lds, st, a, np);
   return hipGetLastError();

@@ -406,7 +406,7 @@ hipError_t launch_wg(const LaunchArgs& a, int S, int n_items, int num_cus, hipSt
   if (per_cu < 1) return hipErrorInvalidConfiguration;
   const int nslots = TT / S;
   const int want = (n_items + nslots - 1) / nslots;
-  const int cap = per_cu * num_cus;
+  const int cap = class_blocks_per_cu(per_cu, TT / 64) * num_cus;
   const int grid = want < cap ? want : cap;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(TT), lds, st, a, S);
   return hipGetLastError();
