@@ -10,13 +10,15 @@
  * Build: gcc -O2 -ffp-contract=off -fno-fast-math -fopenmp -shared -fPIC
  * (strict IEEE binary64: no contraction into fma, no reassociation).
  *
- * What one step computes (second-order problem q'' = g(q), v = q'):
+ * What one step computes (second-order problem q'' = g(q, t), v = q'; eq.
+ * ivp2, the force may depend on time):
  *   initial guess (section 2.5, eq. IRK_init2; eq. Pol0 for nu):
  *       V0_i = v + sum_j nu_ij R_prev_j
  *       L0_j = hb_j V0_j
  *       Q_i  = q + sum_j mu_ij L0_j
  *   fixed-point iteration k = 1, 2, ... (eq. IRK_FP2, eqs. Gi/Qi2):
- *       G_i  = g(Q_i)
+ *       G_i  = g(Q_i, t_i),  t_i = fl(fl((n-1) h) + fl(c_i h))  for step n
+ *              (the stage times t_{n-1} + c_i h of eq. IRK_FP, with t_0 = 0)
  *       R_i  = hb_i G_i                         (hb_i = fl(h b_i))
  *       Qn_i = q + h (c_i v + sum_j eta_ij R_j)
  *       Delta^l = max_i |Qn_i^l - Q_i^l|        (eq. Delta_n)
@@ -49,6 +51,9 @@ enum {
   ORC_HARMONIC = 10, /* g = -G q               */
   ORC_CONST = 11,    /* g = G (every component) */
   ORC_HENON = 12,    /* Henon-Heiles, Dq = 2    */
+  ORC_HENON_T = 13,  /* section 3.3's non-autonomous Henon-Heiles, Dq = 2:
+                        lambda = G, xi = beta                            */
+  ORC_DRIVEN = 14,   /* g = G cos(t) (every component)                   */
 };
 
 enum {
@@ -84,7 +89,8 @@ static double mass_of(const orc_problem *p, int body) {
 
 static double dV(double s, double beta) { return s + beta * (s * s * s); }
 
-void orc_force(const orc_problem *p, const double *Q, double *G) {
+/* g(Q, t); the autonomous kinds ignore t. */
+void orc_force_t(const orc_problem *p, const double *Q, double *G, double t) {
   const int n = p->n, d = p->d, Dq = n * d;
   switch (p->kind) {
   case ORC_KEPLER: {
@@ -134,8 +140,20 @@ void orc_force(const orc_problem *p, const double *Q, double *G) {
     G[0] = -Q[0] - 2.0 * Q[0] * Q[1];
     G[1] = -Q[1] - (Q[0] * Q[0] - Q[1] * Q[1]);
     break;
+  case ORC_HENON_T: {
+    /* dp1/dt = -q1 - 2 a q1 q2, dp2/dt = -q2 - a (q1^2 - q2^2), a = lambda + xi sin t */
+    double a = p->G + p->beta * sin(t);
+    G[0] = -Q[0] - 2.0 * a * Q[0] * Q[1];
+    G[1] = -Q[1] - a * (Q[0] * Q[0] - Q[1] * Q[1]);
+    break;
+  }
+  case ORC_DRIVEN:
+    for (int k = 0; k < Dq; ++k) G[k] = p->G * cos(t);
+    break;
   }
 }
+
+void orc_force(const orc_problem *p, const double *Q, double *G) { orc_force_t(p, Q, G, 0.0); }
 
 /* Hamiltonian H(q, p) of each problem (for energy-error pins). */
 double orc_energy(const orc_problem *pr, const double *q, const double *p) {
@@ -179,6 +197,12 @@ double orc_energy(const orc_problem *pr, const double *q, const double *p) {
     break;
   case ORC_HENON:
     U = 0.5 * (q[0] * q[0] + q[1] * q[1]) + q[0] * q[0] * q[1] - q[1] * q[1] * q[1] / 3.0;
+    break;
+  case ORC_HENON_T: /* at t = 0: a = lambda */
+    U = 0.5 * (q[0] * q[0] + q[1] * q[1]) + pr->G * (q[0] * q[0] * q[1] - q[1] * q[1] * q[1] / 3.0);
+    break;
+  case ORC_DRIVEN: /* at t = 0 */
+    for (int k = 0; k < Dq; ++k) U -= pr->G * q[k];
     break;
   }
   return T + U;
@@ -228,7 +252,8 @@ static int valid_problem(const orc_problem *p) {
     return 1;
   case ORC_CHAIN: return p->d == 1;
   case ORC_HARMONIC: case ORC_CONST: return 1;
-  case ORC_HENON: return p->n * p->d == 2;
+  case ORC_HENON: case ORC_HENON_T: return p->n * p->d == 2;
+  case ORC_DRIVEN: return 1;
   }
   return 0;
 }
@@ -292,7 +317,8 @@ int orc_integrate(const orc_problem *p, const double *q0, const double *p0, doub
       int k = 0, conv = 0;
       while (!conv && k < max_iter) {
         ++k;
-        for (int i = 0; i < S; ++i) orc_force(p, Q + i * Dq, G + i * Dq);
+        const double t_prev = (double)(n - 1) * h;
+        for (int i = 0; i < S; ++i) orc_force_t(p, Q + i * Dq, G + i * Dq, t_prev + ORC_C[i] * h);
         for (int i = 0; i < S; ++i)
           for (int l = 0; l < Dq; ++l) R[i * Dq + l] = hb[i] * G[i * Dq + l];
         for (int i = 0; i < S; ++i)

@@ -27,6 +27,7 @@ LIB_PATH = os.path.join(HERE, "liborc.so")
 SOURCES = ["irkgl16_oracle.c", "irkgl16_dd.c"]
 
 KEPLER, GRAVITY, CHAIN, HARMONIC, CONST, HENON = 0, 1, 2, 10, 11, 12
+HENON_T, DRIVEN = 13, 14  # time-dependent: lambda = G, xi = beta; g = G cos t
 FLAG_NO_COMPENSATION, FLAG_NAIVE_ETA, FLAG_NO_EXTRAPOLATION = 1, 2, 4
 OK, EINVAL, ENOMEM, ENONFINITE, ENOCONV = 0, -1, -2, -4, 1
 
@@ -75,6 +76,8 @@ def lib():
         L.orc_integrate_batch.restype = C.c_int
         L.orc_force.argtypes = [C.POINTER(Problem), dp, dp]
         L.orc_force.restype = None
+        L.orc_force_t.argtypes = [C.POINTER(Problem), dp, dp, C.c_double]
+        L.orc_force_t.restype = None
         L.orc_energy.argtypes = [C.POINTER(Problem), dp, dp]
         L.orc_energy.restype = C.c_double
         L.orc_dw_add.argtypes = [dp, dp, C.c_double]
@@ -183,12 +186,16 @@ def integrate_dd(spec, q0, p0, h, nsteps, stride=1, max_iter=200, want_iters=Fal
                 iters=None if it is None else it[:nsteps], rc=rc)
 
 
-def force(spec, Q):
+def force(spec, Q, t=None):
+    """g(Q) (or g(Q, t) for the time-dependent kinds)."""
     L = lib()
     Q = np.ascontiguousarray(Q, np.float64)
     G = np.empty_like(Q)
     pr = spec.struct()
-    L.orc_force(C.byref(pr), _dp(Q), _dp(G))
+    if t is None:
+        L.orc_force(C.byref(pr), _dp(Q), _dp(G))
+    else:
+        L.orc_force_t(C.byref(pr), _dp(Q), _dp(G), float(t))
     return G
 
 

@@ -248,6 +248,8 @@ def test_forces_are_minus_gradient(orc):
                  coupling=rng.uniform(0.5, 2.0, 10), beta=1.3),
         orc.Spec(orc.KEPLER, 1, 3, G=2.0),
         orc.Spec(orc.HENON, 1, 2),
+        orc.Spec(orc.HENON_T, 1, 2, G=0.7, beta=0.4),  # energy and force at t = 0
+        orc.Spec(orc.DRIVEN, 1, 3, G=-1.3),
     ]
     for sp in cases:
         Q = rng.standard_normal(sp.Dq) * 0.5 + (1.5 if sp.kind == orc.KEPLER else 0.0)
@@ -261,6 +263,68 @@ def test_forces_are_minus_gradient(orc):
             qm[l] -= e
             dU = (orc.energy(sp, qp, zero) - orc.energy(sp, qm, zero)) / (2 * e)
             assert abs(G[l] + dU / m[l]) < 1e-7 * (1 + abs(G[l])), (sp.kind, l)
+
+
+# ---------------------------------------------------------------- time-dependent forces
+
+def test_nonautonomous_henon_reduces_to_classic(orc):
+    """Section 3.3's system is the classic Henon-Heiles one for lambda = 1,
+    xi = 0: identical trajectories and iteration counts, bit for bit."""
+    q0, p0, h, n = [0.0, 0.3], [0.23380903889000242556, 0.2], 2 * np.pi / 64, 2000
+    a = orc.integrate(orc.Spec(orc.HENON, 1, 2), q0, p0, h, n, stride=50, want_iters=True)
+    b = orc.integrate(orc.Spec(orc.HENON_T, 1, 2, G=1.0, beta=0.0), q0, p0, h, n, stride=50,
+                      want_iters=True)
+    assert np.array_equal(a["q"], b["q"]) and np.array_equal(a["p"], b["p"])
+    assert np.array_equal(a["iters"], b["iters"])
+
+
+def test_henon_coupling_scaling_is_exact(orc):
+    """U_lambda(q) = |q|^2/2 + lambda (q1^2 q2 - q2^3/3) satisfies
+    U_lambda(q / lambda) = U_1(q) / lambda^2, so the lambda = 2 orbit from
+    (q0/2, p0/2) is the lambda = 1 orbit scaled by 1/2; with a power-of-two
+    factor every rounding scales too, so the match is exact."""
+    q0, p0, h, n = np.array([0.05, 0.3]), np.array([0.2, 0.2]), 0.2, 1500
+    one = orc.integrate(orc.Spec(orc.HENON_T, 1, 2, G=1.0), q0, p0, h, n, stride=25,
+                        want_iters=True)
+    two = orc.integrate(orc.Spec(orc.HENON_T, 1, 2, G=2.0), q0 / 2, p0 / 2, h, n, stride=25,
+                        want_iters=True)
+    assert np.array_equal(two["q"] * 2, one["q"]) and np.array_equal(two["p"] * 2, one["p"])
+    assert np.array_equal(one["iters"], two["iters"])
+
+
+@pytest.mark.parametrize("h", [0.5, -0.25])
+def test_driven_particle_follows_closed_form(orc, h):
+    """q'' = G cos t from t = 0: q = q0 + v0 t + G (1 - cos t), v = v0 + G sin t.
+    The stages are evaluated at t_{n-1} + c_i h (eq. IRK_FP), so each step is
+    the 8-point Gauss rule for the integral of cos: exact to rounding here;
+    evaluating at any other time is off by O(h)."""
+    G, n = 1.7, 400
+    sp = orc.Spec(orc.DRIVEN, 1, 2, G=G)
+    q0, v0 = np.array([0.5, -1.0]), np.array([0.25, 0.0])
+    r = orc.integrate(sp, q0, v0, h, n, stride=10, want_iters=True)
+    t = (np.arange(n // 10 + 1) * 10 * h)[:, None]
+    np.testing.assert_allclose(r["q"], q0 + v0 * t + G * (1 - np.cos(t)), rtol=0, atol=1e-12)
+    np.testing.assert_allclose(r["p"], v0 + G * np.sin(t), rtol=0, atol=1e-13)
+    assert r["iters"].max() <= 2  # g does not depend on q: exact after one iteration
+
+
+def test_nonautonomous_henon_energy_balance(orc):
+    """For H(q, p, t) = |p|^2/2 + |q|^2/2 + a(t) W(q), a = lambda + xi sin t,
+    W = q1^2 q2 - q2^3/3: dH/dt = xi cos(t) W(q(t)) along the orbit.  The
+    energy change over the run matches the time integral of the right side
+    (Simpson's rule on every-step frames)."""
+    lam, xi, h, n = 1.0, 0.3, 0.01, 4000
+    sp = orc.Spec(orc.HENON_T, 1, 2, G=lam, beta=xi)
+    r = orc.integrate(sp, [0.1, 0.2], [0.15, -0.1], h, n, stride=1)
+    q, p = r["q"], r["p"]
+    t = np.arange(n + 1) * h
+    W = q[:, 0] ** 2 * q[:, 1] - q[:, 1] ** 3 / 3
+    H = 0.5 * (p ** 2).sum(1) + 0.5 * (q ** 2).sum(1) + (lam + xi * np.sin(t)) * W
+    f = xi * np.cos(t) * W
+    integral = h / 3 * (f[0] + f[-1] + 4 * f[1:-1:2].sum() + 2 * f[2:-1:2].sum())
+    change = H[-1] - H[0]
+    assert abs(change) > 1e-4                 # the forcing does work
+    assert abs(change - integral) < 1e-9 * abs(change) + 1e-13
 
 
 # ---------------------------------------------------------------- building blocks
