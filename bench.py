@@ -142,7 +142,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-served", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "henon"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -299,7 +299,7 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": traffic_from_profile(
                          "small_kernel_c2_65536x6body",
-                         ["k_small.hip", "device_common.h", "k_prepare.hip"]),
+                         ["k_small.hip", "small_kernel.h", "device_common.h", "k_prepare.hip"]),
                      "kernel": "small_kernel<gravity, 6 bodies, d=3>",
                      "kernel_ms": float(np.mean(kernel_ms)),
                      "algorithmic_flops_per_launch": flops},
@@ -521,7 +521,75 @@ def run_c5(args):
                    {"rates": rows})
 
 
-OTHER_WORKLOADS = {"c1": run_c1, "c3": run_c3, "c4": run_c4, "c5": run_c5}
+def run_henon(args):
+    """Henon-Heiles ensemble through the run-time compiled user force."""
+    import torch
+    from paper_2511_03655_amd import irkgl16 as K
+    from paper_2511_03655_amd import user_forces as UF
+    from paper_2511_03655_amd import workloads as W
+    from oracle import oracle as orc
+    n_inst, nsteps, h = 262144, 10_000, 2 * np.pi / 64
+    q0, p0 = W.henon_heiles_ensemble(n_inst)
+    q0, p0 = q0.ravel(), p0.ravel()
+    stream = torch.cuda.Stream()
+    t = time.perf_counter()
+    integ = K.Integrator.user(UF.HENON_HEILES, 2, n_inst, flags=K.IRKGL16_DEVICE_PTRS,
+                              stream=stream)
+    t_compile = time.perf_counter() - t
+    ns = np.full(n_inst, nsteps, np.int64)
+    dt, st, rc, qo, po = _timed_gpu(integ, q0, p0, np.full(n_inst, h), ns, ns, reps=2)
+    inst_steps = n_inst * nsteps
+    k = st["iterations"] / inst_steps
+    # 8 flops per stage force evaluation (two components), the rest as c2's convention
+    flops = st["iterations"] * (8 * 8 + 8 * 2 * 21) + inst_steps * (8 * 2 * 36 + 50 * 2)
+    kern_s = st["device_ms"] / 1e3
+    q = qo.cpu().numpy().reshape(n_inst, 2, 2)
+    p = po.cpu().numpy().reshape(n_inst, 2, 2)
+
+    def hh_energy(q, p):
+        return 0.5 * (p ** 2).sum(-1) + 0.5 * (q ** 2).sum(-1) + q[..., 0] ** 2 * q[..., 1] \
+            - q[..., 1] ** 3 / 3
+
+    dE = np.abs(hh_energy(q[:, 1], p[:, 1]) / hh_energy(q[:, 0], p[:, 0]) - 1)
+    n_p, s_p = 64, 200
+    plain = K.Integrator.user(UF.HENON_HEILES, 2, n_p, flags=K.IRKGL16_PLAIN)
+    plain.integrate(q0[:2 * n_p], p0[:2 * n_p], h, 20, 20)
+    t = time.perf_counter()
+    plain.integrate(q0[:2 * n_p], p0[:2 * n_p], h, s_p, s_p)
+    dtp = time.perf_counter() - t
+    cpu = None
+    if not args.no_cpu:
+        n_c, s_c = 65536, 8000
+        specs = [orc.Spec(orc.HENON, 1, 2)] * n_c
+        orc.lib()
+        t = time.perf_counter()
+        orc.integrate_batch(specs, q0[:2 * n_c], p0[:2 * n_c], h, s_c, s_c)
+        dtc = time.perf_counter() - t
+        cpu = {"value": n_c * s_c / dtc, "unit": "instance-steps/s",
+               "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+               "kind": "oracle",
+               "sample": f"{n_c} instances x {s_c} steps ({dtc:.1f} s, OpenMP over instances)"}
+    return _common("instance-steps/s", inst_steps / dt,
+                   {"workload": f"{n_inst} Henon-Heiles orbits near q2=0.3, p2=0.2 at H=1/12, "
+                                f"h=2pi/64, {nsteps} steps, final state; force given as device "
+                                "source and compiled at run time"},
+                   {"seconds": dt, "compile_and_create_s": t_compile,
+                    "mean_iterations_per_step": k,
+                    "roofline": {"bound": "alu", "achieved": flops / kern_s / 1e12,
+                                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                 "frac": flops / kern_s / 1e12 / FP64_PEAK_TFLOPS,
+                                 "traffic": None, "kernel": "small_kernel<user, Dq=2> (hiprtc)",
+                                 "kernel_ms": st["device_ms"]},
+                    "accuracy": {"gate": "relative energy error first->last frame <= 1e-12",
+                                 "pass_frac": float(np.mean(dE <= 1e-12)),
+                                 "median_dE": float(np.median(dE))},
+                    "plain": {"value": n_p * s_p / dtp, "unit": "instance-steps/s",
+                              "sample": f"{n_p} instances x {s_p} steps, one launch per step "
+                                        "per instance"},
+                    "cpu_baseline": cpu})
+
+
+OTHER_WORKLOADS = {"c1": run_c1, "c3": run_c3, "c4": run_c4, "c5": run_c5, "henon": run_henon}
 
 
 if __name__ == "__main__":

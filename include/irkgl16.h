@@ -113,6 +113,40 @@ typedef struct {
 int irkgl16_create(irkgl16_ctx **out, const irkgl16_problem *probs, int32_t n_inst,
                    const irkgl16_options *opt, void *hip_stream);
 
+/* Create a context whose instances share one force supplied as device source
+ * (paper section 3.3: the user's right-hand side is a generic function that
+ * the method evaluates at all 8 stages at once; eq. ivp2: q'' = g(q, t)).
+ * force_src: NUL-terminated HIP device source, read during the call, that
+ * defines
+ *     __device__ void irkgl16_user_force(const double *q, double *g,
+ *                                        const double *prm, double t);
+ * which writes g(q, t) for the Dq = dq position components in q at time t;
+ * prm points at the instance's n_params parameters (NULL when n_params == 0).
+ * It is called at the stage times t = fl(fl((n-1) h) + fl(c_i h)) of step n
+ * (eq. IRK_FP), time counted from 0 at the start of each integrate call.  It
+ * must keep no state between calls; one stage's call runs on one lane, so
+ * branches cost only divergence between the 8 stages of an instance.  The
+ * macro IRKGL16_DQ holds dq.  Masses are 1 (p = v).
+ * dq: 1..64.  params: n_inst x n_params doubles (host memory, copied),
+ * instance-major.  The source is compiled once per process for each
+ * (source, dq, arithmetic mode) with hiprtc for gfx950, with floating-point
+ * contraction off (a*b+c is a multiply and an add unless the source calls fma),
+ * into the small-system kernel: 8 instances per 64-lane wavefront.  The
+ * context is then used with irkgl16_integrate like any other (flags as in
+ * irkgl16_options; q0/p0 are n_inst x dq).  Returns IRKGL16_EINVAL for a bad
+ * argument or a source that does not compile (irkgl16_user_compile_check
+ * gives the compiler log), IRKGL16_EDEVICE when the code object cannot be
+ * loaded or no GPU is usable.  The serving interface does not take user
+ * forces. */
+int irkgl16_create_user(irkgl16_ctx **out, const char *force_src, int32_t dq, int32_t n_params,
+                        const double *params, int32_t n_inst, const irkgl16_options *opt,
+                        void *hip_stream);
+
+/* Compile force_src for dq components (as irkgl16_create_user does) without
+ * a GPU; writes the compiler log (NUL-terminated, truncated to log_len bytes)
+ * when log is non-NULL.  Returns IRKGL16_OK or IRKGL16_EINVAL. */
+int irkgl16_user_compile_check(const char *force_src, int32_t dq, char *log, int64_t log_len);
+
 /* Integrate every instance from its initial state.
  * q0, p0: sum(Dq_i) doubles, instances concatenated in order (host memory, or
  *         device memory with IRKGL16_DEVICE_PTRS).  v = fl(p / m) on input.

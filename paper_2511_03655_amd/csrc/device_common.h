@@ -5,12 +5,22 @@
 // their exact error terms.
 #pragma once
 
+#ifndef __HIPCC_RTC__  // run-time compilation provides these itself
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#endif
 
 #include "irkgl16_coeffs.h"
 
 namespace irk {
+
+#ifdef __HIPCC_RTC__  // fixed-width integer names without the C headers
+typedef long long int64_t;
+typedef int int32_t;
+typedef unsigned int uint32_t;
+typedef unsigned long long uint64_t;
+typedef unsigned char uint8_t;
+#endif
 
 constexpr int kS = 8;  // stages
 
@@ -18,6 +28,7 @@ constexpr int kS = 8;  // stages
 constexpr int kKepler = 0;
 constexpr int kGravity = 1;
 constexpr int kChain = 2;
+constexpr int kUser = 3;  // force given as device source, compiled at run time
 
 // Per-instance status codes (same numbering as the C ABI).
 constexpr int kOk = 0;
@@ -81,6 +92,15 @@ inline int class_blocks_per_cu(int occupancy_per_cu, int waves_per_wg) {
   int b = kClassWavesPerCu / (waves_per_wg > 0 ? waves_per_wg : 1);
   if (b < 1) b = 1;
   return b < occupancy_per_cu ? b : occupancy_per_cu;
+}
+
+// Stage time t_{n-1} + c_i h of eq. IRK_FP for a step that starts after
+// `steps` steps from t = 0, rounded as fl(fl(steps h) + fl(c_i h)) (all HIP
+// code is compiled without contraction).
+__device__ __forceinline__ double stage_time(int64_t steps, double h, double c) {
+  const double t_prev = (double)steps * h;
+  const double ch = c * h;
+  return t_prev + ch;
 }
 
 struct LaunchArgs {

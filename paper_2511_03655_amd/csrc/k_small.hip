@@ -1,375 +1,7 @@
-// Persistent batched IRKGL16 kernel for small systems (Kepler, gravity with a
-// handful of bodies): one 64-lane wavefront integrates 8 instances ("slots")
-// at a time; a slot's 8 lanes take two roles in turn.
-//
-//  * stage-lane role: lane `sub` of a slot evaluates the force at stage `sub`
-//    for all Dq components of its instance (paper section 2.5: the vectorised
-//    f evaluates all 8 stages at once; here the 8 stages are 8 lanes);
-//  * component-lane role: lane `sub` owns components sub, sub+8, sub+16 with
-//    all 8 stage values in registers and performs the 8x8 stage contraction
-//    Q_i = q + h (c_i v + sum_j eta_ij R_j) (eq. IRK_FP2), the per-component
-//    max-norm increment and stopping rule (eqs. Delta_n, stopping), the
-//    compensated update (eq. qnvn2) and the extrapolated initial guess
-//    (eq. IRK_init2) without any cross-lane traffic.
-//
-// The two roles exchange stage positions and increments R_i = h b_i g(Q_i)
-// through one LDS tile per slot laid out [component][stage].  Slots iterate
-// in lockstep; a slot whose instance has converged is masked until the slowest
-// slot of the wave converges, then all slots finish the step together.  When
-// an instance finishes (or exhausts the per-launch step budget) its lanes write
-// the resumable state back and pull the next instance from the class queue.
-// Each instance's arithmetic is independent of which slot or wave runs it.
-#include "device_common.h"
+// Launchers of the small-system kernel (device code in small_kernel.h).
+#include "small_kernel.h"
 
 namespace irk {
-
-// Reads the stage positions from column `sub` of the slot tile and overwrites
-// the same column with the increments R_sub = h b_sub g(Q_sub): a lane only
-// touches its own column, so no barrier is needed between the read and the
-// write.  Ms: the slot's masses (LDS); coef = (h b_sub) and G.
-template <int KIND, int NB, int D, bool EXACT>
-__device__ __forceinline__ void stage_increment(double* __restrict__ Xs, int sub,
-                                                const double* __restrict__ Ms, double eps2,
-                                                double hb, double G) {
-  constexpr int DQ = NB * D;
-  if constexpr (KIND == kKepler) {
-    double q[DQ];
-#pragma unroll
-    for (int l = 0; l < DQ; ++l) q[l] = Xs[l * kS + sub];
-    if constexpr (EXACT) {  // g = -G q / (r2 sqrt(r2))
-      double r2 = 0.0;
-#pragma unroll
-      for (int l = 0; l < DQ; ++l) r2 = r2 + q[l] * q[l];
-      const double r3 = r2 * sqrt(r2);
-#pragma unroll
-      for (int l = 0; l < DQ; ++l) Xs[l * kS + sub] = hb * (-G * q[l] / r3);
-    } else {
-      double r2 = q[0] * q[0];
-#pragma unroll
-      for (int l = 1; l < DQ; ++l) r2 = fma(q[l], q[l], r2);
-      const double w = -(hb * G) * rinv3(r2);
-#pragma unroll
-      for (int l = 0; l < DQ; ++l) Xs[l * kS + sub] = w * q[l];
-    }
-  } else if constexpr (EXACT) {
-    // Ordered pairs, b ascending for every a, as in the force's definition.
-    double out[DQ];
-#pragma unroll
-    for (int a = 0; a < NB; ++a) {
-      double acc[D];
-#pragma unroll
-      for (int k = 0; k < D; ++k) acc[k] = 0.0;
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        if (b == a) continue;
-        double dx[D], r2 = 0.0;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-          dx[k] = Xs[(b * D + k) * kS + sub] - Xs[(a * D + k) * kS + sub];
-          r2 = r2 + dx[k] * dx[k];
-        }
-        r2 = r2 + eps2;
-        const double w = pair_weight<true>(r2, Ms[b]);
-#pragma unroll
-        for (int k = 0; k < D; ++k) acc[k] = acc[k] + w * dx[k];
-      }
-#pragma unroll
-      for (int k = 0; k < D; ++k) out[a * D + k] = hb * (G * acc[k]);
-    }
-#pragma unroll
-    for (int l = 0; l < DQ; ++l) Xs[l * kS + sub] = out[l];
-  } else {
-    double m[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) m[b] = Ms[b];
-    double acc[DQ];
-#pragma unroll
-    for (int l = 0; l < DQ; ++l) acc[l] = 0.0;
-    // Each unordered pair once: w = (|d|^2 + eps^2)^(-3/2) feeds both bodies.
-#pragma unroll
-    for (int a = 0; a < NB; ++a) {
-#pragma unroll
-      for (int b = a + 1; b < NB; ++b) {
-        double dx[D];
-#pragma unroll
-        for (int k = 0; k < D; ++k) dx[k] = Xs[(b * D + k) * kS + sub] - Xs[(a * D + k) * kS + sub];
-        double r2 = fma(dx[0], dx[0], eps2);
-#pragma unroll
-        for (int k = 1; k < D; ++k) r2 = fma(dx[k], dx[k], r2);
-        const double w = rinv3(r2);
-        const double wa = m[a] * w, wb = m[b] * w;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-          acc[a * D + k] = fma(wb, dx[k], acc[a * D + k]);
-          acc[b * D + k] = fma(-wa, dx[k], acc[b * D + k]);
-        }
-      }
-    }
-    const double coef = hb * G;
-#pragma unroll
-    for (int l = 0; l < DQ; ++l) Xs[l * kS + sub] = coef * acc[l];
-  }
-}
-
-template <int DQ>
-struct SmallTile {
-  // Slot tiles padded so that consecutive slots start on different LDS banks.
-  static constexpr int kStride = ((DQ * kS * 2) % 32 == 0) ? DQ * kS + 8 : DQ * kS;
-};
-
-// Per-slot bookkeeping, kept in LDS rather than replicated in 8 lanes' VGPRs.
-template <int NB>
-struct SlotMeta {
-  int64_t nsteps, stride, out_off, iters_off, state_off, step, target, it_sum, nonconv;
-  double h, G, eps2;
-  double m[NB];
-  int32_t inst, maxk, kslot, flags;  // flags: 1 dead, 2 capped
-};
-
-template <int KIND, int NB, int D, bool EXACT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void small_kernel(LaunchArgs a) {
-  constexpr int DQ = NB * D;
-  constexpr int CPL = (DQ + kS - 1) / kS;  // components owned per lane
-  constexpr int TS = SmallTile<DQ>::kStride;
-  __shared__ double X[8 * TS];
-  __shared__ SlotMeta<NB> meta[8];
-  __shared__ int32_t slot_inst[8];
-  __shared__ int32_t qdone;
-
-  const int lane = threadIdx.x;
-  const int slot = lane >> 3;
-  const int sub = lane & 7;
-  double* Xs = X + slot * TS;
-  SlotMeta<NB>& M = meta[slot];
-  const uint64_t smask = 0xFFull << (8 * slot);
-  const ConstTab T = const_tab(a.tab);
-  // Owned component cc is c = sub + 8 cc; lanes past Dq compute on a clamped
-  // copy and never store.
-  auto comp = [&](int cc) { return sub + kS * cc; };
-  auto owns = [&](int cc) { return sub + kS * cc < DQ; };
-  auto cidx = [&](int cc) { return (sub + kS * cc < DQ) ? sub + kS * cc : DQ - 1; };
-
-  int inst = -1;
-  double qh[CPL] = {}, ql[CPL] = {}, vh[CPL] = {}, vl[CPL] = {}, mind[CPL] = {}, prv[CPL] = {};
-  double Qc[CPL][kS] = {};
-
-  if (lane == 0) qdone = 0;
-  if (lane < 8) {
-    slot_inst[lane] = -1;
-    meta[lane].inst = -1;
-  }
-  __syncthreads();
-
-  for (;;) {
-    if (lane < 8 && slot_inst[lane] < 0 && !qdone) {
-      if (a.queue_head) {
-        const int idx = atomicAdd(a.queue_head, 1);
-        if (idx < a.queue_len)
-          slot_inst[lane] = a.queue[idx];
-        else
-          qdone = 1;
-      } else if (lane < a.queue_len) {
-        slot_inst[lane] = a.queue[lane];  // single-shot launch: up to 8 given instances
-      }
-    }
-    __syncthreads();
-    if (!a.queue_head && lane == 0) qdone = 1;
-    const int cur = slot_inst[slot];
-    if (__ballot(cur >= 0) == 0) break;
-
-    const bool fresh = cur >= 0 && cur != inst;
-    if (fresh && sub == 0) {  // slot bookkeeping of a newly loaded instance
-      const InstDesc& dsc = a.desc[cur];
-      const InstStat st = a.stat[cur];
-      M.inst = cur;
-      M.h = dsc.h;
-      M.G = dsc.G;
-      M.eps2 = dsc.eps * dsc.eps;
-      M.nsteps = dsc.nsteps;
-      M.stride = dsc.stride;
-      M.out_off = dsc.out_off;
-      M.iters_off = dsc.iters_off;
-      M.state_off = dsc.state_off;
-      M.step = st.steps_done;
-      M.it_sum = st.iterations;
-      M.nonconv = st.nonconv;
-      M.maxk = st.max_k;
-      int64_t target = dsc.nsteps;
-      if (a.step_budget > 0 && st.steps_done + a.step_budget < dsc.nsteps)
-        target = st.steps_done + a.step_budget;
-      if (st.status != kOk) target = st.steps_done;
-      M.target = target;
-#pragma unroll
-      for (int b = 0; b < NB; ++b) M.m[b] = (dsc.mass_off >= 0) ? a.params[dsc.mass_off + b] : 1.0;
-    }
-    __syncthreads();
-    if (fresh) {  // component state of the new instance
-      inst = cur;
-      const double* S = a.state + M.state_off;
-      double Rp[CPL][kS];
-#pragma unroll
-      for (int cc = 0; cc < CPL; ++cc) {
-        const int c = cidx(cc);
-        qh[cc] = S[c];
-        ql[cc] = S[DQ + c];
-        vh[cc] = S[2 * DQ + c];
-        vl[cc] = S[3 * DQ + c];
-#pragma unroll
-        for (int s = 0; s < kS; ++s) Rp[cc][s] = S[4 * DQ + c * kS + s];
-      }
-      initial_guess<CPL, EXACT>(T, qh, vh, Rp, M.h, Qc);
-    }
-
-    // ---- one step, all live slots in lockstep
-    const bool live = (inst >= 0) && (M.step < M.target);
-    const double h = M.h;
-    bool conv = !live;
-#pragma unroll
-    for (int cc = 0; cc < CPL; ++cc) mind[cc] = prv[cc] = __builtin_inf();
-    int k = 0;
-    while (__ballot(!conv) != 0) {
-      ++k;
-      if (!conv) {
-#pragma unroll
-        for (int cc = 0; cc < CPL; ++cc) {
-          if (owns(cc)) {
-#pragma unroll
-            for (int s = 0; s < kS; ++s) Xs[comp(cc) * kS + s] = Qc[cc][s];
-          }
-        }
-      }
-      __syncthreads();
-      if (!conv) stage_increment<KIND, NB, D, EXACT>(Xs, sub, M.m, M.eps2, h * T[kTabB + sub], M.G);
-      __syncthreads();
-      bool ok = true, bad = false;
-      if (!conv) {
-        double R[CPL][kS], dmax[CPL], nf[CPL];
-#pragma unroll
-        for (int cc = 0; cc < CPL; ++cc) {
-          dmax[cc] = 0.0;
-          nf[cc] = 0.0;
-#pragma unroll
-          for (int s = 0; s < kS; ++s) R[cc][s] = Xs[cidx(cc) * kS + s];
-        }
-#pragma unroll
-        for (int s = 0; s < kS; ++s) {
-          const ConstTab r = row_tab(T);
-#pragma unroll
-          for (int cc = 0; cc < CPL; ++cc) {
-            const double qn = stage_value<EXACT>(r, s, qh[cc], vh[cc], h, R[cc]);
-            max_track(dmax[cc], nf[cc], fabs(qn - Qc[cc][s]));
-            Qc[cc][s] = qn;
-          }
-        }
-#pragma unroll
-        for (int cc = 0; cc < CPL; ++cc) {
-          if (owns(cc)) {
-            bad |= !track_finite(dmax[cc], nf[cc]);
-            ok &= stop_component(dmax[cc], mind[cc], prv[cc]);
-          }
-        }
-      }
-      const uint64_t okm = __ballot(ok);
-      const uint64_t badm = __ballot(bad);
-      const bool slot_ok = (okm & smask) == smask;
-      const bool slot_bad = (badm & smask) != 0;
-      if (!conv && (slot_ok || slot_bad || k >= a.max_iter)) {
-        conv = true;
-        if (sub == 0) {
-          M.kslot = k;
-          M.flags = (slot_bad ? 1 : 0) | ((!slot_ok && !slot_bad) ? 2 : 0);
-        }
-      }
-    }
-    __syncthreads();
-
-    // ---- end of step: compensated update, output, next initial guess
-    bool release = (inst >= 0) && !live;
-    if (live) {
-      const int kslot = M.kslot;
-      const int64_t step0 = M.step, stride = M.stride, out_off = M.out_off;
-      if (M.flags & 1) {  // non-finite: stop this instance, remaining frames NaN
-        const int64_t nf = M.target / stride;  // frames of this launch only
-        for (int64_t f = step0 / stride + 1; f <= nf; ++f) {
-#pragma unroll
-          for (int cc = 0; cc < CPL; ++cc) {
-            if (owns(cc)) {
-              a.qout[out_off + f * DQ + comp(cc)] = __builtin_nan("");
-              a.pout[out_off + f * DQ + comp(cc)] = __builtin_nan("");
-            }
-          }
-        }
-        if (sub == 0) {
-          if (M.iters_off >= 0) a.step_iters[M.iters_off + step0] = (uint8_t)kslot;
-          InstStat st;
-          st.steps_done = step0;
-          st.iterations = M.it_sum;
-          st.nonconv = M.nonconv;
-          st.max_k = M.maxk;
-          st.status = kNonFinite;
-          a.stat[inst] = st;
-        }
-        release = true;
-      } else {
-        const int64_t step = step0 + 1;
-        const bool frame = (step % stride) == 0;
-        const bool last = step >= M.target;
-        double* S = a.state + M.state_off;
-        double R[CPL][kS];
-        const ConstTab r = row_tab(T);
-#pragma unroll
-        for (int cc = 0; cc < CPL; ++cc) {
-#pragma unroll
-          for (int s = 0; s < kS; ++s) R[cc][s] = Xs[cidx(cc) * kS + s];
-          double sv, sc;
-          step_sums<EXACT>(r, R[cc], sv, sc);
-          dw_add(vh[cc], vl[cc], sv);
-          dw_add(qh[cc], ql[cc], h * (vh[cc] - sc));
-          if (owns(cc)) {
-            const int c = comp(cc);
-            if (frame) {
-              const int64_t f = step / stride;
-              a.qout[out_off + f * DQ + c] = qh[cc];
-              a.pout[out_off + f * DQ + c] = M.m[c / D] * vh[cc];
-            }
-            if (last) {
-              S[c] = qh[cc];
-              S[DQ + c] = ql[cc];
-              S[2 * DQ + c] = vh[cc];
-              S[3 * DQ + c] = vl[cc];
-#pragma unroll
-              for (int s = 0; s < kS; ++s) S[4 * DQ + c * kS + s] = R[cc][s];
-            }
-          }
-        }
-        if (!last) initial_guess<CPL, EXACT>(T, qh, vh, R, h, Qc);
-        if (sub == 0) {
-          if (M.iters_off >= 0) a.step_iters[M.iters_off + step0] = (uint8_t)kslot;
-          M.step = step;
-          M.it_sum += kslot;
-          M.nonconv += (M.flags & 2) ? 1 : 0;
-          if (kslot > M.maxk) M.maxk = kslot;
-          if (last) {
-            InstStat st;
-            st.steps_done = step;
-            st.iterations = M.it_sum;
-            st.nonconv = M.nonconv;
-            st.max_k = M.maxk;
-            st.status = kOk;
-            a.stat[inst] = st;
-          }
-        }
-        release = last;
-      }
-    }
-    __syncthreads();
-    if (release) {
-      if (sub == 0) slot_inst[slot] = -1;
-      inst = -1;
-    }
-    __syncthreads();
-  }
-}
 
 // ------------------------------------------------------------------ launchers
 

@@ -45,11 +45,30 @@ int stage_np(int n);
 hipError_t launch_stage_class(int d, int np, const LaunchArgs& a, int n_items, int num_cus,
                               hipStream_t st);
 
+// User-supplied force compiled at run time (user_force.cpp): the small-system
+// kernel with one instance of Dq = dq components (unit masses) per 8-lane slot.
+constexpr int kUserMaxDq = 64;
+struct UserKernel {
+  hipModule_t mod = nullptr;
+  hipFunction_t fn = nullptr;
+  int dq = 0;
+  int per_cu = 1;  // occupancy: workgroups per CU
+  bool exact = false;
+};
+bool user_dq_supported(int dq);
+// 0 on success; -1 compile error (log filled); -3 HIP error.
+int user_compile_check(const char* src, int dq, std::string* log);
+int user_kernel_create(const char* src, int dq, bool exact, UserKernel** out, std::string* log);
+void user_kernel_free(UserKernel* k);
+hipError_t launch_user(const UserKernel& k, const LaunchArgs& a, int n_items, int num_cus,
+                       hipStream_t st);
+
 // Kernel classes.
 constexpr int kClassSmall = 0;  // several systems per wavefront (few bodies)
 constexpr int kClassWg = 1;     // one lane per body or site, systems in workgroup slots
 constexpr int kClassLarge = 2;  // one system on the whole GPU (cooperative launch)
 constexpr int kClassStage = 3;  // one lane per (body, stage), one system per workgroup
+constexpr int kClassUser = 4;   // user force compiled at run time (small-system kernel)
 
 // Kernel class of a problem, or -1 if unsupported.  *size: the class's size
 // parameter (bodies for the small kernel, slot width for the workgroup kernel,

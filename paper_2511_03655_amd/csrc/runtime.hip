@@ -117,6 +117,7 @@ struct irkgl16_ctx {
   hipEvent_t ev_fork = nullptr;
   std::vector<int32_t> h_queue;
   irk::TuneTable tune;  // launch shapes (read at creation)
+  irk::UserKernel* user = nullptr;  // run-time compiled force (irkgl16_create_user)
 
   // last call
   bool have_last = false;
@@ -133,6 +134,7 @@ struct irkgl16_ctx {
     for (hipStream_t sk : aux) (void)hipStreamDestroy(sk);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
+    irk::user_kernel_free(user);
   }
 };
 
@@ -155,14 +157,31 @@ static int alloc_try(DevBuf& b, size_t n) {
     if (_rc != IRKGL16_OK) return _rc;     \
   } while (0)
 
+// A user force (irkgl16_create_user): every instance has Dq = dq components
+// and n_params parameters.
+struct UserSpec {
+  const char* src;
+  int32_t dq, n_params;
+  const double* params;  // n_inst x n_params
+};
+
 static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t n_inst,
-                       const irkgl16_options* opt, void* hip_stream) {
+                       const irkgl16_options* opt, void* hip_stream,
+                       const UserSpec* user = nullptr) {
   if (!out) return IRKGL16_EINVAL;
   *out = nullptr;
   if (n_inst < 0 || (n_inst > 0 && !probs)) return IRKGL16_EINVAL;
-  for (int32_t i = 0; i < n_inst; ++i) {
-    int rc = validate_problem(probs[i]);
-    if (rc != IRKGL16_OK) return rc;
+  if (user) {
+    if (!user->src || !irk::user_dq_supported(user->dq) || user->n_params < 0 ||
+        (user->n_params > 0 && n_inst > 0 && !user->params))
+      return IRKGL16_EINVAL;
+    for (int64_t k = 0; k < (int64_t)n_inst * user->n_params; ++k)
+      if (!std::isfinite(user->params[k])) return IRKGL16_EINVAL;
+  } else {
+    for (int32_t i = 0; i < n_inst; ++i) {
+      int rc = validate_problem(probs[i]);
+      if (rc != IRKGL16_OK) return rc;
+    }
   }
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return IRKGL16_EDEVICE;
@@ -215,6 +234,11 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
       d.coupling_off = (int64_t)params.size();
       params.insert(params.end(), p.coupling, p.coupling + p.n + 1);
     }
+    if (user && user->n_params > 0) {  // the force's parameters, via the coupling offset
+      d.coupling_off = (int64_t)params.size();
+      const double* pp = user->params + (int64_t)i * user->n_params;
+      params.insert(params.end(), pp, pp + user->n_params);
+    }
     const int dqi = p.n * p.d;
     c->dq[i] = dqi;
     d.in_off = c->total_dq;
@@ -223,7 +247,7 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
     state_off += (int64_t)(4 + irk::kS) * dqi;
     // kernel class
     int size = 0;
-    const int cl = irk::kernel_class(p.kind, p.n, p.d, &size);
+    const int cl = user ? irk::kClassUser : irk::kernel_class(p.kind, p.n, p.d, &size);
     if (cl < 0) return fail(IRKGL16_EINVAL);
     if (cl == irk::kClassLarge) c->large_nmax = std::max(c->large_nmax, (int)p.n);
     auto key = std::make_tuple(cl, (int)p.kind, size, (int)p.d);
@@ -242,6 +266,12 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
       ci = it->second;
     }
     c->classes[ci].ids.push_back(i);
+  }
+  if (user) {
+    std::string log;
+    const int rc = irk::user_kernel_create(user->src, user->dq,
+                                           (c->flags & IRKGL16_REPRODUCIBLE) != 0, &c->user, &log);
+    if (rc != 0) return fail(rc == -1 ? IRKGL16_EINVAL : IRKGL16_EDEVICE);
   }
   // Launch shapes from the tuning table.
   c->tune = irk::load_tune_table();
@@ -359,6 +389,7 @@ static hipError_t launch_class(irkgl16_ctx* c, const KernelClass& kc, const irk:
     }
     return hipSuccess;
   }
+  if (kc.cls == irk::kClassUser) return irk::launch_user(*c->user, a, n_items, c->num_cus, st);
   return irk::launch_batched(kc.cls, kc.kind, kc.size, kc.d, a, n_items, c->num_cus, st, kc.tune);
 }
 
@@ -577,6 +608,46 @@ int irkgl16_create(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t n_in
                    const irkgl16_options* opt, void* hip_stream) {
   try {
     return create_impl(out, probs, n_inst, opt, hip_stream);
+  } catch (const std::bad_alloc&) {
+    return IRKGL16_ENOMEM;
+  } catch (...) {
+    return IRKGL16_EDEVICE;
+  }
+}
+
+int irkgl16_create_user(irkgl16_ctx** out, const char* force_src, int32_t dq, int32_t n_params,
+                        const double* params, int32_t n_inst, const irkgl16_options* opt,
+                        void* hip_stream) {
+  try {
+    if (!out) return IRKGL16_EINVAL;
+    *out = nullptr;
+    if (n_inst < 0 || !force_src || !irk::user_dq_supported(dq)) return IRKGL16_EINVAL;
+    std::vector<irkgl16_problem> probs((size_t)std::max(n_inst, 1));
+    for (auto& p : probs) {
+      std::memset(&p, 0, sizeof(p));
+      p.kind = irk::kUser;
+      p.n = 1;
+      p.d = dq;
+    }
+    const UserSpec spec{force_src, dq, n_params, params};
+    return create_impl(out, probs.data(), n_inst, opt, hip_stream, &spec);
+  } catch (const std::bad_alloc&) {
+    return IRKGL16_ENOMEM;
+  } catch (...) {
+    return IRKGL16_EDEVICE;
+  }
+}
+
+int irkgl16_user_compile_check(const char* force_src, int32_t dq, char* log, int64_t log_len) {
+  try {
+    std::string l;
+    const int rc = irk::user_compile_check(force_src, dq, &l);
+    if (log && log_len > 0) {
+      const size_t n = std::min<size_t>(l.size(), (size_t)(log_len - 1));
+      std::memcpy(log, l.data(), n);
+      log[n] = '\0';
+    }
+    return rc == 0 ? IRKGL16_OK : IRKGL16_EINVAL;
   } catch (const std::bad_alloc&) {
     return IRKGL16_ENOMEM;
   } catch (...) {

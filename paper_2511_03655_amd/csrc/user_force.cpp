@@ -1,0 +1,165 @@
+// Run-time compilation of a user-supplied force (paper section 2.5: the
+// method evaluates any branch-free f at all 8 stages at once; here the
+// caller's force function is compiled with hiprtc into the small-system
+// kernel, one 8-lane slot per instance, one lane per stage).
+//
+// The program handed to hiprtc is
+//
+//     #define IRKGL16_USER_FORCE 1
+//     #define IRKGL16_DQ <dq>
+//     <caller's source, which defines irkgl16_user_force>
+//     #include "small_kernel.h"
+//
+// with small_kernel.h, device_common.h and irkgl16_coeffs.h served from
+// copies embedded in this library at build time, so the run-time kernel is the
+// same code as the ahead-of-time one.  Compiled code objects are cached per
+// process by (source, dq, arithmetic mode).
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "launch.h"
+#include "rtc_headers.inc"
+
+namespace irk {
+
+namespace {
+
+constexpr int kNumRtcHeaders = (int)(sizeof(kRtcHeaderNames) / sizeof(kRtcHeaderNames[0]));
+
+std::string kernel_expr(int dq, bool exact) {
+  return "&irk::small_kernel<" + std::to_string(kUser) + ", 1, " + std::to_string(dq) + ", " +
+         (exact ? "true" : "false") + ">";
+}
+
+struct Compiled {
+  std::vector<char> code;
+  std::string lowered;
+};
+
+std::mutex g_cache_mu;
+std::map<std::tuple<std::string, int, bool>, Compiled> g_cache;
+
+// Compiles the program for one (source, dq, mode); on failure returns false
+// and the compiler log in *log.
+bool compile(const char* src, int dq, bool exact, Compiled* out, std::string* log) {
+  std::string prog = "#define IRKGL16_USER_FORCE 1\n#define IRKGL16_DQ " + std::to_string(dq) +
+                     "\n#line 1 \"user_force\"\n" + src + "\n#line 1 \"irkgl16_rtc\"\n" +
+                     "#include \"small_kernel.h\"\n";
+  hiprtcProgram p;
+  if (hiprtcCreateProgram(&p, prog.c_str(), "irkgl16_user.hip", kNumRtcHeaders, kRtcHeaderTexts,
+                          kRtcHeaderNames) != HIPRTC_SUCCESS) {
+    *log = "hiprtcCreateProgram failed";
+    return false;
+  }
+  const std::string expr = kernel_expr(dq, exact);
+  bool ok = hiprtcAddNameExpression(p, expr.c_str()) == HIPRTC_SUCCESS;
+  const char* opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off",
+                        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+  const hiprtcResult rc = ok ? hiprtcCompileProgram(p, (int)(sizeof(opts) / sizeof(opts[0])), opts)
+                             : HIPRTC_ERROR_INVALID_INPUT;
+  size_t log_size = 0;
+  if (hiprtcGetProgramLogSize(p, &log_size) == HIPRTC_SUCCESS && log_size > 1) {
+    std::string l(log_size, '\0');
+    if (hiprtcGetProgramLog(p, &l[0]) == HIPRTC_SUCCESS) {
+      l.resize(std::strlen(l.c_str()));
+      *log = l;
+    }
+  }
+  ok = ok && rc == HIPRTC_SUCCESS;
+  if (ok) {
+    const char* lowered = nullptr;
+    size_t code_size = 0;
+    ok = hiprtcGetLoweredName(p, expr.c_str(), &lowered) == HIPRTC_SUCCESS && lowered &&
+         hiprtcGetCodeSize(p, &code_size) == HIPRTC_SUCCESS && code_size > 0;
+    if (ok) {
+      out->lowered = lowered;
+      out->code.resize(code_size);
+      ok = hiprtcGetCode(p, out->code.data()) == HIPRTC_SUCCESS;
+    }
+    if (!ok && log->empty()) *log = "hiprtc produced no code object for the kernel";
+  }
+  (void)hiprtcDestroyProgram(&p);
+  return ok;
+}
+
+bool compile_cached(const char* src, int dq, bool exact, Compiled* out, std::string* log) {
+  const auto key = std::make_tuple(std::string(src), dq, exact);
+  {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) {
+      *out = it->second;
+      return true;
+    }
+  }
+  if (!compile(src, dq, exact, out, log)) return false;
+  std::lock_guard<std::mutex> lk(g_cache_mu);
+  g_cache[key] = *out;
+  return true;
+}
+
+}  // namespace
+
+bool user_dq_supported(int dq) { return dq >= 1 && dq <= kUserMaxDq; }
+
+int user_compile_check(const char* src, int dq, std::string* log) {
+  log->clear();
+  if (!src || !user_dq_supported(dq)) {
+    *log = "invalid source pointer or dq";
+    return -1;
+  }
+  Compiled c;
+  return compile_cached(src, dq, false, &c, log) ? 0 : -1;
+}
+
+int user_kernel_create(const char* src, int dq, bool exact, UserKernel** out, std::string* log) {
+  *out = nullptr;
+  log->clear();
+  if (!src || !user_dq_supported(dq)) return -1;
+  Compiled c;
+  if (!compile_cached(src, dq, exact, &c, log)) return -1;
+  UserKernel* k = new UserKernel();
+  k->dq = dq;
+  k->exact = exact;
+  if (hipModuleLoadData(&k->mod, c.code.data()) != hipSuccess ||
+      hipModuleGetFunction(&k->fn, k->mod, c.lowered.c_str()) != hipSuccess) {
+    user_kernel_free(k);
+    *log = "loading the compiled code object failed";
+    return -3;
+  }
+  int per_cu = 0;
+  if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k->fn, 64, 0) != hipSuccess) {
+    user_kernel_free(k);
+    return -3;
+  }
+  k->per_cu = per_cu < 1 ? 1 : per_cu;
+  *out = k;
+  return 0;
+}
+
+void user_kernel_free(UserKernel* k) {
+  if (!k) return;
+  if (k->mod) (void)hipModuleUnload(k->mod);
+  delete k;
+}
+
+hipError_t launch_user(const UserKernel& k, const LaunchArgs& a, int n_items, int num_cus,
+                       hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  if (a.exact != (k.exact ? 1 : 0)) return hipErrorInvalidValue;
+  const int want = (n_items + 7) / 8;  // 8 instances per 64-lane workgroup
+  const int cap = class_blocks_per_cu(k.per_cu, 1) * num_cus;
+  const int grid = want < cap ? want : cap;
+  LaunchArgs arg = a;
+  void* params[] = {&arg};
+  return hipModuleLaunchKernel(k.fn, (unsigned)grid, 1, 1, 64, 1, 1, 0, st, params, nullptr);
+}
+
+}  // namespace irk

@@ -27,7 +27,8 @@ IRKGL16_DEVICE_PTRS, IRKGL16_PLAIN, IRKGL16_REPRODUCIBLE, IRKGL16_GRAPH = 1, 2, 
 
 EXPORTED = ["irkgl16_create", "irkgl16_integrate", "irkgl16_last_stats", "irkgl16_destroy",
             "irkgl16_strerror", "irkgl16_server_create", "irkgl16_submit", "irkgl16_poll",
-            "irkgl16_wait", "irkgl16_server_destroy"]
+            "irkgl16_wait", "irkgl16_server_destroy", "irkgl16_create_user",
+            "irkgl16_user_compile_check"]
 
 
 class irkgl16_problem(C.Structure):
@@ -99,6 +100,11 @@ def lib():
         L.irkgl16_wait.restype = C.c_int
         L.irkgl16_server_destroy.argtypes = [C.c_void_p]
         L.irkgl16_server_destroy.restype = None
+        L.irkgl16_create_user.argtypes = [C.POINTER(C.c_void_p), C.c_char_p, C.c_int32, C.c_int32,
+                                          dp, C.c_int32, C.POINTER(irkgl16_options), C.c_void_p]
+        L.irkgl16_create_user.restype = C.c_int
+        L.irkgl16_user_compile_check.argtypes = [C.c_char_p, C.c_int32, C.c_char_p, C.c_int64]
+        L.irkgl16_user_compile_check.restype = C.c_int
         _lib = L
     return _lib
 
@@ -147,6 +153,34 @@ def irkgl16_create(problems, max_iter=0, record_iters=False, flags=0, stream=Non
     return ctx
 
 
+def irkgl16_create_user(force_src, dq, params, n_inst, max_iter=0, record_iters=False, flags=0,
+                        stream=None):
+    """Context for n_inst instances of a force given as device source.
+
+    params: array of shape (n_inst, n_params) (or None for no parameters).
+    """
+    prm = None if params is None else np.ascontiguousarray(params, np.float64).reshape(n_inst, -1)
+    n_params = 0 if prm is None else prm.shape[1]
+    opt = irkgl16_options(int(max_iter), int(bool(record_iters)), int(flags))
+    if stream is not None and hasattr(stream, "cuda_stream"):
+        stream = stream.cuda_stream
+    ctx = C.c_void_p()
+    rc = lib().irkgl16_create_user(
+        C.byref(ctx), force_src.encode(), int(dq), int(n_params),
+        prm.ctypes.data_as(C.POINTER(C.c_double)) if n_params > 0 else None, int(n_inst),
+        C.byref(opt), C.c_void_p(stream) if stream else None)
+    if rc != IRKGL16_OK:
+        raise IRKGL16Error(rc, "irkgl16_create_user")
+    return ctx
+
+
+def irkgl16_user_compile_check(force_src, dq, log_len=1 << 16):
+    """Returns (status, compiler log)."""
+    buf = C.create_string_buffer(log_len)
+    rc = lib().irkgl16_user_compile_check(force_src.encode(), int(dq), buf, log_len)
+    return rc, buf.value.decode(errors="replace")
+
+
 def irkgl16_integrate(ctx, q0, p0, h, nsteps, out_stride, q_out, p_out, stats=None):
     h = np.ascontiguousarray(h, np.float64)
     ns = np.ascontiguousarray(nsteps, np.int64)
@@ -177,8 +211,22 @@ class Integrator:
         self.record_iters = bool(record_iters)
         self.ctx = irkgl16_create(self.problems, max_iter, record_iters, flags, stream)
 
+    @classmethod
+    def user(cls, force_src, dq, n_inst, params=None, max_iter=0, record_iters=False, flags=0,
+             stream=None):
+        """Integrator of n_inst instances of a user force (irkgl16_create_user)."""
+        self = cls.__new__(cls)
+        self.problems = [dict(kind=-1, n=1, d=int(dq))] * int(n_inst)
+        self.dq = np.full(int(n_inst), int(dq), np.int64)
+        self.flags = int(flags)
+        self.record_iters = bool(record_iters)
+        self.ctx = None
+        self.ctx = irkgl16_create_user(force_src, dq, params, n_inst, max_iter, record_iters,
+                                       flags, stream)
+        return self
+
     def close(self):
-        if self.ctx:
+        if getattr(self, "ctx", None):
             irkgl16_destroy(self.ctx)
             self.ctx = None
 

@@ -18,6 +18,9 @@ stand-ins used for throughput):
 * :func:`fpu_chain` -- a Fermi-Pasta-Ulam-beta chain with fixed ends, energy
   in the lowest mode plus small Gaussian noise.
 * :func:`uneven_mix` -- the mixed batch of gravitational systems and chains.
+* :func:`henon_heiles_ensemble` -- Henon-Heiles initial states on the
+  surface q1 = 0 (section 5.1.2's problem: q2 = 0.3, p2 = 0.2, H = 1/12 and
+  perturbations of it, or other energies).
 * :func:`poisson_requests` -- an open-loop Poisson request stream.
 """
 from __future__ import annotations
@@ -247,3 +250,25 @@ def poisson_requests(rate, n_req, seed=BASE_SEED + 5, steps_range=(1e3, 1e6), st
         inst["stride"] = stride
         out.append((float(t[k]), inst))
     return out
+
+
+def henon_heiles_ensemble(n, seed=BASE_SEED + 6, energy=1 / 12, q2_range=(0.25, 0.35),
+                          p2_range=(0.15, 0.25)):
+    """n Henon-Heiles states (q of shape (n, 2), p of shape (n, 2)): q1 = 0,
+    q2 and p2 uniform in the given ranges, p1 > 0 from the energy (a number,
+    or a (lo, hi) range to draw from), with
+    H = (p1^2 + p2^2)/2 + (q1^2 + q2^2)/2 + q1^2 q2 - q2^3/3.
+    The defaults surround the paper's regular orbit (q2 = 0.3, p2 = 0.2,
+    H = 1/12)."""
+    rng = np.random.default_rng(seed)
+    q, p = [], []
+    while len(q) < n:
+        E = rng.uniform(*energy) if np.ndim(energy) else float(energy)
+        q2 = rng.uniform(*q2_range)
+        p2 = rng.uniform(*p2_range)
+        rest = 2 * E - p2 ** 2 - q2 ** 2 + 2.0 / 3.0 * q2 ** 3
+        if rest <= 0:
+            continue
+        q.append([0.0, q2])
+        p.append([np.sqrt(rest), p2])
+    return np.array(q), np.array(p)

@@ -113,3 +113,51 @@ def test_graft_entry_build_compiles_everything(tmp_path):
     ge.build()
     assert os.path.exists(os.path.join(ROOT, "paper_2511_03655_amd", "libirkgl16.so"))
     assert os.path.exists(os.path.join(ROOT, "oracle", "liborc.so"))
+
+
+def test_user_force_compiles_without_gpu():
+    from paper_2511_03655_amd import user_forces as UF
+    rc, log = K.irkgl16_user_compile_check(UF.HENON_HEILES, 2)
+    assert rc == K.IRKGL16_OK, log
+    for src, dq in ((UF.HARMONIC, 6), (UF.HENON_HEILES_T, 2), (UF.DRIVEN, 3)):
+        rc, log = K.irkgl16_user_compile_check(src, dq)
+        assert rc == K.IRKGL16_OK, log
+
+
+def test_user_force_compile_errors_are_reported():
+    bad = "__device__ void irkgl16_user_force(const double* q, double* g, const double* prm,\n" \
+          "                                   double t) {\n" \
+          "  g[0] = -q[0]\n}\n"  # missing semicolon on line 3
+    rc, log = K.irkgl16_user_compile_check(bad, 1)
+    assert rc == K.IRKGL16_EINVAL
+    assert "user_force:" in log and "error" in log
+    rc, _ = K.irkgl16_user_compile_check("", 1)  # no force function defined
+    assert rc == K.IRKGL16_EINVAL
+    old = "__device__ void irkgl16_user_force(const double* q, double* g, const double* prm) {}"
+    rc, _ = K.irkgl16_user_compile_check(old, 1)  # wrong signature (no time argument)
+    assert rc == K.IRKGL16_EINVAL
+    for dq in (0, 65, -3):
+        rc, _ = K.irkgl16_user_compile_check("", dq)
+        assert rc == K.IRKGL16_EINVAL
+    L = K.lib()
+    assert L.irkgl16_user_compile_check(None, 2, None, 0) == K.IRKGL16_EINVAL
+
+
+def test_create_user_validates_arguments():
+    from paper_2511_03655_amd import user_forces as UF
+    with pytest.raises(K.IRKGL16Error) as e:
+        K.irkgl16_create_user(UF.HARMONIC, 0, None, 4)
+    assert e.value.code == K.IRKGL16_EINVAL
+    with pytest.raises(K.IRKGL16Error) as e:
+        K.irkgl16_create_user(UF.HARMONIC, 3, np.array([[1.0], [np.nan]]), 2)
+    assert e.value.code == K.IRKGL16_EINVAL
+    L = K.lib()
+    assert L.irkgl16_create_user(None, None, 2, 0, None, 1, None, None) == K.IRKGL16_EINVAL
+
+
+@pytest.mark.skipif(_has_gpu(), reason="checks the no-device path")
+def test_create_user_without_gpu_reports_edevice():
+    from paper_2511_03655_amd import user_forces as UF
+    with pytest.raises(K.IRKGL16Error) as e:
+        K.irkgl16_create_user(UF.HENON_HEILES, 2, None, 3)
+    assert e.value.code == K.IRKGL16_EDEVICE
