@@ -248,6 +248,41 @@ __device__ __forceinline__ double pair_weight(double r2, double m) {
   }
 }
 
+// Stage increment R = h b_s g(q) of the Kepler force g = -G q / |q|^3 for one
+// stage value q.
+template <int DQ, bool EXACT>
+__device__ __forceinline__ void kepler_increment(const double (&q)[DQ], double hb, double G,
+                                                 double (&R)[DQ]) {
+  if constexpr (EXACT) {  // g = -G q / (r2 sqrt(r2))
+    double r2 = 0.0;
+#pragma unroll
+    for (int l = 0; l < DQ; ++l) r2 = r2 + q[l] * q[l];
+    const double r3 = r2 * sqrt(r2);
+#pragma unroll
+    for (int l = 0; l < DQ; ++l) R[l] = hb * (-G * q[l] / r3);
+  } else {
+    double r2 = q[0] * q[0];
+#pragma unroll
+    for (int l = 1; l < DQ; ++l) r2 = fma(q[l], q[l], r2);
+    const double w = -(hb * G) * rinv3(r2);
+#pragma unroll
+    for (int l = 0; l < DQ; ++l) R[l] = w * q[l];
+  }
+}
+
+#ifdef IRKGL16_USER_FORCE
+// Stage increment R = h b_s g(q, t) of a force supplied as source (defined
+// before this header in the run-time compiled program).
+template <int DQ>
+__device__ __forceinline__ void user_increment(const double (&q)[DQ], double hb, const double* prm,
+                                               double t, double (&R)[DQ]) {
+  double g[DQ];
+  irkgl16_user_force(q, g, prm, t);
+#pragma unroll
+  for (int l = 0; l < DQ; ++l) R[l] = hb * g[l];
+}
+#endif
+
 // Initial guess for the owned components from their previous-step increments
 // Rp (eq. IRK_init2): V0_i = v + sum_j nu_ij Rp_j, L0_j = h b_j V0_j,
 // Q_i = q + sum_j mu_ij L0_j, in that order with EXACT.  The fused mode

@@ -1,0 +1,243 @@
+// Persistent batched IRKGL16 kernel for systems with very few position
+// components (Dq <= kLaneMaxDq): one lane integrates one instance, holding all
+// 8 x Dq stage values and increments in registers.
+//
+// Each lane evaluates the force at its instance's 8 stages in turn (paper
+// section 2.5: all stage evaluations of an iteration are independent), then
+// performs the 8x8 stage contraction Q_i = q + h (c_i v + sum_j eta_ij R_j)
+// (eq. IRK_FP2), the per-component max-norm increment and stopping rule (eqs.
+// Delta_n, stopping), the compensated update (eq. qnvn2) and the extrapolated
+// initial guess (eq. IRK_init2) for every component -- no LDS and no
+// cross-lane traffic.  For a system of one or two bodies in the plane the
+// 8-lane slot layout of the small-system kernel leaves most lanes idle in the
+// contraction; here every lane of a wavefront works on its own instance.
+//
+// The 64 lanes of a wavefront step in lockstep: a lane whose instance has
+// converged is masked until the slowest lane of the wave converges.  A lane
+// whose instance finishes (or exhausts the per-launch step budget) writes the
+// resumable state back and takes the next instance from the class queue (one
+// atomic per wavefront for all lanes that need one).  Every lane performs its
+// instance's operations in the same order as the small-system kernel, so an
+// instance's results do not depend on the kernel or lane that runs it.
+//
+// Device code only: compiled ahead of time for the built-in forces
+// (k_lane.hip) and at run time with hiprtc for a user force.
+#pragma once
+
+#include "device_common.h"
+
+namespace irk {
+
+constexpr int kLaneMaxDq = 4;
+
+// R_s = h b_s g(Q_s, t_s) for the 8 stages of one instance.
+template <int KIND, int DQ, bool EXACT>
+__device__ __forceinline__ void lane_increments(ConstTab T, const double (&Q)[DQ][kS], double h,
+                                                double G, const double* prm, int64_t step,
+                                                double (&R)[DQ][kS]) {
+#pragma unroll
+  for (int s = 0; s < kS; ++s) {
+    const ConstTab r = row_tab(T);
+    const double hb = h * r[kTabB + s];
+    double q[DQ], out[DQ];
+#pragma unroll
+    for (int l = 0; l < DQ; ++l) q[l] = Q[l][s];
+#ifdef IRKGL16_USER_FORCE
+    if constexpr (KIND == kUser) user_increment<DQ>(q, hb, prm, stage_time(step, h, r[kTabC + s]), out);
+#endif
+    if constexpr (KIND == kKepler) kepler_increment<DQ, EXACT>(q, hb, G, out);
+#pragma unroll
+    for (int l = 0; l < DQ; ++l) R[l][s] = out[l];
+  }
+  (void)prm;
+  (void)step;
+  (void)G;
+}
+
+template <int KIND, int DQ, bool EXACT>
+__global__ __launch_bounds__(64) void lane_kernel(LaunchArgs a) {
+  static_assert(DQ >= 1 && DQ <= kLaneMaxDq, "lane kernel: Dq out of range");
+  const int lane = threadIdx.x;
+  const ConstTab T = const_tab(a.tab);
+
+  int inst = -1;
+  bool qdone = false;  // wave-uniform: the class queue is exhausted
+  bool taken = false;  // single-shot launch: instances already taken
+  double h = 0.0, G = 0.0;
+  const double* prm = nullptr;
+  int64_t step = 0, target = 0, stride = 1, out_off = 0, iters_off = -1, state_off = 0;
+  int64_t it_sum = 0, nonconv = 0;
+  int32_t maxk = 0;
+  double qh[DQ], ql[DQ], vh[DQ], vl[DQ], mind[DQ], prv[DQ];
+  double Qc[DQ][kS], R[DQ][kS];
+
+  for (;;) {
+    // ---- lanes without an instance take the next ones from the queue
+    bool fresh = false;
+    if (a.queue_head) {
+      if (!qdone) {
+        const uint64_t need = __ballot(inst < 0);
+        if (need != 0) {
+          const int cnt = __popcll(need);
+          const int leader = __ffsll((unsigned long long)need) - 1;
+          int base = 0;
+          if (lane == leader) base = atomicAdd(a.queue_head, cnt);
+          base = __shfl(base, leader, 64);
+          if (inst < 0) {
+            const int idx = base + __popcll(need & ((1ull << lane) - 1ull));
+            if (idx < a.queue_len) {
+              inst = a.queue[idx];
+              fresh = true;
+            }
+          }
+          if (base + cnt >= a.queue_len) qdone = true;
+        }
+      }
+    } else if (!taken) {  // single-shot launch: up to 64 given instances
+      taken = true;
+      if (lane < a.queue_len) {
+        inst = a.queue[lane];
+        fresh = true;
+      }
+    }
+    if (__ballot(inst >= 0) == 0) break;
+
+    if (fresh) {  // bookkeeping and state of a newly taken instance
+      const InstDesc& dsc = a.desc[inst];
+      const InstStat st = a.stat[inst];
+      h = dsc.h;
+      G = dsc.G;
+      prm = dsc.coupling_off >= 0 ? a.params + dsc.coupling_off : nullptr;
+      stride = dsc.stride;
+      out_off = dsc.out_off;
+      iters_off = dsc.iters_off;
+      state_off = dsc.state_off;
+      step = st.steps_done;
+      it_sum = st.iterations;
+      nonconv = st.nonconv;
+      maxk = st.max_k;
+      target = dsc.nsteps;
+      if (a.step_budget > 0 && step + a.step_budget < dsc.nsteps) target = step + a.step_budget;
+      if (st.status != kOk) target = step;
+      const double* S = a.state + state_off;
+#pragma unroll
+      for (int l = 0; l < DQ; ++l) {
+        qh[l] = S[l];
+        ql[l] = S[DQ + l];
+        vh[l] = S[2 * DQ + l];
+        vl[l] = S[3 * DQ + l];
+#pragma unroll
+        for (int s = 0; s < kS; ++s) R[l][s] = S[4 * DQ + l * kS + s];
+      }
+      initial_guess<DQ, EXACT>(T, qh, vh, R, h, Qc);
+    }
+
+    // ---- one step, all live lanes in lockstep
+    const bool live = (inst >= 0) && (step < target);
+    bool conv = !live;
+#pragma unroll
+    for (int l = 0; l < DQ; ++l) mind[l] = prv[l] = __builtin_inf();
+    int k = 0, kl = 0, flags = 0;
+    while (__ballot(!conv) != 0) {
+      ++k;
+      if (!conv) {
+        lane_increments<KIND, DQ, EXACT>(T, Qc, h, G, prm, step, R);
+        double dmax[DQ], nf[DQ];
+#pragma unroll
+        for (int l = 0; l < DQ; ++l) dmax[l] = nf[l] = 0.0;
+#pragma unroll
+        for (int s = 0; s < kS; ++s) {
+          const ConstTab r = row_tab(T);
+#pragma unroll
+          for (int l = 0; l < DQ; ++l) {
+            const double qn = stage_value<EXACT>(r, s, qh[l], vh[l], h, R[l]);
+            max_track(dmax[l], nf[l], fabs(qn - Qc[l][s]));
+            Qc[l][s] = qn;
+          }
+        }
+        bool ok = true, bad = false;
+#pragma unroll
+        for (int l = 0; l < DQ; ++l) {
+          bad |= !track_finite(dmax[l], nf[l]);
+          ok &= stop_component(dmax[l], mind[l], prv[l]);
+        }
+        if (ok || bad || k >= a.max_iter) {
+          conv = true;
+          kl = k;
+          flags = bad ? 1 : (!ok ? 2 : 0);
+        }
+      }
+    }
+
+    // ---- end of step: compensated update, output, next initial guess
+    bool release = (inst >= 0) && !live;
+    if (live) {
+      if (flags & 1) {  // non-finite: stop this instance, remaining frames NaN
+        const int64_t nfr = target / stride;  // frames of this launch only
+        for (int64_t f = step / stride + 1; f <= nfr; ++f) {
+#pragma unroll
+          for (int l = 0; l < DQ; ++l) {
+            a.qout[out_off + f * DQ + l] = __builtin_nan("");
+            a.pout[out_off + f * DQ + l] = __builtin_nan("");
+          }
+        }
+        if (iters_off >= 0) a.step_iters[iters_off + step] = (uint8_t)kl;
+        InstStat st;
+        st.steps_done = step;
+        st.iterations = it_sum;
+        st.nonconv = nonconv;
+        st.max_k = maxk;
+        st.status = kNonFinite;
+        a.stat[inst] = st;
+        release = true;
+      } else {
+        const ConstTab r = row_tab(T);
+#pragma unroll
+        for (int l = 0; l < DQ; ++l) {
+          double sv, sc;
+          step_sums<EXACT>(r, R[l], sv, sc);
+          dw_add(vh[l], vl[l], sv);
+          dw_add(qh[l], ql[l], h * (vh[l] - sc));
+        }
+        if (iters_off >= 0) a.step_iters[iters_off + step] = (uint8_t)kl;
+        ++step;
+        it_sum += kl;
+        nonconv += (flags & 2) ? 1 : 0;
+        if (kl > maxk) maxk = kl;
+        if (step % stride == 0) {  // unit masses: p = v
+          const int64_t f = step / stride;
+#pragma unroll
+          for (int l = 0; l < DQ; ++l) {
+            a.qout[out_off + f * DQ + l] = qh[l];
+            a.pout[out_off + f * DQ + l] = vh[l];
+          }
+        }
+        if (step >= target) {
+          double* S = a.state + state_off;
+#pragma unroll
+          for (int l = 0; l < DQ; ++l) {
+            S[l] = qh[l];
+            S[DQ + l] = ql[l];
+            S[2 * DQ + l] = vh[l];
+            S[3 * DQ + l] = vl[l];
+#pragma unroll
+            for (int s = 0; s < kS; ++s) S[4 * DQ + l * kS + s] = R[l][s];
+          }
+          InstStat st;
+          st.steps_done = step;
+          st.iterations = it_sum;
+          st.nonconv = nonconv;
+          st.max_k = maxk;
+          st.status = kOk;
+          a.stat[inst] = st;
+          release = true;
+        } else {
+          initial_guess<DQ, EXACT>(T, qh, vh, R, h, Qc);
+        }
+      }
+    }
+    if (release) inst = -1;
+  }
+}
+
+}  // namespace irk

@@ -45,14 +45,17 @@ int stage_np(int n);
 hipError_t launch_stage_class(int d, int np, const LaunchArgs& a, int n_items, int num_cus,
                               hipStream_t st);
 
-// User-supplied force compiled at run time (user_force.cpp): the small-system
-// kernel with one instance of Dq = dq components (unit masses) per 8-lane slot.
+// User-supplied force compiled at run time (user_force.cpp): instances of
+// Dq = dq components (unit masses) on the one-instance-per-lane kernel for
+// dq <= kLaneMaxDqHost, else on the small-system kernel (one per 8-lane slot).
 constexpr int kUserMaxDq = 64;
+constexpr int kLaneMaxDqHost = 4;  // = kLaneMaxDq of lane_kernel.h
 struct UserKernel {
   hipModule_t mod = nullptr;
   hipFunction_t fn = nullptr;
   int dq = 0;
-  int per_cu = 1;  // occupancy: workgroups per CU
+  int per_cu = 1;          // occupancy: workgroups per CU
+  int lanes_per_inst = 8;  // 1: lane kernel, 8: small-system kernel
   bool exact = false;
 };
 bool user_dq_supported(int dq);

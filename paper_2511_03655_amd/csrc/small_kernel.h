@@ -42,35 +42,24 @@ __device__ __forceinline__ void stage_increment(double* __restrict__ Xs, int sub
   constexpr int DQ = NB * D;
 #ifdef IRKGL16_USER_FORCE
   if constexpr (KIND == kUser) {  // R = h b_sub g(Q_sub, t_sub), g from the caller's source
-    double q[DQ], g[DQ];
+    double q[DQ], r[DQ];
 #pragma unroll
     for (int l = 0; l < DQ; ++l) q[l] = Xs[l * kS + sub];
-    irkgl16_user_force(q, g, prm, t);
+    user_increment<DQ>(q, hb, prm, t, r);
 #pragma unroll
-    for (int l = 0; l < DQ; ++l) Xs[l * kS + sub] = hb * g[l];
+    for (int l = 0; l < DQ; ++l) Xs[l * kS + sub] = r[l];
     return;
   }
 #endif
   (void)prm;
+  (void)t;
   if constexpr (KIND == kKepler) {
-    double q[DQ];
+    double q[DQ], r[DQ];
 #pragma unroll
     for (int l = 0; l < DQ; ++l) q[l] = Xs[l * kS + sub];
-    if constexpr (EXACT) {  // g = -G q / (r2 sqrt(r2))
-      double r2 = 0.0;
+    kepler_increment<DQ, EXACT>(q, hb, G, r);
 #pragma unroll
-      for (int l = 0; l < DQ; ++l) r2 = r2 + q[l] * q[l];
-      const double r3 = r2 * sqrt(r2);
-#pragma unroll
-      for (int l = 0; l < DQ; ++l) Xs[l * kS + sub] = hb * (-G * q[l] / r3);
-    } else {
-      double r2 = q[0] * q[0];
-#pragma unroll
-      for (int l = 1; l < DQ; ++l) r2 = fma(q[l], q[l], r2);
-      const double w = -(hb * G) * rinv3(r2);
-#pragma unroll
-      for (int l = 0; l < DQ; ++l) Xs[l * kS + sub] = w * q[l];
-    }
+    for (int l = 0; l < DQ; ++l) Xs[l * kS + sub] = r[l];
   } else if constexpr (EXACT) {
     // Ordered pairs, b ascending for every a, as in the force's definition.
     double out[DQ];

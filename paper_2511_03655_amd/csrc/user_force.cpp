@@ -1,19 +1,20 @@
-// Run-time compilation of a user-supplied force (paper section 2.5: the
-// method evaluates any branch-free f at all 8 stages at once; here the
-// caller's force function is compiled with hiprtc into the small-system
-// kernel, one 8-lane slot per instance, one lane per stage).
+// Run-time compilation of a user-supplied force (paper section 3.3: the
+// user's right-hand side is a generic function that the method evaluates at
+// all 8 stages at once; here the caller's device function is compiled with
+// hiprtc into one of the batched kernels).
 //
 // The program handed to hiprtc is
 //
 //     #define IRKGL16_USER_FORCE 1
 //     #define IRKGL16_DQ <dq>
 //     <caller's source, which defines irkgl16_user_force>
-//     #include "small_kernel.h"
+//     #include "lane_kernel.h"     (dq <= kLaneMaxDq: one instance per lane)
+//     #include "small_kernel.h"    (otherwise: one instance per 8-lane slot)
 //
-// with small_kernel.h, device_common.h and irkgl16_coeffs.h served from
-// copies embedded in this library at build time, so the run-time kernel is the
-// same code as the ahead-of-time one.  Compiled code objects are cached per
-// process by (source, dq, arithmetic mode).
+// with the device headers served from copies embedded in this library at
+// build time, so the run-time kernel is the same code as the ahead-of-time
+// one.  Compiled code objects are cached per process by (source, dq,
+// arithmetic mode).
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
@@ -24,6 +25,7 @@
 #include <tuple>
 #include <vector>
 
+#include "lane_kernel.h"
 #include "launch.h"
 #include "rtc_headers.inc"
 
@@ -31,11 +33,19 @@ namespace irk {
 
 namespace {
 
+static_assert(kLaneMaxDqHost == kLaneMaxDq, "lane kernel size limit out of sync");
+
 constexpr int kNumRtcHeaders = (int)(sizeof(kRtcHeaderNames) / sizeof(kRtcHeaderNames[0]));
 
+bool use_lane_kernel(int dq) { return dq <= kLaneMaxDqHost; }
+
 std::string kernel_expr(int dq, bool exact) {
+  const std::string mode = exact ? "true" : "false";
+  if (use_lane_kernel(dq))
+    return "&irk::lane_kernel<" + std::to_string(kUser) + ", " + std::to_string(dq) + ", " + mode +
+           ">";
   return "&irk::small_kernel<" + std::to_string(kUser) + ", 1, " + std::to_string(dq) + ", " +
-         (exact ? "true" : "false") + ">";
+         mode + ">";
 }
 
 struct Compiled {
@@ -51,7 +61,8 @@ std::map<std::tuple<std::string, int, bool>, Compiled> g_cache;
 bool compile(const char* src, int dq, bool exact, Compiled* out, std::string* log) {
   std::string prog = "#define IRKGL16_USER_FORCE 1\n#define IRKGL16_DQ " + std::to_string(dq) +
                      "\n#line 1 \"user_force\"\n" + src + "\n#line 1 \"irkgl16_rtc\"\n" +
-                     "#include \"small_kernel.h\"\n";
+                     (use_lane_kernel(dq) ? "#include \"lane_kernel.h\"\n"
+                                          : "#include \"small_kernel.h\"\n");
   hiprtcProgram p;
   if (hiprtcCreateProgram(&p, prog.c_str(), "irkgl16_user.hip", kNumRtcHeaders, kRtcHeaderTexts,
                           kRtcHeaderNames) != HIPRTC_SUCCESS) {
@@ -128,6 +139,7 @@ int user_kernel_create(const char* src, int dq, bool exact, UserKernel** out, st
   UserKernel* k = new UserKernel();
   k->dq = dq;
   k->exact = exact;
+  k->lanes_per_inst = use_lane_kernel(dq) ? 1 : 8;
   if (hipModuleLoadData(&k->mod, c.code.data()) != hipSuccess ||
       hipModuleGetFunction(&k->fn, k->mod, c.lowered.c_str()) != hipSuccess) {
     user_kernel_free(k);
@@ -154,7 +166,8 @@ hipError_t launch_user(const UserKernel& k, const LaunchArgs& a, int n_items, in
                        hipStream_t st) {
   if (n_items <= 0) return hipSuccess;
   if (a.exact != (k.exact ? 1 : 0)) return hipErrorInvalidValue;
-  const int want = (n_items + 7) / 8;  // 8 instances per 64-lane workgroup
+  const int per_wg = 64 / k.lanes_per_inst;  // instances per 64-lane workgroup
+  const int want = (n_items + per_wg - 1) / per_wg;
   const int cap = class_blocks_per_cu(k.per_cu, 1) * num_cus;
   const int grid = want < cap ? want : cap;
   LaunchArgs arg = a;
