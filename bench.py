@@ -578,7 +578,11 @@ def run_henon(args):
                     "roofline": {"bound": "alu", "achieved": flops / kern_s / 1e12,
                                  "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                                  "frac": flops / kern_s / 1e12 / FP64_PEAK_TFLOPS,
-                                 "traffic": None, "kernel": "lane_kernel<user, Dq=2> (hiprtc)",
+                                 "traffic": traffic_from_profile(
+                                     "lane_kernel_henon_262144",
+                                     ["lane_kernel.h", "device_common.h", "k_prepare.hip",
+                                      "user_force.cpp", "../user_forces.py"]),
+                                 "kernel": "lane_kernel<user, Dq=2> (hiprtc)",
                                  "kernel_ms": st["device_ms"]},
                     "accuracy": {"gate": "relative energy error first->last frame <= 1e-12",
                                  "pass_frac": float(np.mean(dE <= 1e-12)),
