@@ -24,10 +24,12 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liborc.so")
-SOURCES = ["irkgl16_oracle.c", "irkgl16_dd.c"]
+SOURCES = ["irkgl16_oracle.c", "irkgl16_dd.c", "irkgl16_ode.c"]
 
 KEPLER, GRAVITY, CHAIN, HARMONIC, CONST, HENON = 0, 1, 2, 10, 11, 12
 HENON_T, DRIVEN = 13, 14  # time-dependent: lambda = G, xi = beta; g = G cos t
+# first-order problems y' = f(t, y) (irkgl16_ode.c): D = n * d
+ODE_OSC, ODE_KEPLER, ODE_DAMPED, ODE_SBH, ODE_DRIVEN = 20, 21, 22, 23, 24
 FLAG_NO_COMPENSATION, FLAG_NAIVE_ETA, FLAG_NO_EXTRAPOLATION = 1, 2, 4
 OK, EINVAL, ENOMEM, ENONFINITE, ENOCONV = 0, -1, -2, -4, 1
 
@@ -91,6 +93,16 @@ def lib():
         L.ddo_integrate.restype = C.c_int
         L.ddo_energy.argtypes = [C.POINTER(Problem), dp, dp, dp, dp, dp, dp]
         L.ddo_energy.restype = None
+        L.orc_rhs.argtypes = [C.POINTER(Problem), C.c_double, dp, dp]
+        L.orc_rhs.restype = None
+        L.orc_energy_ode.argtypes = [C.POINTER(Problem), dp]
+        L.orc_energy_ode.restype = C.c_double
+        L.orc_integrate_ode.argtypes = [C.POINTER(Problem), dp, C.c_double, C.c_int64, C.c_int64,
+                                        C.c_int32, dp, i32p, C.POINTER(Stats)]
+        L.orc_integrate_ode.restype = C.c_int
+        L.orc_integrate_ode_batch.argtypes = [C.c_int32, C.POINTER(Problem), dp, dp, i64p, i64p,
+                                              C.c_int32, dp, i64p, i32p]
+        L.orc_integrate_ode_batch.restype = C.c_int
         _lib = L
     return _lib
 
@@ -315,3 +327,61 @@ def integrate_py(g, q0, v0, h, nsteps, tables, max_iter=100):
         q, ql = two_sum_update(q, ql, h * (v - sc))
         Rprev = R
     return q, v, np.array(iters)
+
+
+# ---------------------------------------------------------------- first-order form
+
+def rhs(spec, t, Y):
+    """f(t, Y) of a first-order kind."""
+    L = lib()
+    Y = np.ascontiguousarray(Y, np.float64)
+    F = np.empty_like(Y)
+    pr = spec.struct()
+    L.orc_rhs(C.byref(pr), float(t), _dp(Y), _dp(F))
+    return F
+
+
+def energy_ode(spec, y):
+    L = lib()
+    y = np.ascontiguousarray(y, np.float64)
+    pr = spec.struct()
+    return L.orc_energy_ode(C.byref(pr), _dp(y))
+
+
+def integrate_ode(spec, y0, h, nsteps, stride=1, max_iter=100, want_iters=False):
+    """First-order (mu form) FP64 oracle, one instance.  Returns dict(y, iters, stats, rc)."""
+    L = lib()
+    y0 = np.ascontiguousarray(y0, np.float64)
+    nf = nsteps // stride + 1
+    yo = np.empty((nf, spec.Dq))
+    it = np.zeros(max(nsteps, 1), np.int32) if want_iters else None
+    st = Stats()
+    pr = spec.struct()
+    rc = L.orc_integrate_ode(C.byref(pr), _dp(y0), float(h), int(nsteps), int(stride),
+                             int(max_iter), _dp(yo),
+                             it.ctypes.data_as(C.POINTER(C.c_int32)) if it is not None else None,
+                             C.byref(st))
+    return dict(y=yo, iters=None if it is None else it[:nsteps],
+                stats=dict(steps_done=st.steps_done, iterations=st.iterations, max_k=st.max_k,
+                           nonconverged=st.nonconverged, status=st.status), rc=rc)
+
+
+def integrate_ode_batch(specs, y0, h, nsteps, stride, max_iter=100):
+    """First-order oracle over many instances (OpenMP), packed as the library."""
+    L = lib()
+    n = len(specs)
+    arr = (Problem * n)(*[s.struct() for s in specs])
+    y0 = np.ascontiguousarray(y0, np.float64)
+    h = np.ascontiguousarray(np.broadcast_to(h, (n,)), np.float64)
+    ns = np.ascontiguousarray(np.broadcast_to(nsteps, (n,)), np.int64)
+    sd = np.ascontiguousarray(np.broadcast_to(stride, (n,)), np.int64)
+    tot = int(sum(s.Dq * (int(a) // int(b) + 1) for s, a, b in zip(specs, ns, sd)))
+    yo = np.empty(tot)
+    iters = np.zeros(n, np.int64)
+    status = np.zeros(n, np.int32)
+    rc = L.orc_integrate_ode_batch(n, arr, _dp(y0), _dp(h),
+                                   ns.ctypes.data_as(C.POINTER(C.c_int64)),
+                                   sd.ctypes.data_as(C.POINTER(C.c_int64)), int(max_iter),
+                                   _dp(yo), iters.ctypes.data_as(C.POINTER(C.c_int64)),
+                                   status.ctypes.data_as(C.POINTER(C.c_int32)))
+    return dict(y=yo, iters=iters, status=status, rc=rc)
