@@ -147,6 +147,31 @@ int irkgl16_create_user(irkgl16_ctx **out, const char *force_src, int32_t dq, in
  * when log is non-NULL.  Returns IRKGL16_OK or IRKGL16_EINVAL. */
 int irkgl16_user_compile_check(const char *force_src, int32_t dq, char *log, int64_t log_len);
 
+/* Create a context for the FIRST-ORDER form (paper section 2.4, eqs. Yi2 and
+ * yn2; section 2.5, eqs. IRK_init and IRK_FP): y' = f(t, y), y in R^D, for
+ * problems that are not of the form q'' = g(q, t) (e.g. non-separable
+ * Hamiltonians, eq. Ham_SBH).  Stages Y_i = y + sum_j mu_ij L_j with
+ * L_i = h b_i f(t_i, Y_i), update y + sum_i L_i with the two-double state,
+ * initial guess Y_i = y + sum_j nu_ij L_prev_j, stopping rule eq. stopping
+ * over all D components.  rhs_src: NUL-terminated HIP device source that
+ * defines
+ *     __device__ void irkgl16_user_rhs(const double *y, double *f,
+ *                                      const double *prm, double t);
+ * writing f(t, y) for the D components (macro IRKGL16_DQ = D), with the same
+ * rules, parameters, stage times and compilation as irkgl16_create_user.
+ * D: 1..64.  With such a context irkgl16_integrate takes y0 in q0 (D values
+ * per instance) and writes the y frames to q_out; p0 and p_out are not used
+ * (may be NULL).  Errors as irkgl16_create_user
+ * (irkgl16_ode_compile_check gives the compiler log). */
+int irkgl16_create_ode(irkgl16_ctx **out, const char *rhs_src, int32_t D, int32_t n_params,
+                       const double *params, int32_t n_inst, const irkgl16_options *opt,
+                       void *hip_stream);
+
+/* Compile rhs_src for D components (as irkgl16_create_ode does) without a
+ * GPU; log as irkgl16_user_compile_check.  Returns IRKGL16_OK or
+ * IRKGL16_EINVAL. */
+int irkgl16_ode_compile_check(const char *rhs_src, int32_t D, char *log, int64_t log_len);
+
 /* Integrate every instance from its initial state.
  * q0, p0: sum(Dq_i) doubles, instances concatenated in order (host memory, or
  *         device memory with IRKGL16_DEVICE_PTRS).  v = fl(p / m) on input.

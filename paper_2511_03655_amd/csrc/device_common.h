@@ -28,7 +28,8 @@ constexpr int kS = 8;  // stages
 constexpr int kKepler = 0;
 constexpr int kGravity = 1;
 constexpr int kChain = 2;
-constexpr int kUser = 3;  // force given as device source, compiled at run time
+constexpr int kUser = 3;     // force g(q, t) given as device source, compiled at run time
+constexpr int kUserOde = 4;  // first-order right-hand side f(t, y) given as device source
 
 // Per-instance status codes (same numbering as the C ABI).
 constexpr int kOk = 0;
@@ -317,5 +318,86 @@ __device__ __forceinline__ void initial_guess(ConstTab T, const double (&qh)[CPL
     for (int cc = 0; cc < CPL; ++cc) Q[cc][s] = qh[cc] + row_dot<EXACT>(r, kTabMu + s * kS, L0[cc]);
   }
 }
+
+// ---- first-order (mu) form, eqs. Yi2 / yn2, IRK_init / IRK_FP
+// Stage value Y_s = y + sum_j M_sj L_j with M = mu (iteration) or nu (initial
+// guess from the previous step's increments).
+template <bool EXACT>
+__device__ __forceinline__ double ode_stage_value(ConstTab w, int s, double y, const double (&L)[kS],
+                                                  int mat) {
+  return y + row_dot<EXACT>(w, mat + s * kS, L);
+}
+
+// sum_i L_i (eq. yn2).
+template <bool EXACT>
+__device__ __forceinline__ double ode_step_sum(const double (&L)[kS]) {
+  if constexpr (EXACT) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < kS; ++i) s = s + L[i];
+    return s;
+  } else {
+    double s = L[0];
+#pragma unroll
+    for (int i = 1; i < kS; ++i) s += L[i];
+    return s;
+  }
+}
+
+#ifdef IRKGL16_USER_ODE
+// Stage increment L = h b_s f(t, y) of a right-hand side supplied as source.
+template <int DQ>
+__device__ __forceinline__ void ode_increment(const double (&y)[DQ], double hb, const double* prm,
+                                              double t, double (&L)[DQ]) {
+  double f[DQ];
+  irkgl16_user_rhs(y, f, prm, t);
+#pragma unroll
+  for (int l = 0; l < DQ; ++l) L[l] = hb * f[l];
+}
+#endif
+
+// ---- the two forms behind one interface (KIND == kUserOde: first order)
+// Initial guess for CPL owned components from the previous step's increments.
+template <int KIND, int CPL, bool EXACT>
+__device__ __forceinline__ void form_guess(ConstTab T, const double (&qh)[CPL],
+                                           const double (&vh)[CPL], const double (&Rp)[CPL][kS],
+                                           double h, double (&Q)[CPL][kS]) {
+  if constexpr (KIND == kUserOde) {
+#pragma unroll
+    for (int s = 0; s < kS; ++s) {
+      const ConstTab r = row_tab(T);
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc) Q[cc][s] = ode_stage_value<EXACT>(r, s, qh[cc], Rp[cc], kTabNu);
+    }
+  } else {
+    initial_guess<CPL, EXACT>(T, qh, vh, Rp, h, Q);
+  }
+}
+
+// New stage value of one component from the current increments.
+template <int KIND, bool EXACT>
+__device__ __forceinline__ double form_stage_value(ConstTab r, int s, double q, double v, double h,
+                                                   const double (&R)[kS]) {
+  if constexpr (KIND == kUserOde) {
+    return ode_stage_value<EXACT>(r, s, q, R, kTabMu);
+  } else {
+    return stage_value<EXACT>(r, s, q, v, h, R);
+  }
+}
+
+// Compensated end-of-step update of one component (eq. yn2 or eq. qnvn2).
+template <int KIND, bool EXACT>
+__device__ __forceinline__ void form_update(ConstTab r, const double (&R)[kS], double h, double& qh,
+                                            double& ql, double& vh, double& vl) {
+  if constexpr (KIND == kUserOde) {
+    dw_add(qh, ql, ode_step_sum<EXACT>(R));
+  } else {
+    double sv, sc;
+    step_sums<EXACT>(r, R, sv, sc);
+    dw_add(vh, vl, sv);
+    dw_add(qh, ql, h * (vh - sc));
+  }
+}
+
 
 }  // namespace irk

@@ -1,5 +1,6 @@
 // Per-call setup kernel (one block per instance; `ids`, if given, lists the
-// instances to set up): converts the caller's initial (q0, p0) into the
+// instances to set up; p0 and pout are null for first-order contexts, whose
+// state is y = q0 alone): converts the caller's initial (q0, p0) into the
 // resumable device state (q and v = fl(p / m) as two-double values with zero
 // low parts, previous-step increments R_prev = 0 so that the first initial
 // guess uses the current velocity only), writes output frame 0 (q, m v), clears
@@ -30,14 +31,14 @@ __global__ __launch_bounds__(64) void prepare_kernel(const InstDesc* __restrict_
   for (int c = threadIdx.x; c < dq; c += blockDim.x) {
     const double m = (d.mass_off >= 0) ? params[d.mass_off + c / d.d] : 1.0;
     const double q = q0[d.in_off + c];
-    const double v = p0[d.in_off + c] / m;
+    const double v = p0 ? p0[d.in_off + c] / m : 0.0;  // first-order form: no p
     S[c] = q;
     S[dq + c] = 0.0;
     S[2 * dq + c] = v;
     S[3 * dq + c] = 0.0;
     for (int s = 0; s < kS; ++s) S[4 * dq + c * kS + s] = 0.0;
     qout[d.out_off + c] = q;
-    pout[d.out_off + c] = m * v;
+    if (pout) pout[d.out_off + c] = m * v;
   }
   if (d.iters_off >= 0) {
     for (int64_t j = threadIdx.x; j < d.nsteps; j += blockDim.x) step_iters[d.iters_off + j] = 0;

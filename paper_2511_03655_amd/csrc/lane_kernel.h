@@ -1,6 +1,9 @@
 // Persistent batched IRKGL16 kernel for systems with very few position
 // components (Dq <= kLaneMaxDq): one lane integrates one instance, holding all
-// 8 x Dq stage values and increments in registers.
+// 8 x Dq stage values and increments in registers.  KIND == kUserOde runs the
+// first-order form instead (section 2.4, eqs. Yi2 / yn2; section 2.5, eqs.
+// IRK_init / IRK_FP: y' = f(t, y), Dq = D components, stages
+// Y_i = y + sum_j mu_ij L_j, update y + sum_i L_i).
 //
 // Each lane evaluates the force at its instance's 8 stages in turn (paper
 // section 2.5: all stage evaluations of an iteration are independent), then
@@ -20,8 +23,9 @@
 // instance's operations in the same order as the small-system kernel, so an
 // instance's results do not depend on the kernel or lane that runs it.
 //
-// Device code only: compiled ahead of time for the built-in forces
-// (k_lane.hip) and at run time with hiprtc for a user force.
+// Device code only: compiled at run time with hiprtc for a user force or
+// right-hand side (the built-in Kepler increment is shared with the
+// small-system kernel).
 #pragma once
 
 #include "device_common.h"
@@ -44,6 +48,9 @@ __device__ __forceinline__ void lane_increments(ConstTab T, const double (&Q)[DQ
     for (int l = 0; l < DQ; ++l) q[l] = Q[l][s];
 #ifdef IRKGL16_USER_FORCE
     if constexpr (KIND == kUser) user_increment<DQ>(q, hb, prm, stage_time(step, h, r[kTabC + s]), out);
+#endif
+#ifdef IRKGL16_USER_ODE
+    if constexpr (KIND == kUserOde) ode_increment<DQ>(q, hb, prm, stage_time(step, h, r[kTabC + s]), out);
 #endif
     if constexpr (KIND == kKepler) kepler_increment<DQ, EXACT>(q, hb, G, out);
 #pragma unroll
@@ -129,7 +136,7 @@ __global__ __launch_bounds__(64) void lane_kernel(LaunchArgs a) {
 #pragma unroll
         for (int s = 0; s < kS; ++s) R[l][s] = S[4 * DQ + l * kS + s];
       }
-      initial_guess<DQ, EXACT>(T, qh, vh, R, h, Qc);
+      form_guess<KIND, DQ, EXACT>(T, qh, vh, R, h, Qc);
     }
 
     // ---- one step, all live lanes in lockstep
@@ -150,7 +157,7 @@ __global__ __launch_bounds__(64) void lane_kernel(LaunchArgs a) {
           const ConstTab r = row_tab(T);
 #pragma unroll
           for (int l = 0; l < DQ; ++l) {
-            const double qn = stage_value<EXACT>(r, s, qh[l], vh[l], h, R[l]);
+            const double qn = form_stage_value<KIND, EXACT>(r, s, qh[l], vh[l], h, R[l]);
             max_track(dmax[l], nf[l], fabs(qn - Qc[l][s]));
             Qc[l][s] = qn;
           }
@@ -178,7 +185,7 @@ __global__ __launch_bounds__(64) void lane_kernel(LaunchArgs a) {
 #pragma unroll
           for (int l = 0; l < DQ; ++l) {
             a.qout[out_off + f * DQ + l] = __builtin_nan("");
-            a.pout[out_off + f * DQ + l] = __builtin_nan("");
+            if constexpr (KIND != kUserOde) a.pout[out_off + f * DQ + l] = __builtin_nan("");
           }
         }
         if (iters_off >= 0) a.step_iters[iters_off + step] = (uint8_t)kl;
@@ -193,23 +200,18 @@ __global__ __launch_bounds__(64) void lane_kernel(LaunchArgs a) {
       } else {
         const ConstTab r = row_tab(T);
 #pragma unroll
-        for (int l = 0; l < DQ; ++l) {
-          double sv, sc;
-          step_sums<EXACT>(r, R[l], sv, sc);
-          dw_add(vh[l], vl[l], sv);
-          dw_add(qh[l], ql[l], h * (vh[l] - sc));
-        }
+        for (int l = 0; l < DQ; ++l) form_update<KIND, EXACT>(r, R[l], h, qh[l], ql[l], vh[l], vl[l]);
         if (iters_off >= 0) a.step_iters[iters_off + step] = (uint8_t)kl;
         ++step;
         it_sum += kl;
         nonconv += (flags & 2) ? 1 : 0;
         if (kl > maxk) maxk = kl;
-        if (step % stride == 0) {  // unit masses: p = v
+        if (step % stride == 0) {  // unit masses: p = v; first order: y only
           const int64_t f = step / stride;
 #pragma unroll
           for (int l = 0; l < DQ; ++l) {
             a.qout[out_off + f * DQ + l] = qh[l];
-            a.pout[out_off + f * DQ + l] = vh[l];
+            if constexpr (KIND != kUserOde) a.pout[out_off + f * DQ + l] = vh[l];
           }
         }
         if (step >= target) {
@@ -232,7 +234,7 @@ __global__ __launch_bounds__(64) void lane_kernel(LaunchArgs a) {
           a.stat[inst] = st;
           release = true;
         } else {
-          initial_guess<DQ, EXACT>(T, qh, vh, R, h, Qc);
+          form_guess<KIND, DQ, EXACT>(T, qh, vh, R, h, Qc);
         }
       }
     }

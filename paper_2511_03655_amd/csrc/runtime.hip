@@ -118,6 +118,7 @@ struct irkgl16_ctx {
   std::vector<int32_t> h_queue;
   irk::TuneTable tune;  // launch shapes (read at creation)
   irk::UserKernel* user = nullptr;  // run-time compiled force (irkgl16_create_user)
+  bool ode = false;                 // first-order form: state y only, no p in or out
 
   // last call
   bool have_last = false;
@@ -163,6 +164,7 @@ struct UserSpec {
   const char* src;
   int32_t dq, n_params;
   const double* params;  // n_inst x n_params
+  bool ode;              // first-order right-hand side f(t, y) (irkgl16_create_ode)
 };
 
 static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t n_inst,
@@ -270,7 +272,9 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
   if (user) {
     std::string log;
     const int rc = irk::user_kernel_create(user->src, user->dq,
-                                           (c->flags & IRKGL16_REPRODUCIBLE) != 0, &c->user, &log);
+                                           (c->flags & IRKGL16_REPRODUCIBLE) != 0, user->ode,
+                                           &c->user, &log);
+    c->ode = user->ode;
     if (rc != 0) return fail(rc == -1 ? IRKGL16_EINVAL : IRKGL16_EDEVICE);
   }
   // Launch shapes from the tuning table.
@@ -478,7 +482,12 @@ static int integrate_impl(irkgl16_ctx* c, const double* q0, const double* p0, co
                           double* p_out, irkgl16_stats* stats) {
   if (!c) return IRKGL16_EINVAL;
   const int32_t n = c->n_inst;
-  if (n > 0 && (!q0 || !p0 || !h || !nsteps || !out_stride || !q_out || !p_out))
+  if (c->ode) {  // first-order form: y in q0 / q_out; p0 and p_out are not used
+    p0 = nullptr;
+    p_out = nullptr;
+  }
+  if (n > 0 && (!q0 || (!p0 && !c->ode) || !h || !nsteps || !out_stride || !q_out ||
+                (!p_out && !c->ode)))
     return IRKGL16_EINVAL;
   int64_t out_total = 0, iters_total = 0;
   for (int32_t i = 0; i < n; ++i) {
@@ -500,13 +509,15 @@ static int integrate_impl(irkgl16_ctx* c, const double* q0, const double* p0, co
   double *dqo = q_out, *dpo = p_out;
   if (!dev) {
     ALLOC_TRY(c->d_q0, sizeof(double) * (size_t)std::max<int64_t>(c->total_dq, 1));
-    ALLOC_TRY(c->d_p0, sizeof(double) * (size_t)std::max<int64_t>(c->total_dq, 1));
     ALLOC_TRY(c->d_qout, sizeof(double) * (size_t)std::max<int64_t>(out_total, 1));
-    ALLOC_TRY(c->d_pout, sizeof(double) * (size_t)std::max<int64_t>(out_total, 1));
     dq0 = c->d_q0.as<double>();
-    dp0 = c->d_p0.as<double>();
     dqo = c->d_qout.as<double>();
-    dpo = c->d_pout.as<double>();
+    if (!c->ode) {
+      ALLOC_TRY(c->d_p0, sizeof(double) * (size_t)std::max<int64_t>(c->total_dq, 1));
+      ALLOC_TRY(c->d_pout, sizeof(double) * (size_t)std::max<int64_t>(out_total, 1));
+      dp0 = c->d_p0.as<double>();
+      dpo = c->d_pout.as<double>();
+    }
   }
   if (c->record) ALLOC_TRY(c->d_iters, (size_t)std::max<int64_t>(iters_total, 1));
   c->last_nsteps.assign(nsteps, nsteps + n);
@@ -531,8 +542,9 @@ static int integrate_impl(irkgl16_ctx* c, const double* q0, const double* p0, co
   if (!dev) {
     HIP_TRY(hipMemcpyAsync(c->d_q0.p, q0, sizeof(double) * c->total_dq, hipMemcpyHostToDevice,
                            c->stream));
-    HIP_TRY(hipMemcpyAsync(c->d_p0.p, p0, sizeof(double) * c->total_dq, hipMemcpyHostToDevice,
-                           c->stream));
+    if (!c->ode)
+      HIP_TRY(hipMemcpyAsync(c->d_p0.p, p0, sizeof(double) * c->total_dq, hipMemcpyHostToDevice,
+                             c->stream));
   }
   HIP_TRY(hipEventRecord(c->ev0, c->stream));
   HIP_TRY(irk::launch_prepare(c->d_desc.as<irk::InstDesc>(), c->d_stat.as<irk::InstStat>(),
@@ -594,8 +606,9 @@ static int integrate_impl(irkgl16_ctx* c, const double* q0, const double* p0, co
   if (!dev) {
     HIP_TRY(hipMemcpyAsync(q_out, dqo, sizeof(double) * out_total, hipMemcpyDeviceToHost,
                            c->stream));
-    HIP_TRY(hipMemcpyAsync(p_out, dpo, sizeof(double) * out_total, hipMemcpyDeviceToHost,
-                           c->stream));
+    if (!c->ode)
+      HIP_TRY(hipMemcpyAsync(p_out, dpo, sizeof(double) * out_total, hipMemcpyDeviceToHost,
+                             c->stream));
     return irkgl16_last_stats(c, stats);
   }
   if (stats) return irkgl16_last_stats(c, stats);
@@ -629,7 +642,7 @@ int irkgl16_create_user(irkgl16_ctx** out, const char* force_src, int32_t dq, in
       p.n = 1;
       p.d = dq;
     }
-    const UserSpec spec{force_src, dq, n_params, params};
+    const UserSpec spec{force_src, dq, n_params, params, false};
     return create_impl(out, probs.data(), n_inst, opt, hip_stream, &spec);
   } catch (const std::bad_alloc&) {
     return IRKGL16_ENOMEM;
@@ -638,10 +651,33 @@ int irkgl16_create_user(irkgl16_ctx** out, const char* force_src, int32_t dq, in
   }
 }
 
-int irkgl16_user_compile_check(const char* force_src, int32_t dq, char* log, int64_t log_len) {
+int irkgl16_create_ode(irkgl16_ctx** out, const char* rhs_src, int32_t D, int32_t n_params,
+                       const double* params, int32_t n_inst, const irkgl16_options* opt,
+                       void* hip_stream) {
+  try {
+    if (!out) return IRKGL16_EINVAL;
+    *out = nullptr;
+    if (n_inst < 0 || !rhs_src || !irk::user_dq_supported(D)) return IRKGL16_EINVAL;
+    std::vector<irkgl16_problem> probs((size_t)std::max(n_inst, 1));
+    for (auto& p : probs) {
+      std::memset(&p, 0, sizeof(p));
+      p.kind = irk::kUserOde;
+      p.n = 1;
+      p.d = D;
+    }
+    const UserSpec spec{rhs_src, D, n_params, params, true};
+    return create_impl(out, probs.data(), n_inst, opt, hip_stream, &spec);
+  } catch (const std::bad_alloc&) {
+    return IRKGL16_ENOMEM;
+  } catch (...) {
+    return IRKGL16_EDEVICE;
+  }
+}
+
+static int compile_check(const char* src, int32_t dq, bool ode, char* log, int64_t log_len) {
   try {
     std::string l;
-    const int rc = irk::user_compile_check(force_src, dq, &l);
+    const int rc = irk::user_compile_check(src, dq, ode, &l);
     if (log && log_len > 0) {
       const size_t n = std::min<size_t>(l.size(), (size_t)(log_len - 1));
       std::memcpy(log, l.data(), n);
@@ -653,6 +689,14 @@ int irkgl16_user_compile_check(const char* force_src, int32_t dq, char* log, int
   } catch (...) {
     return IRKGL16_EDEVICE;
   }
+}
+
+int irkgl16_user_compile_check(const char* force_src, int32_t dq, char* log, int64_t log_len) {
+  return compile_check(force_src, dq, false, log, log_len);
+}
+
+int irkgl16_ode_compile_check(const char* rhs_src, int32_t D, char* log, int64_t log_len) {
+  return compile_check(rhs_src, D, true, log, log_len);
 }
 
 int irkgl16_integrate(irkgl16_ctx* ctx, const double* q0, const double* p0, const double* h,

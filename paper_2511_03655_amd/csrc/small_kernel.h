@@ -20,9 +20,15 @@
 // the resumable state back and pull the next instance from the class queue.
 // Each instance's arithmetic is independent of which slot or wave runs it.
 //
+// KIND == kUserOde runs the first-order form (section 2.4, eqs. Yi2 / yn2;
+// section 2.5, eqs. IRK_init / IRK_FP) with the same two roles: stage lanes
+// evaluate f(t, Y_sub), component lanes form Y_i = y + sum_j mu_ij L_j and
+// update y + sum_i L_i.
+//
 // Device code only: the library compiles it ahead of time for the built-in
-// forces (k_small.hip) and, for a user-supplied force, at run time with hiprtc
-// (IRKGL16_USER_FORCE defined, the force function defined before this header).
+// forces (k_small.hip) and, for a user-supplied force or right-hand side, at
+// run time with hiprtc (IRKGL16_USER_FORCE or IRKGL16_USER_ODE defined, the
+// function defined before this header).
 #pragma once
 
 #include "device_common.h"
@@ -46,6 +52,17 @@ __device__ __forceinline__ void stage_increment(double* __restrict__ Xs, int sub
 #pragma unroll
     for (int l = 0; l < DQ; ++l) q[l] = Xs[l * kS + sub];
     user_increment<DQ>(q, hb, prm, t, r);
+#pragma unroll
+    for (int l = 0; l < DQ; ++l) Xs[l * kS + sub] = r[l];
+    return;
+  }
+#endif
+#ifdef IRKGL16_USER_ODE
+  if constexpr (KIND == kUserOde) {  // L = h b_sub f(t_sub, Y_sub), first-order form
+    double y[DQ], r[DQ];
+#pragma unroll
+    for (int l = 0; l < DQ; ++l) y[l] = Xs[l * kS + sub];
+    ode_increment<DQ>(y, hb, prm, t, r);
 #pragma unroll
     for (int l = 0; l < DQ; ++l) Xs[l * kS + sub] = r[l];
     return;
@@ -228,7 +245,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
 #pragma unroll
         for (int s = 0; s < kS; ++s) Rp[cc][s] = S[4 * DQ + c * kS + s];
       }
-      initial_guess<CPL, EXACT>(T, qh, vh, Rp, M.h, Qc);
+      form_guess<KIND, CPL, EXACT>(T, qh, vh, Rp, M.h, Qc);
     }
 
     // ---- one step, all live slots in lockstep
@@ -270,7 +287,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
           const ConstTab r = row_tab(T);
 #pragma unroll
           for (int cc = 0; cc < CPL; ++cc) {
-            const double qn = stage_value<EXACT>(r, s, qh[cc], vh[cc], h, R[cc]);
+            const double qn = form_stage_value<KIND, EXACT>(r, s, qh[cc], vh[cc], h, R[cc]);
             max_track(dmax[cc], nf[cc], fabs(qn - Qc[cc][s]));
             Qc[cc][s] = qn;
           }
@@ -309,7 +326,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
           for (int cc = 0; cc < CPL; ++cc) {
             if (owns(cc)) {
               a.qout[out_off + f * DQ + comp(cc)] = __builtin_nan("");
-              a.pout[out_off + f * DQ + comp(cc)] = __builtin_nan("");
+              if constexpr (KIND != kUserOde) a.pout[out_off + f * DQ + comp(cc)] = __builtin_nan("");
             }
           }
         }
@@ -335,16 +352,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
         for (int cc = 0; cc < CPL; ++cc) {
 #pragma unroll
           for (int s = 0; s < kS; ++s) R[cc][s] = Xs[cidx(cc) * kS + s];
-          double sv, sc;
-          step_sums<EXACT>(r, R[cc], sv, sc);
-          dw_add(vh[cc], vl[cc], sv);
-          dw_add(qh[cc], ql[cc], h * (vh[cc] - sc));
+          form_update<KIND, EXACT>(r, R[cc], h, qh[cc], ql[cc], vh[cc], vl[cc]);
           if (owns(cc)) {
             const int c = comp(cc);
             if (frame) {
               const int64_t f = step / stride;
               a.qout[out_off + f * DQ + c] = qh[cc];
-              a.pout[out_off + f * DQ + c] = M.m[c / D] * vh[cc];
+              if constexpr (KIND != kUserOde) a.pout[out_off + f * DQ + c] = M.m[c / D] * vh[cc];
             }
             if (last) {
               S[c] = qh[cc];
@@ -356,7 +370,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
             }
           }
         }
-        if (!last) initial_guess<CPL, EXACT>(T, qh, vh, R, h, Qc);
+        if (!last) form_guess<KIND, CPL, EXACT>(T, qh, vh, R, h, Qc);
         if (sub == 0) {
           if (M.iters_off >= 0) a.step_iters[M.iters_off + step0] = (uint8_t)kslot;
           M.step = step;

@@ -5,15 +5,15 @@
 //
 // The program handed to hiprtc is
 //
-//     #define IRKGL16_USER_FORCE 1
+//     #define IRKGL16_USER_FORCE 1       (or IRKGL16_USER_ODE: first-order form)
 //     #define IRKGL16_DQ <dq>
-//     <caller's source, which defines irkgl16_user_force>
+//     <caller's source, which defines irkgl16_user_force (or irkgl16_user_rhs)>
 //     #include "lane_kernel.h"     (dq <= kLaneMaxDq: one instance per lane)
 //     #include "small_kernel.h"    (otherwise: one instance per 8-lane slot)
 //
 // with the device headers served from copies embedded in this library at
 // build time, so the run-time kernel is the same code as the ahead-of-time
-// one.  Compiled code objects are cached per process by (source, dq,
+// one.  Compiled code objects are cached per process by (source, dq, form,
 // arithmetic mode).
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
@@ -39,13 +39,12 @@ constexpr int kNumRtcHeaders = (int)(sizeof(kRtcHeaderNames) / sizeof(kRtcHeader
 
 bool use_lane_kernel(int dq) { return dq <= kLaneMaxDqHost; }
 
-std::string kernel_expr(int dq, bool exact) {
+std::string kernel_expr(int dq, bool exact, bool ode) {
   const std::string mode = exact ? "true" : "false";
+  const std::string kind = std::to_string(ode ? kUserOde : kUser);
   if (use_lane_kernel(dq))
-    return "&irk::lane_kernel<" + std::to_string(kUser) + ", " + std::to_string(dq) + ", " + mode +
-           ">";
-  return "&irk::small_kernel<" + std::to_string(kUser) + ", 1, " + std::to_string(dq) + ", " +
-         mode + ">";
+    return "&irk::lane_kernel<" + kind + ", " + std::to_string(dq) + ", " + mode + ">";
+  return "&irk::small_kernel<" + kind + ", 1, " + std::to_string(dq) + ", " + mode + ">";
 }
 
 struct Compiled {
@@ -54,12 +53,13 @@ struct Compiled {
 };
 
 std::mutex g_cache_mu;
-std::map<std::tuple<std::string, int, bool>, Compiled> g_cache;
+std::map<std::tuple<std::string, int, bool, bool>, Compiled> g_cache;
 
-// Compiles the program for one (source, dq, mode); on failure returns false
-// and the compiler log in *log.
-bool compile(const char* src, int dq, bool exact, Compiled* out, std::string* log) {
-  std::string prog = "#define IRKGL16_USER_FORCE 1\n#define IRKGL16_DQ " + std::to_string(dq) +
+// Compiles the program for one (source, dq, form, mode); on failure returns
+// false and the compiler log in *log.
+bool compile(const char* src, int dq, bool exact, bool ode, Compiled* out, std::string* log) {
+  std::string prog = std::string(ode ? "#define IRKGL16_USER_ODE 1" : "#define IRKGL16_USER_FORCE 1") +
+                     "\n#define IRKGL16_DQ " + std::to_string(dq) +
                      "\n#line 1 \"user_force\"\n" + src + "\n#line 1 \"irkgl16_rtc\"\n" +
                      (use_lane_kernel(dq) ? "#include \"lane_kernel.h\"\n"
                                           : "#include \"small_kernel.h\"\n");
@@ -69,7 +69,7 @@ bool compile(const char* src, int dq, bool exact, Compiled* out, std::string* lo
     *log = "hiprtcCreateProgram failed";
     return false;
   }
-  const std::string expr = kernel_expr(dq, exact);
+  const std::string expr = kernel_expr(dq, exact, ode);
   bool ok = hiprtcAddNameExpression(p, expr.c_str()) == HIPRTC_SUCCESS;
   const char* opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off",
                         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
@@ -100,8 +100,9 @@ bool compile(const char* src, int dq, bool exact, Compiled* out, std::string* lo
   return ok;
 }
 
-bool compile_cached(const char* src, int dq, bool exact, Compiled* out, std::string* log) {
-  const auto key = std::make_tuple(std::string(src), dq, exact);
+bool compile_cached(const char* src, int dq, bool exact, bool ode, Compiled* out,
+                    std::string* log) {
+  const auto key = std::make_tuple(std::string(src), dq, exact, ode);
   {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     auto it = g_cache.find(key);
@@ -110,7 +111,7 @@ bool compile_cached(const char* src, int dq, bool exact, Compiled* out, std::str
       return true;
     }
   }
-  if (!compile(src, dq, exact, out, log)) return false;
+  if (!compile(src, dq, exact, ode, out, log)) return false;
   std::lock_guard<std::mutex> lk(g_cache_mu);
   g_cache[key] = *out;
   return true;
@@ -120,25 +121,27 @@ bool compile_cached(const char* src, int dq, bool exact, Compiled* out, std::str
 
 bool user_dq_supported(int dq) { return dq >= 1 && dq <= kUserMaxDq; }
 
-int user_compile_check(const char* src, int dq, std::string* log) {
+int user_compile_check(const char* src, int dq, bool ode, std::string* log) {
   log->clear();
   if (!src || !user_dq_supported(dq)) {
-    *log = "invalid source pointer or dq";
+    *log = "invalid source pointer or dimension";
     return -1;
   }
   Compiled c;
-  return compile_cached(src, dq, false, &c, log) ? 0 : -1;
+  return compile_cached(src, dq, false, ode, &c, log) ? 0 : -1;
 }
 
-int user_kernel_create(const char* src, int dq, bool exact, UserKernel** out, std::string* log) {
+int user_kernel_create(const char* src, int dq, bool exact, bool ode, UserKernel** out,
+                       std::string* log) {
   *out = nullptr;
   log->clear();
   if (!src || !user_dq_supported(dq)) return -1;
   Compiled c;
-  if (!compile_cached(src, dq, exact, &c, log)) return -1;
+  if (!compile_cached(src, dq, exact, ode, &c, log)) return -1;
   UserKernel* k = new UserKernel();
   k->dq = dq;
   k->exact = exact;
+  k->ode = ode;
   k->lanes_per_inst = use_lane_kernel(dq) ? 1 : 8;
   if (hipModuleLoadData(&k->mod, c.code.data()) != hipSuccess ||
       hipModuleGetFunction(&k->fn, k->mod, c.lowered.c_str()) != hipSuccess) {

@@ -28,7 +28,7 @@ IRKGL16_DEVICE_PTRS, IRKGL16_PLAIN, IRKGL16_REPRODUCIBLE, IRKGL16_GRAPH = 1, 2, 
 EXPORTED = ["irkgl16_create", "irkgl16_integrate", "irkgl16_last_stats", "irkgl16_destroy",
             "irkgl16_strerror", "irkgl16_server_create", "irkgl16_submit", "irkgl16_poll",
             "irkgl16_wait", "irkgl16_server_destroy", "irkgl16_create_user",
-            "irkgl16_user_compile_check"]
+            "irkgl16_user_compile_check", "irkgl16_create_ode", "irkgl16_ode_compile_check"]
 
 
 class irkgl16_problem(C.Structure):
@@ -105,6 +105,10 @@ def lib():
         L.irkgl16_create_user.restype = C.c_int
         L.irkgl16_user_compile_check.argtypes = [C.c_char_p, C.c_int32, C.c_char_p, C.c_int64]
         L.irkgl16_user_compile_check.restype = C.c_int
+        L.irkgl16_create_ode.argtypes = L.irkgl16_create_user.argtypes
+        L.irkgl16_create_ode.restype = C.c_int
+        L.irkgl16_ode_compile_check.argtypes = [C.c_char_p, C.c_int32, C.c_char_p, C.c_int64]
+        L.irkgl16_ode_compile_check.restype = C.c_int
         _lib = L
     return _lib
 
@@ -181,6 +185,31 @@ def irkgl16_user_compile_check(force_src, dq, log_len=1 << 16):
     return rc, buf.value.decode(errors="replace")
 
 
+def irkgl16_create_ode(rhs_src, D, params, n_inst, max_iter=0, record_iters=False, flags=0,
+                       stream=None):
+    """First-order context (y' = f(t, y)) for n_inst instances of D components."""
+    prm = None if params is None else np.ascontiguousarray(params, np.float64).reshape(n_inst, -1)
+    n_params = 0 if prm is None else prm.shape[1]
+    opt = irkgl16_options(int(max_iter), int(bool(record_iters)), int(flags))
+    if stream is not None and hasattr(stream, "cuda_stream"):
+        stream = stream.cuda_stream
+    ctx = C.c_void_p()
+    rc = lib().irkgl16_create_ode(
+        C.byref(ctx), rhs_src.encode(), int(D), int(n_params),
+        prm.ctypes.data_as(C.POINTER(C.c_double)) if n_params > 0 else None, int(n_inst),
+        C.byref(opt), C.c_void_p(stream) if stream else None)
+    if rc != IRKGL16_OK:
+        raise IRKGL16Error(rc, "irkgl16_create_ode")
+    return ctx
+
+
+def irkgl16_ode_compile_check(rhs_src, D, log_len=1 << 16):
+    """Returns (status, compiler log)."""
+    buf = C.create_string_buffer(log_len)
+    rc = lib().irkgl16_ode_compile_check(rhs_src.encode(), int(D), buf, log_len)
+    return rc, buf.value.decode(errors="replace")
+
+
 def irkgl16_integrate(ctx, q0, p0, h, nsteps, out_stride, q_out, p_out, stats=None):
     h = np.ascontiguousarray(h, np.float64)
     ns = np.ascontiguousarray(nsteps, np.int64)
@@ -225,6 +254,22 @@ class Integrator:
                                        flags, stream)
         return self
 
+    @classmethod
+    def ode(cls, rhs_src, D, n_inst, params=None, max_iter=0, record_iters=False, flags=0,
+            stream=None):
+        """Integrator of n_inst first-order instances (irkgl16_create_ode): y0 is
+        passed as q0; integrate returns the y frames as q_out (p_out is None)."""
+        self = cls.__new__(cls)
+        self.problems = [dict(kind=-2, n=1, d=int(D))] * int(n_inst)
+        self.dq = np.full(int(n_inst), int(D), np.int64)
+        self.flags = int(flags)
+        self.record_iters = bool(record_iters)
+        self.is_ode = True
+        self.ctx = None
+        self.ctx = irkgl16_create_ode(rhs_src, D, params, n_inst, max_iter, record_iters, flags,
+                                      stream)
+        return self
+
     def close(self):
         if getattr(self, "ctx", None):
             irkgl16_destroy(self.ctx)
@@ -243,12 +288,13 @@ class Integrator:
         sd = np.broadcast_to(np.asarray(out_stride, np.int64), (n,))
         total = int(np.sum(self.dq * (ns // np.maximum(sd, 1) + 1)))
         dev = bool(self.flags & IRKGL16_DEVICE_PTRS)
+        ode = getattr(self, "is_ode", False)
         if not dev:
             q0 = np.ascontiguousarray(q0, np.float64)
-            p0 = np.ascontiguousarray(p0, np.float64)
+            p0 = None if ode else np.ascontiguousarray(p0, np.float64)
             if q_out is None:
                 q_out = np.empty(total)
-            if p_out is None:
+            if p_out is None and not ode:
                 p_out = np.empty(total)
         st = irkgl16_stats()
         inst_it = np.zeros(n, np.int64)

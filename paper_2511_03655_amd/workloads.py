@@ -18,6 +18,9 @@ stand-ins used for throughput):
 * :func:`fpu_chain` -- a Fermi-Pasta-Ulam-beta chain with fixed ends, energy
   in the lowest mode plus small Gaussian noise.
 * :func:`uneven_mix` -- the mixed batch of gravitational systems and chains.
+* :func:`schwarzschild_ensemble` -- states of the charged particle near a
+  Schwarzschild black hole of section 5.1.1 (theta = pi/2, p_r = 0, r around
+  the paper's r = 11, p_theta from H = -1/2).
 * :func:`henon_heiles_ensemble` -- Henon-Heiles initial states on the
   surface q1 = 0 (section 5.1.2's problem: q2 = 0.3, p2 = 0.2, H = 1/12 and
   perturbations of it, or other energies).
@@ -272,3 +275,22 @@ def henon_heiles_ensemble(n, seed=BASE_SEED + 6, energy=1 / 12, q2_range=(0.25, 
         q.append([0.0, q2])
         p.append([np.sqrt(rest), p2])
     return np.array(q), np.array(p)
+
+
+SBH_PARAMS = (0.995, 4.6, 8.9e-4)  # E, L, beta of section 5.1.1
+
+
+def schwarzschild_ensemble(n, seed=BASE_SEED + 7, r_range=(10.5, 11.5), params=SBH_PARAMS,
+                           energy=-0.5):
+    """n states y = (r, theta, p_r, p_theta) of eq. Ham_SBH: theta = pi/2,
+    p_r = 0, r uniform in r_range, p_theta > 0 from H = energy (the paper:
+    r = 11, H = -1/2)."""
+    E, L, b = params
+    rng = np.random.default_rng(seed)
+    r0 = rng.uniform(r_range[0], r_range[1], n)
+    A = 1 - 2 / r0
+    w = L - b * r0 * r0 / 2
+    pth2 = 2 * r0 * r0 * (energy + E * E / (2 * A) - w * w / (2 * r0 * r0))
+    if np.any(pth2 <= 0):
+        raise ValueError("no p_theta > 0 reaches the requested energy for some r")
+    return np.stack([r0, np.full(n, np.pi / 2), np.zeros(n), np.sqrt(pth2)], 1)

@@ -161,3 +161,29 @@ def test_create_user_without_gpu_reports_edevice():
     with pytest.raises(K.IRKGL16Error) as e:
         K.irkgl16_create_user(UF.HENON_HEILES, 2, None, 3)
     assert e.value.code == K.IRKGL16_EDEVICE
+
+
+def test_ode_sources_compile_without_gpu():
+    from paper_2511_03655_amd import user_forces as UF
+    for src, D in ((UF.OSC_RHS, 2), (UF.KEPLER_RHS, 6), (UF.DAMPED_RHS, 2), (UF.DRIVEN_RHS, 2),
+                   (UF.SCHWARZSCHILD_RHS, 4), (UF.OSC_RHS, 16)):
+        rc, log = K.irkgl16_ode_compile_check(src, D)
+        assert rc == K.IRKGL16_OK, log
+    # a second-order force is not a first-order right-hand side, and vice versa
+    rc, _ = K.irkgl16_ode_compile_check(UF.HENON_HEILES, 2)
+    assert rc == K.IRKGL16_EINVAL
+    rc, _ = K.irkgl16_user_compile_check(UF.OSC_RHS, 2)
+    assert rc == K.IRKGL16_EINVAL
+    for D in (0, 65):
+        rc, _ = K.irkgl16_ode_compile_check(UF.OSC_RHS, D)
+        assert rc == K.IRKGL16_EINVAL
+
+
+@pytest.mark.skipif(_has_gpu(), reason="checks the no-device path")
+def test_create_ode_without_gpu_reports_edevice():
+    from paper_2511_03655_amd import user_forces as UF
+    with pytest.raises(K.IRKGL16Error) as e:
+        K.irkgl16_create_ode(UF.DAMPED_RHS, 2, np.array([[0.1]]), 1)
+    assert e.value.code == K.IRKGL16_EDEVICE
+    L = K.lib()
+    assert L.irkgl16_create_ode(None, None, 2, 0, None, 1, None, None) == K.IRKGL16_EINVAL
