@@ -142,7 +142,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-served", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "henon"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "henon", "sbh"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -346,15 +346,15 @@ def _flops_inst_step(inst, k):
     return k * (8 * fg + 8 * dq * 21) + 8 * dq * 36 + 50 * dq
 
 
-def _timed_gpu(integ, q0, p0, h, ns, sd, reps=1):
+def _timed_gpu(integ, q0, p0, h, ns, sd, reps=1, ode=False):
     import torch
     from paper_2511_03655_amd import irkgl16 as K
     dev = torch.device("cuda:0")
     q0d = torch.from_numpy(np.ascontiguousarray(q0)).to(dev)
-    p0d = torch.from_numpy(np.ascontiguousarray(p0)).to(dev)
+    p0d = None if ode else torch.from_numpy(np.ascontiguousarray(p0)).to(dev)
     total = int(np.sum(integ.dq * (np.asarray(ns) // np.asarray(sd) + 1)))
     qo = torch.empty(total, dtype=torch.float64, device=dev)
-    po = torch.empty_like(qo)
+    po = None if ode else torch.empty_like(qo)
     ones = np.ones(len(np.atleast_1d(ns)), np.int64)
     K.irkgl16_integrate(integ.ctx, q0d, p0d, h, ones, ones, qo, po)  # warm-up: one step
     torch.cuda.synchronize()
@@ -593,7 +593,85 @@ def run_henon(args):
                     "cpu_baseline": cpu})
 
 
-OTHER_WORKLOADS = {"c1": run_c1, "c3": run_c3, "c4": run_c4, "c5": run_c5, "henon": run_henon}
+def run_sbh(args):
+    """First-order form: charged particles near a Schwarzschild black hole
+    (eq. Ham_SBH), right-hand side compiled at run time."""
+    import torch
+    from paper_2511_03655_amd import irkgl16 as K
+    from paper_2511_03655_amd import user_forces as UF
+    from paper_2511_03655_amd import workloads as W
+    from oracle import oracle as orc
+    n_inst, nsteps, h = 65536, 10_000, 2.0
+    Y0 = W.schwarzschild_ensemble(n_inst)
+    prm = np.tile(W.SBH_PARAMS, (n_inst, 1))
+    stream = torch.cuda.Stream()
+    t = time.perf_counter()
+    integ = K.Integrator.ode(UF.SCHWARZSCHILD_RHS, 4, n_inst, params=prm,
+                             flags=K.IRKGL16_DEVICE_PTRS, stream=stream)
+    t_compile = time.perf_counter() - t
+    ns = np.full(n_inst, nsteps, np.int64)
+    y0 = Y0.ravel()
+    dt, st, rc, yo, _ = _timed_gpu(integ, y0, y0, np.full(n_inst, h), ns, ns, reps=2, ode=True)
+    inst_steps = n_inst * nsteps
+    k = st["iterations"] / inst_steps
+    # 40 flops per right-hand-side evaluation (trigonometric calls, square
+    # roots and divisions count 1), the rest by the per-component convention
+    flops = st["iterations"] * (8 * 40 + 8 * 4 * 21) + inst_steps * (8 * 4 * 36 + 50 * 4)
+    kern_s = st["device_ms"] / 1e3
+    y = yo.cpu().numpy().reshape(n_inst, 2, 4)
+    E, L, b = W.SBH_PARAMS
+
+    def energy(v):
+        r, th, pr, pth = v[:, 0], v[:, 1], v[:, 2], v[:, 3]
+        A = 1 - 2 / r
+        u = r * r * np.sin(th) ** 2
+        return 0.5 * A * pr * pr - 0.5 * E * E / A + pth * pth / (2 * r * r) + \
+            (L - 0.5 * b * u) ** 2 / (2 * u)
+
+    dE = np.abs(energy(y[:, 1]) - energy(y[:, 0])) / 0.5
+    n_p, s_p = 64, 200
+    plain = K.Integrator.ode(UF.SCHWARZSCHILD_RHS, 4, n_p, params=prm[:n_p],
+                             flags=K.IRKGL16_PLAIN)
+    plain.integrate(y0[:4 * n_p], None, h, 20, 20)
+    t = time.perf_counter()
+    plain.integrate(y0[:4 * n_p], None, h, s_p, s_p)
+    dtp = time.perf_counter() - t
+    cpu = None
+    if not args.no_cpu:
+        n_c, s_c = 65536, 5000
+        spec = orc.Spec(orc.ODE_SBH, 1, 4, G=E, eps=L, beta=b)
+        orc.lib()
+        t = time.perf_counter()
+        orc.integrate_ode_batch([spec] * n_c, y0[:4 * n_c], h, s_c, s_c)
+        dtc = time.perf_counter() - t
+        cpu = {"value": n_c * s_c / dtc, "unit": "instance-steps/s",
+               "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+               "kind": "oracle",
+               "sample": f"{n_c} instances x {s_c} steps ({dtc:.1f} s, OpenMP over instances)"}
+    return _common("instance-steps/s", inst_steps / dt,
+                   {"workload": f"{n_inst} Schwarzschild-black-hole orbits (E=0.995, L=4.6, "
+                                f"beta=8.9e-4, r0 in [10.5, 11.5], H=-1/2), first-order form, "
+                                f"h={h}, {nsteps} steps, final state; right-hand side given as "
+                                "device source and compiled at run time"},
+                   {"seconds": dt, "compile_and_create_s": t_compile,
+                    "mean_iterations_per_step": k,
+                    "roofline": {"bound": "alu", "achieved": flops / kern_s / 1e12,
+                                 "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                 "frac": flops / kern_s / 1e12 / FP64_PEAK_TFLOPS,
+                                 "traffic": None,
+                                 "kernel": "lane_kernel<user ODE, D=4> (hiprtc)",
+                                 "kernel_ms": st["device_ms"]},
+                    "accuracy": {"gate": "relative energy error first->last frame <= 1e-12",
+                                 "pass_frac": float(np.mean(dE <= 1e-12)),
+                                 "median_dE": float(np.median(dE))},
+                    "plain": {"value": n_p * s_p / dtp, "unit": "instance-steps/s",
+                              "sample": f"{n_p} instances x {s_p} steps, one launch per step "
+                                        "per instance"},
+                    "cpu_baseline": cpu})
+
+
+OTHER_WORKLOADS = {"c1": run_c1, "c3": run_c3, "c4": run_c4, "c5": run_c5, "henon": run_henon,
+                   "sbh": run_sbh}
 
 
 if __name__ == "__main__":

@@ -131,8 +131,12 @@ __global__ __launch_bounds__(64) void lane_kernel(LaunchArgs a) {
       for (int l = 0; l < DQ; ++l) {
         qh[l] = S[l];
         ql[l] = S[DQ + l];
-        vh[l] = S[2 * DQ + l];
-        vl[l] = S[3 * DQ + l];
+        if constexpr (KIND == kUserOde) {  // first order: no velocity state
+          vh[l] = vl[l] = 0.0;
+        } else {
+          vh[l] = S[2 * DQ + l];
+          vl[l] = S[3 * DQ + l];
+        }
 #pragma unroll
         for (int s = 0; s < kS; ++s) R[l][s] = S[4 * DQ + l * kS + s];
       }
@@ -220,8 +224,10 @@ __global__ __launch_bounds__(64) void lane_kernel(LaunchArgs a) {
           for (int l = 0; l < DQ; ++l) {
             S[l] = qh[l];
             S[DQ + l] = ql[l];
-            S[2 * DQ + l] = vh[l];
-            S[3 * DQ + l] = vl[l];
+            if constexpr (KIND != kUserOde) {
+              S[2 * DQ + l] = vh[l];
+              S[3 * DQ + l] = vl[l];
+            }
 #pragma unroll
             for (int s = 0; s < kS; ++s) S[4 * DQ + l * kS + s] = R[l][s];
           }
