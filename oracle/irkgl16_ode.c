@@ -1,6 +1,7 @@
 /*
  * Plain FP64 oracle for fixed-step IRKGL16 in the floating-point-symplectic
- * FIRST-ORDER (mu) formulation, for y' = f(t, y) with y in R^D.
+ * FIRST-ORDER (mu) formulation, for y' = f(t, y) with y in R^D (and, with
+ * orc_integrate_ode_s, the s-stage members s = 2, 4, 6: s in place of 8).
  *
  * TEST INFRASTRUCTURE ONLY.  Like irkgl16_oracle.c it shares no code, header,
  * table or helper with the GPU library; only the test-suite, the smoke check
@@ -61,6 +62,13 @@ enum { ODE_OK = 0, ODE_EINVAL = -1, ODE_ENOMEM = -2, ODE_ENONFINITE = -4 };
 
 void orc_dw_add(double *hi, double *lo, double delta);
 int orc_stop_component(double delta, double *mind, double *prev);
+
+/* tables of the s-stage member (defined in irkgl16_oracle.c) */
+typedef struct {
+  int s;
+  const double *c, *b, *eta, *mu, *nu;
+} orc_tab;
+int orc_stage_tables(int s, orc_tab *T);
 
 static int ode_dim(const ode_problem *p) { return p->n * p->d; }
 
@@ -174,24 +182,26 @@ double orc_energy_ode(const ode_problem *p, const double *y) {
  * (y.hi).  iters (nullable): k of each step.  After a non-finite Delta the
  * instance stops and its remaining frames are NaN.
  */
-int orc_integrate_ode(const ode_problem *p, const double *y0, double h, int64_t nsteps,
-                      int64_t stride, int32_t max_iter, double *y_out, int32_t *iters,
-                      ode_stats *st) {
+static int ode_core(const ode_problem *p, const orc_tab *T, const double *y0, double h,
+                    int64_t nsteps, int64_t stride, int32_t max_iter, double *y_out,
+                    int32_t *iters, ode_stats *st) {
   if (!ode_valid(p) || !isfinite(h) || nsteps < 0 || stride < 1 || nsteps % stride ||
       max_iter < 1)
     return ODE_EINVAL;
   const int D = ode_dim(p);
-  double *buf = (double *)calloc((size_t)D * (4 + 4 * S), sizeof(double));
+  const int s = T->s;
+  const double *mu = T->mu, *nu = T->nu;
+  double *buf = (double *)calloc((size_t)D * (4 + 4 * s), sizeof(double));
   if (!buf) return ODE_ENOMEM;
   double *yh = buf, *yl = yh + D, *mind = yl + D, *prev = mind + D;
-  double *Y = prev + D, *Yn = Y + S * D, *L = Yn + S * D, *Lp = L + S * D;
+  double *Y = prev + D, *Yn = Y + s * D, *L = Yn + s * D, *Lp = L + s * D;
   double F[64];
   if (D > 64) {
     free(buf);
     return ODE_EINVAL;
   }
   double hb[S];
-  for (int i = 0; i < S; ++i) hb[i] = h * ORC_B[i];
+  for (int i = 0; i < s; ++i) hb[i] = h * T->b[i];
   for (int l = 0; l < D; ++l) {
     yh[l] = y0[l];
     y_out[l] = y0[l];
@@ -201,38 +211,38 @@ int orc_integrate_ode(const ode_problem *p, const double *y0, double h, int64_t 
   for (int64_t n = 1; n <= nsteps; ++n) {
     if (!dead) {
       /* initial guess: Y_i = y + sum_j nu_ij L_prev_j */
-      for (int i = 0; i < S; ++i)
+      for (int i = 0; i < s; ++i)
         for (int l = 0; l < D; ++l) {
-          double s = 0.0;
-          for (int j = 0; j < S; ++j) s += ORC_NU[i][j] * Lp[j * D + l];
-          Y[i * D + l] = yh[l] + s;
+          double sum = 0.0;
+          for (int j = 0; j < s; ++j) sum += nu[i * s + j] * Lp[j * D + l];
+          Y[i * D + l] = yh[l] + sum;
         }
       for (int l = 0; l < D; ++l) mind[l] = prev[l] = INFINITY;
       int k = 0, conv = 0;
       const double t_prev = (double)(n - 1) * h;
       while (!conv && k < max_iter) {
         ++k;
-        for (int i = 0; i < S; ++i) {
-          orc_rhs(p, t_prev + ORC_C[i] * h, Y + i * D, F);
+        for (int i = 0; i < s; ++i) {
+          orc_rhs(p, t_prev + T->c[i] * h, Y + i * D, F);
           for (int l = 0; l < D; ++l) L[i * D + l] = hb[i] * F[l];
         }
-        for (int i = 0; i < S; ++i)
+        for (int i = 0; i < s; ++i)
           for (int l = 0; l < D; ++l) {
-            double s = 0.0;
-            for (int j = 0; j < S; ++j) s += ORC_MU[i][j] * L[j * D + l];
-            Yn[i * D + l] = yh[l] + s;
+            double sum = 0.0;
+            for (int j = 0; j < s; ++j) sum += mu[i * s + j] * L[j * D + l];
+            Yn[i * D + l] = yh[l] + sum;
           }
         conv = 1;
         for (int l = 0; l < D; ++l) {
           double dl = 0.0;
-          for (int i = 0; i < S; ++i) {
+          for (int i = 0; i < s; ++i) {
             double a = fabs(Yn[i * D + l] - Y[i * D + l]);
             if (isnan(a) || a > dl) dl = a;
           }
           if (!isfinite(dl)) dead = 1;
           if (!orc_stop_component(dl, mind + l, prev + l)) conv = 0;
         }
-        memcpy(Y, Yn, sizeof(double) * S * D);
+        memcpy(Y, Yn, sizeof(double) * s * D);
         if (dead) break;
       }
       if (!dead) {
@@ -242,10 +252,10 @@ int orc_integrate_ode(const ode_problem *p, const double *y0, double h, int64_t 
         if (iters) iters[n - 1] = k;
         for (int l = 0; l < D; ++l) {
           double sum = 0.0;
-          for (int i = 0; i < S; ++i) sum += L[i * D + l];
+          for (int i = 0; i < s; ++i) sum += L[i * D + l];
           orc_dw_add(yh + l, yl + l, sum);
         }
-        memcpy(Lp, L, sizeof(double) * S * D);
+        memcpy(Lp, L, sizeof(double) * s * D);
         loc.steps_done = n;
       } else {
         loc.status = ODE_ENONFINITE;
@@ -259,6 +269,23 @@ int orc_integrate_ode(const ode_problem *p, const double *y0, double h, int64_t 
   if (st) *st = loc;
   free(buf);
   return loc.status;
+}
+
+int orc_integrate_ode(const ode_problem *p, const double *y0, double h, int64_t nsteps,
+                      int64_t stride, int32_t max_iter, double *y_out, int32_t *iters,
+                      ode_stats *st) {
+  orc_tab T;
+  orc_stage_tables(S, &T);
+  return ode_core(p, &T, y0, h, nsteps, stride, max_iter, y_out, iters, st);
+}
+
+/* The same with the s-stage member of the family (s = 2, 4, 6, 8). */
+int orc_integrate_ode_s(const ode_problem *p, int32_t s, const double *y0, double h,
+                        int64_t nsteps, int64_t stride, int32_t max_iter, double *y_out,
+                        int32_t *iters, ode_stats *st) {
+  orc_tab T;
+  if (!orc_stage_tables(s, &T)) return ODE_EINVAL;
+  return ode_core(p, &T, y0, h, nsteps, stride, max_iter, y_out, iters, st);
 }
 
 /* Many instances (OpenMP over instances); packed as the GPU library packs
@@ -291,6 +318,47 @@ int orc_integrate_ode_batch(int32_t n_inst, const ode_problem *probs, const doub
     ode_stats st;
     int rc = orc_integrate_ode(probs + i, y0 + in_off[i], h[i], nsteps[i], stride[i], max_iter,
                                y_out + out_off[i], NULL, &st);
+    if (iters_total) iters_total[i] = st.iterations;
+    if (status) status[i] = rc;
+    if (rc < 0) {
+#pragma omp critical
+      if (rc < worst) worst = rc;
+    }
+  }
+  free(in_off);
+  free(out_off);
+  return worst;
+}
+
+/* The same for the s-stage member. */
+int orc_integrate_ode_batch_s(int32_t n_inst, int32_t s, const ode_problem *probs, const double *y0,
+                            const double *h, const int64_t *nsteps, const int64_t *stride,
+                            int32_t max_iter, double *y_out, int64_t *iters_total,
+                            int32_t *status) {
+  int64_t *in_off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_inst + 1));
+  int64_t *out_off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_inst + 1));
+  if (!in_off || !out_off) {
+    free(in_off);
+    free(out_off);
+    return ODE_ENOMEM;
+  }
+  in_off[0] = out_off[0] = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    const int64_t D = (int64_t)probs[i].n * probs[i].d;
+    if (stride[i] < 1 || nsteps[i] < 0 || nsteps[i] % stride[i]) {
+      free(in_off);
+      free(out_off);
+      return ODE_EINVAL;
+    }
+    in_off[i + 1] = in_off[i] + D;
+    out_off[i + 1] = out_off[i] + D * (nsteps[i] / stride[i] + 1);
+  }
+  int worst = ODE_OK;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int i = 0; i < n_inst; ++i) {
+    ode_stats st;
+    int rc = orc_integrate_ode_s(probs + i, s, y0 + in_off[i], h[i], nsteps[i], stride[i],
+                                 max_iter, y_out + out_off[i], NULL, &st);
     if (iters_total) iters_total[i] = st.iterations;
     if (status) status[i] = rc;
     if (rc < 0) {

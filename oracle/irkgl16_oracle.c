@@ -1,6 +1,7 @@
 /*
  * Plain FP64 oracle for fixed-step IRKGL16 in the floating-point-symplectic
- * second-order (eta) formulation.
+ * second-order (eta) formulation (and, with orc_integrate_s, for the s-stage
+ * members s = 2, 4, 6 of the same family: the same steps with s in place of 8).
  *
  * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct CPU
  * reference that the GPU library is checked against.  It shares no code,
@@ -258,33 +259,33 @@ static int valid_problem(const orc_problem *p) {
   return 0;
 }
 
-/*
- * Integrate one instance.  q0, p0: Dq values.  Frames f = 0..nsteps/stride
- * (state after f*stride steps; frame 0 is the initial state) are written to
- * q_out/p_out as [frame][Dq] with p = m * v.hi.  iters (nullable): k of each
- * step.  delta1 (nullable): max over components of Delta^[1] of each step.
- * After a non-finite Delta the instance stops and its remaining frames are NaN.
- */
-int orc_integrate(const orc_problem *p, const double *q0, const double *p0, double h,
-                  int64_t nsteps, int64_t stride, int32_t max_iter, int32_t flags,
-                  double *q_out, double *p_out, int32_t *iters, double *delta1,
-                  orc_stats *st) {
+/* The coefficient tables of one member of the family: s stages, c and b of
+ * length s, eta, mu, nu row-major s x s (row = stage formed). */
+typedef struct {
+  int s;
+  const double *c, *b, *eta, *mu, *nu;
+} orc_tab;
+
+/* One instance with the tables of T (the steps listed at the top of this
+ * file, with s in place of 8).  Arguments as orc_integrate. */
+static int integrate_core(const orc_problem *p, const orc_tab *T, const double *q0,
+                          const double *p0, double h, int64_t nsteps, int64_t stride,
+                          int32_t max_iter, int32_t flags, double *q_out, double *p_out,
+                          int32_t *iters, double *delta1, orc_stats *st) {
   if (!valid_problem(p) || !(isfinite(h)) || nsteps < 0 || stride < 1 || nsteps % stride ||
       max_iter < 1)
     return ORC_EINVAL;
+  const int s = T->s;
   const int Dq = p->n * p->d;
-  double *buf = (double *)calloc((size_t)Dq * (6 + 6 * S), sizeof(double));
+  double *buf = (double *)calloc((size_t)Dq * (6 + 6 * s), sizeof(double));
   if (!buf) return ORC_ENOMEM;
   double *qh = buf, *ql = qh + Dq, *vh = ql + Dq, *vl = vh + Dq, *mind = vl + Dq,
          *prev = mind + Dq;
-  double *Q = prev + Dq, *Qn = Q + S * Dq, *G = Qn + S * Dq, *R = G + S * Dq,
-         *Rp = R + S * Dq, *V0 = Rp + S * Dq;
-  double eta[S][S];
-  for (int i = 0; i < S; ++i)
-    for (int j = 0; j < S; ++j)
-      eta[i][j] = ((flags & ORC_FLAG_NAIVE_ETA) && j > i) ? ORC_ETA_NAIVE[i][j] : ORC_ETA[i][j];
+  double *Q = prev + Dq, *Qn = Q + s * Dq, *G = Qn + s * Dq, *R = G + s * Dq,
+         *Rp = R + s * Dq, *V0 = Rp + s * Dq;
+  const double *eta = T->eta, *mu = T->mu, *nu = T->nu, *cc = T->c;
   double hb[S];
-  for (int i = 0; i < S; ++i) hb[i] = h * ORC_B[i];
+  for (int i = 0; i < s; ++i) hb[i] = h * T->b[i];
   for (int l = 0; l < Dq; ++l) {
     qh[l] = q0[l];
     vh[l] = p0[l] / mass_of(p, l / p->d);
@@ -298,19 +299,19 @@ int orc_integrate(const orc_problem *p, const double *q0, const double *p0, doub
   int dead = 0;
   for (int64_t n = 1; n <= nsteps; ++n) {
     if (!dead) {
-      if (flags & ORC_FLAG_NO_EXTRAPOLATION) memset(Rp, 0, sizeof(double) * S * Dq);
+      if (flags & ORC_FLAG_NO_EXTRAPOLATION) memset(Rp, 0, sizeof(double) * s * Dq);
       /* initial guess */
-      for (int i = 0; i < S; ++i)
+      for (int i = 0; i < s; ++i)
         for (int l = 0; l < Dq; ++l) {
-          double s = 0.0;
-          for (int j = 0; j < S; ++j) s += ORC_NU[i][j] * Rp[j * Dq + l];
-          V0[i * Dq + l] = vh[l] + s;
+          double sum = 0.0;
+          for (int j = 0; j < s; ++j) sum += nu[i * s + j] * Rp[j * Dq + l];
+          V0[i * Dq + l] = vh[l] + sum;
         }
-      for (int i = 0; i < S; ++i)
+      for (int i = 0; i < s; ++i)
         for (int l = 0; l < Dq; ++l) {
-          double s = 0.0;
-          for (int j = 0; j < S; ++j) s += ORC_MU[i][j] * (hb[j] * V0[j * Dq + l]);
-          Q[i * Dq + l] = qh[l] + s;
+          double sum = 0.0;
+          for (int j = 0; j < s; ++j) sum += mu[i * s + j] * (hb[j] * V0[j * Dq + l]);
+          Q[i * Dq + l] = qh[l] + sum;
         }
       for (int l = 0; l < Dq; ++l) mind[l] = prev[l] = INFINITY;
       /* fixed-point iteration */
@@ -318,20 +319,20 @@ int orc_integrate(const orc_problem *p, const double *q0, const double *p0, doub
       while (!conv && k < max_iter) {
         ++k;
         const double t_prev = (double)(n - 1) * h;
-        for (int i = 0; i < S; ++i) orc_force_t(p, Q + i * Dq, G + i * Dq, t_prev + ORC_C[i] * h);
-        for (int i = 0; i < S; ++i)
+        for (int i = 0; i < s; ++i) orc_force_t(p, Q + i * Dq, G + i * Dq, t_prev + cc[i] * h);
+        for (int i = 0; i < s; ++i)
           for (int l = 0; l < Dq; ++l) R[i * Dq + l] = hb[i] * G[i * Dq + l];
-        for (int i = 0; i < S; ++i)
+        for (int i = 0; i < s; ++i)
           for (int l = 0; l < Dq; ++l) {
-            double s = 0.0;
-            for (int j = 0; j < S; ++j) s += eta[i][j] * R[j * Dq + l];
-            Qn[i * Dq + l] = qh[l] + h * (ORC_C[i] * vh[l] + s);
+            double sum = 0.0;
+            for (int j = 0; j < s; ++j) sum += eta[i * s + j] * R[j * Dq + l];
+            Qn[i * Dq + l] = qh[l] + h * (cc[i] * vh[l] + sum);
           }
         conv = 1;
         double dmax = 0.0;
         for (int l = 0; l < Dq; ++l) {
           double dl = 0.0;
-          for (int i = 0; i < S; ++i) {
+          for (int i = 0; i < s; ++i) {
             double a = fabs(Qn[i * Dq + l] - Q[i * Dq + l]);
             if (isnan(a) || a > dl) dl = a; /* a NaN, once seen, is kept */
           }
@@ -340,7 +341,7 @@ int orc_integrate(const orc_problem *p, const double *q0, const double *p0, doub
           if (!stop_component(dl, mind + l, prev + l)) conv = 0;
         }
         if (k == 1 && delta1) delta1[n - 1] = dmax;
-        memcpy(Q, Qn, sizeof(double) * S * Dq);
+        memcpy(Q, Qn, sizeof(double) * s * Dq);
         if (dead) break;
       }
       if (!dead) {
@@ -351,8 +352,8 @@ int orc_integrate(const orc_problem *p, const double *q0, const double *p0, doub
         /* update with compensated summation */
         for (int l = 0; l < Dq; ++l) {
           double sv = 0.0, sc = 0.0;
-          for (int i = 0; i < S; ++i) sv += R[i * Dq + l];
-          for (int i = 0; i < S; ++i) sc += ORC_C[i] * R[i * Dq + l];
+          for (int i = 0; i < s; ++i) sv += R[i * Dq + l];
+          for (int i = 0; i < s; ++i) sc += cc[i] * R[i * Dq + l];
           if (flags & ORC_FLAG_NO_COMPENSATION) {
             vh[l] += sv;
             qh[l] += h * (vh[l] - sc);
@@ -361,7 +362,7 @@ int orc_integrate(const orc_problem *p, const double *q0, const double *p0, doub
             dw_add(qh + l, ql + l, h * (vh[l] - sc));
           }
         }
-        memcpy(Rp, R, sizeof(double) * S * Dq);
+        memcpy(Rp, R, sizeof(double) * s * Dq);
         loc.steps_done = n;
       } else {
         loc.status = ORC_ENONFINITE;
@@ -382,6 +383,52 @@ int orc_integrate(const orc_problem *p, const double *q0, const double *p0, doub
   if (st) *st = loc;
   free(buf);
   return loc.status;
+}
+
+/* Tables of the s-stage member (s = 2, 4, 6, 8), or 0 for another s. */
+int orc_stage_tables(int s, orc_tab *T) {
+  T->s = s;
+  switch (s) {
+  case 2: T->c = ORC_S2_C; T->b = ORC_S2_B; T->eta = &ORC_S2_ETA[0][0]; T->mu = &ORC_S2_MU[0][0]; T->nu = &ORC_S2_NU[0][0]; return 1;
+  case 4: T->c = ORC_S4_C; T->b = ORC_S4_B; T->eta = &ORC_S4_ETA[0][0]; T->mu = &ORC_S4_MU[0][0]; T->nu = &ORC_S4_NU[0][0]; return 1;
+  case 6: T->c = ORC_S6_C; T->b = ORC_S6_B; T->eta = &ORC_S6_ETA[0][0]; T->mu = &ORC_S6_MU[0][0]; T->nu = &ORC_S6_NU[0][0]; return 1;
+  case 8: T->c = ORC_C; T->b = ORC_B; T->eta = &ORC_ETA[0][0]; T->mu = &ORC_MU[0][0]; T->nu = &ORC_NU[0][0]; return 1;
+  }
+  return 0;
+}
+
+/*
+ * Integrate one instance with IRKGL16 (s = 8).  q0, p0: Dq values.  Frames
+ * f = 0..nsteps/stride (state after f*stride steps; frame 0 is the initial
+ * state) are written to q_out/p_out as [frame][Dq] with p = m * v.hi.  iters
+ * (nullable): k of each step.  delta1 (nullable): max over components of
+ * Delta^[1] of each step.  After a non-finite Delta the instance stops and its
+ * remaining frames are NaN.  flags: the negative controls above.
+ */
+int orc_integrate(const orc_problem *p, const double *q0, const double *p0, double h,
+                  int64_t nsteps, int64_t stride, int32_t max_iter, int32_t flags,
+                  double *q_out, double *p_out, int32_t *iters, double *delta1,
+                  orc_stats *st) {
+  double eta[S][S];
+  for (int i = 0; i < S; ++i)
+    for (int j = 0; j < S; ++j)
+      eta[i][j] = ((flags & ORC_FLAG_NAIVE_ETA) && j > i) ? ORC_ETA_NAIVE[i][j] : ORC_ETA[i][j];
+  orc_tab T;
+  orc_stage_tables(S, &T);
+  T.eta = &eta[0][0];
+  return integrate_core(p, &T, q0, p0, h, nsteps, stride, max_iter, flags, q_out, p_out, iters,
+                        delta1, st);
+}
+
+/* The same with the s-stage member of the family (s = 2, 4, 6, 8; the
+ * method of order 2s), no negative-control flags. */
+int orc_integrate_s(const orc_problem *p, int32_t s, const double *q0, const double *p0,
+                    double h, int64_t nsteps, int64_t stride, int32_t max_iter, double *q_out,
+                    double *p_out, int32_t *iters, orc_stats *st) {
+  orc_tab T;
+  if (!orc_stage_tables(s, &T)) return ORC_EINVAL;
+  return integrate_core(p, &T, q0, p0, h, nsteps, stride, max_iter, 0, q_out, p_out, iters,
+                        NULL, st);
 }
 
 /*
@@ -419,6 +466,51 @@ int orc_integrate_batch(int32_t n_inst, const orc_problem *probs, const double *
     int rc = orc_integrate(probs + i, q0 + in_off[i], p0 + in_off[i], h[i], nsteps[i], stride[i],
                            max_iter, flags, q_out + out_off[i], p_out + out_off[i], NULL, NULL,
                            &st);
+    if (iters_total) iters_total[i] = st.iterations;
+    if (status) status[i] = rc;
+    if (rc < 0) {
+#pragma omp critical
+      if (rc < worst) worst = rc;
+    }
+  }
+  free(in_off);
+  free(out_off);
+  return worst;
+}
+
+/* The same for the s-stage member (flags apply to s = 8 only). */
+int orc_integrate_batch_s(int32_t n_inst, int32_t s, const orc_problem *probs, const double *q0,
+                        const double *p0, const double *h, const int64_t *nsteps,
+                        const int64_t *stride, int32_t max_iter, int32_t flags, double *q_out,
+                        double *p_out, int64_t *iters_total, int32_t *status) {
+  int64_t *in_off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_inst + 1));
+  int64_t *out_off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_inst + 1));
+  if (!in_off || !out_off) {
+    free(in_off);
+    free(out_off);
+    return ORC_ENOMEM;
+  }
+  in_off[0] = out_off[0] = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    int64_t Dq = (int64_t)probs[i].n * probs[i].d;
+    if (stride[i] < 1 || nsteps[i] < 0 || nsteps[i] % stride[i]) {
+      free(in_off);
+      free(out_off);
+      return ORC_EINVAL;
+    }
+    in_off[i + 1] = in_off[i] + Dq;
+    out_off[i + 1] = out_off[i] + Dq * (nsteps[i] / stride[i] + 1);
+  }
+  int worst = ORC_OK;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int i = 0; i < n_inst; ++i) {
+    orc_stats st;
+    int rc = s == S ? orc_integrate(probs + i, q0 + in_off[i], p0 + in_off[i], h[i], nsteps[i],
+                                    stride[i], max_iter, flags, q_out + out_off[i],
+                                    p_out + out_off[i], NULL, NULL, &st)
+                    : orc_integrate_s(probs + i, s, q0 + in_off[i], p0 + in_off[i], h[i],
+                                      nsteps[i], stride[i], max_iter, q_out + out_off[i],
+                                      p_out + out_off[i], NULL, &st);
     if (iters_total) iters_total[i] = st.iterations;
     if (status) status[i] = rc;
     if (rc < 0) {

@@ -103,6 +103,18 @@ def lib():
         L.orc_integrate_ode_batch.argtypes = [C.c_int32, C.POINTER(Problem), dp, dp, i64p, i64p,
                                               C.c_int32, dp, i64p, i32p]
         L.orc_integrate_ode_batch.restype = C.c_int
+        L.orc_integrate_s.argtypes = [C.POINTER(Problem), C.c_int32, dp, dp, C.c_double, C.c_int64,
+                                      C.c_int64, C.c_int32, dp, dp, i32p, C.POINTER(Stats)]
+        L.orc_integrate_s.restype = C.c_int
+        L.orc_integrate_batch_s.argtypes = [C.c_int32, C.c_int32, C.POINTER(Problem), dp, dp, dp,
+                                            i64p, i64p, C.c_int32, C.c_int32, dp, dp, i64p, i32p]
+        L.orc_integrate_batch_s.restype = C.c_int
+        L.orc_integrate_ode_s.argtypes = [C.POINTER(Problem), C.c_int32, dp, C.c_double, C.c_int64,
+                                          C.c_int64, C.c_int32, dp, i32p, C.POINTER(Stats)]
+        L.orc_integrate_ode_s.restype = C.c_int
+        L.orc_integrate_ode_batch_s.argtypes = [C.c_int32, C.c_int32, C.POINTER(Problem), dp, dp,
+                                                i64p, i64p, C.c_int32, dp, i64p, i32p]
+        L.orc_integrate_ode_batch_s.restype = C.c_int
         _lib = L
     return _lib
 
@@ -159,8 +171,29 @@ def integrate(spec, q0, p0, h, nsteps, stride=1, max_iter=100, flags=0, want_ite
                            nonconverged=st.nonconverged, status=st.status), rc=rc)
 
 
-def integrate_batch(specs, q0, p0, h, nsteps, stride, max_iter=100, flags=0):
-    """FP64 oracle over many instances (OpenMP).  Packed arrays as the library."""
+def integrate_s(spec, s, q0, p0, h, nsteps, stride=1, max_iter=100, want_iters=False):
+    """Second-order FP64 oracle with the s-stage member (s = 2, 4, 6, 8)."""
+    L = lib()
+    q0 = np.ascontiguousarray(q0, np.float64)
+    p0 = np.ascontiguousarray(p0, np.float64)
+    nf = nsteps // stride + 1
+    qo = np.empty((nf, spec.Dq))
+    po = np.empty((nf, spec.Dq))
+    it = np.zeros(max(nsteps, 1), np.int32) if want_iters else None
+    st = Stats()
+    pr = spec.struct()
+    rc = L.orc_integrate_s(C.byref(pr), int(s), _dp(q0), _dp(p0), float(h), int(nsteps),
+                           int(stride), int(max_iter), _dp(qo), _dp(po),
+                           it.ctypes.data_as(C.POINTER(C.c_int32)) if it is not None else None,
+                           C.byref(st))
+    return dict(q=qo, p=po, iters=None if it is None else it[:nsteps],
+                stats=dict(steps_done=st.steps_done, iterations=st.iterations, max_k=st.max_k,
+                           nonconverged=st.nonconverged, status=st.status), rc=rc)
+
+
+def integrate_batch(specs, q0, p0, h, nsteps, stride, max_iter=100, flags=0, s=8):
+    """FP64 oracle over many instances (OpenMP).  Packed arrays as the library;
+    s stages (default 8; flags apply to s = 8 only)."""
     L = lib()
     n = len(specs)
     arr = (Problem * n)(*[s.struct() for s in specs])
@@ -174,11 +207,12 @@ def integrate_batch(specs, q0, p0, h, nsteps, stride, max_iter=100, flags=0):
     po = np.empty(tot)
     iters = np.zeros(n, np.int64)
     status = np.zeros(n, np.int32)
-    rc = L.orc_integrate_batch(n, arr, _dp(q0), _dp(p0), _dp(h),
-                               ns.ctypes.data_as(C.POINTER(C.c_int64)),
-                               sd.ctypes.data_as(C.POINTER(C.c_int64)), int(max_iter), int(flags),
-                               _dp(qo), _dp(po), iters.ctypes.data_as(C.POINTER(C.c_int64)),
-                               status.ctypes.data_as(C.POINTER(C.c_int32)))
+    rc = L.orc_integrate_batch_s(n, int(s), arr, _dp(q0), _dp(p0), _dp(h),
+                                 ns.ctypes.data_as(C.POINTER(C.c_int64)),
+                                 sd.ctypes.data_as(C.POINTER(C.c_int64)), int(max_iter),
+                                 int(flags), _dp(qo), _dp(po),
+                                 iters.ctypes.data_as(C.POINTER(C.c_int64)),
+                                 status.ctypes.data_as(C.POINTER(C.c_int32)))
     return dict(q=qo, p=po, iters=iters, status=status, rc=rc)
 
 
@@ -348,8 +382,9 @@ def energy_ode(spec, y):
     return L.orc_energy_ode(C.byref(pr), _dp(y))
 
 
-def integrate_ode(spec, y0, h, nsteps, stride=1, max_iter=100, want_iters=False):
-    """First-order (mu form) FP64 oracle, one instance.  Returns dict(y, iters, stats, rc)."""
+def integrate_ode(spec, y0, h, nsteps, stride=1, max_iter=100, want_iters=False, s=8):
+    """First-order (mu form) FP64 oracle, one instance, s stages (default 8).
+    Returns dict(y, iters, stats, rc)."""
     L = lib()
     y0 = np.ascontiguousarray(y0, np.float64)
     nf = nsteps // stride + 1
@@ -357,17 +392,21 @@ def integrate_ode(spec, y0, h, nsteps, stride=1, max_iter=100, want_iters=False)
     it = np.zeros(max(nsteps, 1), np.int32) if want_iters else None
     st = Stats()
     pr = spec.struct()
-    rc = L.orc_integrate_ode(C.byref(pr), _dp(y0), float(h), int(nsteps), int(stride),
-                             int(max_iter), _dp(yo),
-                             it.ctypes.data_as(C.POINTER(C.c_int32)) if it is not None else None,
-                             C.byref(st))
+    itp = it.ctypes.data_as(C.POINTER(C.c_int32)) if it is not None else None
+    if s == 8:
+        rc = L.orc_integrate_ode(C.byref(pr), _dp(y0), float(h), int(nsteps), int(stride),
+                                 int(max_iter), _dp(yo), itp, C.byref(st))
+    else:
+        rc = L.orc_integrate_ode_s(C.byref(pr), int(s), _dp(y0), float(h), int(nsteps),
+                                   int(stride), int(max_iter), _dp(yo), itp, C.byref(st))
     return dict(y=yo, iters=None if it is None else it[:nsteps],
                 stats=dict(steps_done=st.steps_done, iterations=st.iterations, max_k=st.max_k,
                            nonconverged=st.nonconverged, status=st.status), rc=rc)
 
 
-def integrate_ode_batch(specs, y0, h, nsteps, stride, max_iter=100):
-    """First-order oracle over many instances (OpenMP), packed as the library."""
+def integrate_ode_batch(specs, y0, h, nsteps, stride, max_iter=100, s=8):
+    """First-order oracle over many instances (OpenMP), packed as the library;
+    s stages (default 8)."""
     L = lib()
     n = len(specs)
     arr = (Problem * n)(*[s.struct() for s in specs])
@@ -379,9 +418,9 @@ def integrate_ode_batch(specs, y0, h, nsteps, stride, max_iter=100):
     yo = np.empty(tot)
     iters = np.zeros(n, np.int64)
     status = np.zeros(n, np.int32)
-    rc = L.orc_integrate_ode_batch(n, arr, _dp(y0), _dp(h),
-                                   ns.ctypes.data_as(C.POINTER(C.c_int64)),
-                                   sd.ctypes.data_as(C.POINTER(C.c_int64)), int(max_iter),
-                                   _dp(yo), iters.ctypes.data_as(C.POINTER(C.c_int64)),
-                                   status.ctypes.data_as(C.POINTER(C.c_int32)))
+    rc = L.orc_integrate_ode_batch_s(n, int(s), arr, _dp(y0), _dp(h),
+                                     ns.ctypes.data_as(C.POINTER(C.c_int64)),
+                                     sd.ctypes.data_as(C.POINTER(C.c_int64)), int(max_iter),
+                                     _dp(yo), iters.ctypes.data_as(C.POINTER(C.c_int64)),
+                                     status.ctypes.data_as(C.POINTER(C.c_int32)))
     return dict(y=yo, iters=iters, status=status, rc=rc)

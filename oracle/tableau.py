@@ -1,4 +1,5 @@
-"""Oracle coefficient tables for the 8-stage Gauss-Legendre collocation method.
+"""Oracle coefficient tables for the s-stage Gauss-Legendre collocation methods
+(s = 8: IRKGL16; s = 2, 4, 6: the lower-order members of the family).
 
 TEST INFRASTRUCTURE ONLY.  Nothing under ``oracle/`` is part of the product
 path; only the test-suite, the smoke check and the CPU-baseline leg of the
@@ -30,7 +31,8 @@ rounded to binary64 exactly once, to nearest-even, through ``fractions``:
   ``nu_ij = fl(W_ij / b_j)`` because nu multiplies L = h b f.
 
 Run ``python oracle/tableau.py`` to regenerate ``oracle/tableau.h`` (binary64
-tables plus double-double hi/lo pairs for the double-double oracle).
+tables for s = 8 plus double-double hi/lo pairs for the double-double oracle,
+and binary64 tables for s = 2, 4, 6).
 """
 from __future__ import annotations
 
@@ -40,6 +42,7 @@ from fractions import Fraction
 import mpmath
 
 S = 8
+STAGES = (2, 4, 6, 8)
 DPS = 120
 
 
@@ -67,8 +70,9 @@ def legendre_zeros(n=S):
     return sorted(zs)
 
 
-def exact_tableau():
-    """High-precision (c, b, A, alpha, beta, W) as mpmath objects."""
+def exact_tableau(s=S):
+    """High-precision (c, b, A, alpha, beta, W) of the s-stage method as mpmath objects."""
+    S = s
     with mpmath.workdps(DPS):
         x = legendre_zeros(S)
         c = [(1 + xi) / 2 for xi in x]
@@ -130,10 +134,11 @@ def dd_split(x):
 def fp64_tables(ex=None):
     """The binary64 coefficient tables the integrator uses.
 
-    Returns dict with lists: c, b (length 8) and eta, mu, nu (8x8, row i =
+    Returns dict with lists: c, b (length s) and eta, mu, nu (s x s, row i =
     stage being formed, column j = stage summed over).
     """
     ex = ex or exact_tableau()
+    S = len(ex["c"])
     with mpmath.workdps(DPS):
         c = [rne(v) for v in ex["c"]]
         b = [rne(v) for v in ex["b"]]
@@ -193,7 +198,7 @@ def dd_tables(ex=None):
     return dict(c=c, b=b, eta=eta, mu=mu, nu=nu)
 
 
-def _emit_header(path, fp, dd):
+def _emit_header(path, fp, dd, others):
     lines = [
         "/* Generated by oracle/tableau.py -- do not edit.",
         " * Oracle coefficient tables (test infrastructure only).",
@@ -211,6 +216,15 @@ def _emit_header(path, fp, dd):
             lines.append("  {" + ", ".join(x.hex() for x in row) + "},")
         lines.append("};")
 
+    def vec_s(name, xs):
+        lines.append(f"static const double {name}[{len(xs)}] = {{" + ", ".join(x.hex() for x in xs) + "};")
+
+    def mat_s(name, m):
+        lines.append(f"static const double {name}[{len(m)}][{len(m)}] = {{")
+        for row in m:
+            lines.append("  {" + ", ".join(x.hex() for x in row) + "},")
+        lines.append("};")
+
     vec("ORC_C", fp["c"])
     vec("ORC_B", fp["b"])
     mat("ORC_ETA", fp["eta"])
@@ -223,6 +237,12 @@ def _emit_header(path, fp, dd):
     for nm in ("eta", "mu", "nu"):
         mat(f"ORC_DD_{nm.upper()}_HI", [[p[0] for p in row] for row in dd[nm]])
         mat(f"ORC_DD_{nm.upper()}_LO", [[p[1] for p in row] for row in dd[nm]])
+    for st, t in others.items():  # lower stage counts (same construction)
+        vec_s(f"ORC_S{st}_C", t["c"])
+        vec_s(f"ORC_S{st}_B", t["b"])
+        mat_s(f"ORC_S{st}_ETA", t["eta"])
+        mat_s(f"ORC_S{st}_MU", t["mu"])
+        mat_s(f"ORC_S{st}_NU", t["nu"])
     lines.append("#endif")
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")
@@ -232,8 +252,9 @@ def main():
     ex = exact_tableau()
     fp = fp64_tables(ex)
     dd = dd_tables(ex)
+    others = {s: fp64_tables(exact_tableau(s)) for s in STAGES if s != S}
     here = os.path.dirname(os.path.abspath(__file__))
-    _emit_header(os.path.join(here, "tableau.h"), fp, dd)
+    _emit_header(os.path.join(here, "tableau.h"), fp, dd, others)
     print("wrote", os.path.join(here, "tableau.h"))
 
 
