@@ -83,11 +83,16 @@ typedef struct {
 
 /* max_iter: cap on fixed-point iterations per step (<= 0 means 100; the paper
  * sets none).  record_iters: keep the iteration count of every step.  flags:
- * IRKGL16_* option flags. */
+ * IRKGL16_* option flags.  stages: s of the s-stage Gauss-Legendre member of
+ * the family (order 2s; section 2.2): 0 or 8 for IRKGL16; 2, 4 or 6 (IRKGL4,
+ * IRKGL8, IRKGL12, coefficients built as for s = 8, section 2.4) only for
+ * contexts created by irkgl16_create_user / irkgl16_create_ode; anything else
+ * is IRKGL16_EINVAL. */
 typedef struct {
   int32_t max_iter;
   int32_t record_iters;
   uint32_t flags;
+  int32_t stages;
 } irkgl16_options;
 
 /* Results of the last irkgl16_integrate call.  The three pointers are

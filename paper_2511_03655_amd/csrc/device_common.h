@@ -67,6 +67,16 @@ struct InstStat {
 constexpr int kTabC = 0, kTabB = 8, kTabEta = 16, kTabMu = 80, kTabNu = 144, kTabK = 208,
               kTabSize = 272;
 
+// The same layout for the s-stage member of the family (s = 2, 4, 6, 8):
+// [c | b | eta | mu | nu | K], s x s matrices row-major.  Tab<8> is the table
+// above.
+template <int S>
+struct Tab {
+  static constexpr int C = 0, B = S, Eta = 2 * S, Mu = 2 * S + S * S, Nu = 2 * S + 2 * S * S,
+                       K = 2 * S + 3 * S * S, Size = 2 * S + 4 * S * S;
+};
+static_assert(Tab<8>::K == kTabK && Tab<8>::Size == kTabSize, "table layout");
+
 // Pointer into the constant address space: loads through it with uniform
 // indices become scalar (SMEM) loads.
 typedef const __attribute__((address_space(4))) double* ConstTab;
@@ -190,51 +200,54 @@ __device__ __forceinline__ bool track_finite(double acc, double nf) {
 // results are bit-identical to a strict-IEEE CPU evaluation of the same
 // formulas.
 
-// sum_j w[off + j] x[j], j = 0..7
-template <bool EXACT>
-__device__ __forceinline__ double row_dot(ConstTab w, int off, const double (&x)[kS]) {
+// The helpers below are generic in the stage count S (deduced from the
+// length of the stage arrays; 8 for IRKGL16) and read the table of Tab<S>.
+
+// sum_j w[off + j] x[j], j = 0..S-1
+template <bool EXACT, int S>
+__device__ __forceinline__ double row_dot(ConstTab w, int off, const double (&x)[S]) {
   if constexpr (EXACT) {
     double s = 0.0;
 #pragma unroll
-    for (int j = 0; j < kS; ++j) s = s + w[off + j] * x[j];
+    for (int j = 0; j < S; ++j) s = s + w[off + j] * x[j];
     return s;
   } else {
     double s = w[off] * x[0];
 #pragma unroll
-    for (int j = 1; j < kS; ++j) s = fma(w[off + j], x[j], s);
+    for (int j = 1; j < S; ++j) s = fma(w[off + j], x[j], s);
     return s;
   }
 }
 
 // Stage value q + h (c_s v + sum_j M_sj R_j) with M = eta (eqs. Qi2 /
 // IRK_FP2), or M = K for the folded initial guess.
-template <bool EXACT>
+template <bool EXACT, int S>
 __device__ __forceinline__ double stage_value(ConstTab w, int s, double q, double v, double h,
-                                              const double (&R)[kS], int mat = kTabEta) {
+                                              const double (&R)[S], int mat = Tab<S>::Eta) {
   if constexpr (EXACT) {
-    return q + h * (w[kTabC + s] * v + row_dot<true>(w, mat + s * kS, R));
+    return q + h * (w[Tab<S>::C + s] * v + row_dot<true>(w, mat + s * S, R));
   } else {
-    double acc = w[kTabC + s] * v;
+    double acc = w[Tab<S>::C + s] * v;
 #pragma unroll
-    for (int j = 0; j < kS; ++j) acc = fma(w[mat + s * kS + j], R[j], acc);
+    for (int j = 0; j < S; ++j) acc = fma(w[mat + s * S + j], R[j], acc);
     return fma(h, acc, q);
   }
 }
 
 // sum_i R_i and sum_i c_i R_i (eq. qnvn2).
-template <bool EXACT>
-__device__ __forceinline__ void step_sums(ConstTab w, const double (&R)[kS], double& sv,
+template <bool EXACT, int S>
+__device__ __forceinline__ void step_sums(ConstTab w, const double (&R)[S], double& sv,
                                           double& sc) {
   if constexpr (EXACT) {
     sv = 0.0;
 #pragma unroll
-    for (int i = 0; i < kS; ++i) sv = sv + R[i];
-    sc = row_dot<true>(w, kTabC, R);
+    for (int i = 0; i < S; ++i) sv = sv + R[i];
+    sc = row_dot<true>(w, Tab<S>::C, R);
   } else {
     sv = R[0];
 #pragma unroll
-    for (int i = 1; i < kS; ++i) sv += R[i];
-    sc = row_dot<false>(w, kTabC, R);
+    for (int i = 1; i < S; ++i) sv += R[i];
+    sc = row_dot<false>(w, Tab<S>::C, R);
   }
 }
 
@@ -290,56 +303,58 @@ __device__ __forceinline__ void user_increment(const double (&q)[DQ], double hb,
 // evaluates the same linear map folded into one matrix,
 // Q_i = q + h (c_i v + sum_j K_ij Rp_j) with K = A W diag(1/b) (80 instead of
 // 144 operations per component).  Rows are fetched one at a time.
-template <int CPL, bool EXACT>
+template <int CPL, bool EXACT, int S>
 __device__ __forceinline__ void initial_guess(ConstTab T, const double (&qh)[CPL],
-                                              const double (&vh)[CPL], const double (&Rp)[CPL][kS],
-                                              double h, double (&Q)[CPL][kS]) {
+                                              const double (&vh)[CPL], const double (&Rp)[CPL][S],
+                                              double h, double (&Q)[CPL][S]) {
   if constexpr (!EXACT) {
 #pragma unroll
-    for (int s = 0; s < kS; ++s) {
+    for (int s = 0; s < S; ++s) {
       const ConstTab r = row_tab(T);
 #pragma unroll
-      for (int cc = 0; cc < CPL; ++cc) Q[cc][s] = stage_value<false>(r, s, qh[cc], vh[cc], h, Rp[cc], kTabK);
+      for (int cc = 0; cc < CPL; ++cc)
+        Q[cc][s] = stage_value<false>(r, s, qh[cc], vh[cc], h, Rp[cc], Tab<S>::K);
     }
     return;
   }
-  double L0[CPL][kS];
+  double L0[CPL][S];
 #pragma unroll
-  for (int s = 0; s < kS; ++s) {
+  for (int s = 0; s < S; ++s) {
     const ConstTab r = row_tab(T);
-    const double hb = h * r[kTabB + s];
+    const double hb = h * r[Tab<S>::B + s];
 #pragma unroll
-    for (int cc = 0; cc < CPL; ++cc) L0[cc][s] = hb * (vh[cc] + row_dot<EXACT>(r, kTabNu + s * kS, Rp[cc]));
+    for (int cc = 0; cc < CPL; ++cc)
+      L0[cc][s] = hb * (vh[cc] + row_dot<EXACT>(r, Tab<S>::Nu + s * S, Rp[cc]));
   }
 #pragma unroll
-  for (int s = 0; s < kS; ++s) {
+  for (int s = 0; s < S; ++s) {
     const ConstTab r = row_tab(T);
 #pragma unroll
-    for (int cc = 0; cc < CPL; ++cc) Q[cc][s] = qh[cc] + row_dot<EXACT>(r, kTabMu + s * kS, L0[cc]);
+    for (int cc = 0; cc < CPL; ++cc) Q[cc][s] = qh[cc] + row_dot<EXACT>(r, Tab<S>::Mu + s * S, L0[cc]);
   }
 }
 
 // ---- first-order (mu) form, eqs. Yi2 / yn2, IRK_init / IRK_FP
 // Stage value Y_s = y + sum_j M_sj L_j with M = mu (iteration) or nu (initial
 // guess from the previous step's increments).
-template <bool EXACT>
-__device__ __forceinline__ double ode_stage_value(ConstTab w, int s, double y, const double (&L)[kS],
+template <bool EXACT, int S>
+__device__ __forceinline__ double ode_stage_value(ConstTab w, int s, double y, const double (&L)[S],
                                                   int mat) {
-  return y + row_dot<EXACT>(w, mat + s * kS, L);
+  return y + row_dot<EXACT>(w, mat + s * S, L);
 }
 
 // sum_i L_i (eq. yn2).
-template <bool EXACT>
-__device__ __forceinline__ double ode_step_sum(const double (&L)[kS]) {
+template <bool EXACT, int S>
+__device__ __forceinline__ double ode_step_sum(const double (&L)[S]) {
   if constexpr (EXACT) {
     double s = 0.0;
 #pragma unroll
-    for (int i = 0; i < kS; ++i) s = s + L[i];
+    for (int i = 0; i < S; ++i) s = s + L[i];
     return s;
   } else {
     double s = L[0];
 #pragma unroll
-    for (int i = 1; i < kS; ++i) s += L[i];
+    for (int i = 1; i < S; ++i) s += L[i];
     return s;
   }
 }
@@ -358,16 +373,17 @@ __device__ __forceinline__ void ode_increment(const double (&y)[DQ], double hb, 
 
 // ---- the two forms behind one interface (KIND == kUserOde: first order)
 // Initial guess for CPL owned components from the previous step's increments.
-template <int KIND, int CPL, bool EXACT>
+template <int KIND, int CPL, bool EXACT, int S>
 __device__ __forceinline__ void form_guess(ConstTab T, const double (&qh)[CPL],
-                                           const double (&vh)[CPL], const double (&Rp)[CPL][kS],
-                                           double h, double (&Q)[CPL][kS]) {
+                                           const double (&vh)[CPL], const double (&Rp)[CPL][S],
+                                           double h, double (&Q)[CPL][S]) {
   if constexpr (KIND == kUserOde) {
 #pragma unroll
-    for (int s = 0; s < kS; ++s) {
+    for (int s = 0; s < S; ++s) {
       const ConstTab r = row_tab(T);
 #pragma unroll
-      for (int cc = 0; cc < CPL; ++cc) Q[cc][s] = ode_stage_value<EXACT>(r, s, qh[cc], Rp[cc], kTabNu);
+      for (int cc = 0; cc < CPL; ++cc)
+        Q[cc][s] = ode_stage_value<EXACT>(r, s, qh[cc], Rp[cc], Tab<S>::Nu);
     }
   } else {
     initial_guess<CPL, EXACT>(T, qh, vh, Rp, h, Q);
@@ -375,19 +391,19 @@ __device__ __forceinline__ void form_guess(ConstTab T, const double (&qh)[CPL],
 }
 
 // New stage value of one component from the current increments.
-template <int KIND, bool EXACT>
+template <int KIND, bool EXACT, int S>
 __device__ __forceinline__ double form_stage_value(ConstTab r, int s, double q, double v, double h,
-                                                   const double (&R)[kS]) {
+                                                   const double (&R)[S]) {
   if constexpr (KIND == kUserOde) {
-    return ode_stage_value<EXACT>(r, s, q, R, kTabMu);
+    return ode_stage_value<EXACT>(r, s, q, R, Tab<S>::Mu);
   } else {
     return stage_value<EXACT>(r, s, q, v, h, R);
   }
 }
 
 // Compensated end-of-step update of one component (eq. yn2 or eq. qnvn2).
-template <int KIND, bool EXACT>
-__device__ __forceinline__ void form_update(ConstTab r, const double (&R)[kS], double h, double& qh,
+template <int KIND, bool EXACT, int S>
+__device__ __forceinline__ void form_update(ConstTab r, const double (&R)[S], double h, double& qh,
                                             double& ql, double& vh, double& vl) {
   if constexpr (KIND == kUserOde) {
     dw_add(qh, ql, ode_step_sum<EXACT>(R));

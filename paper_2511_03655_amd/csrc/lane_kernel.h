@@ -1,6 +1,7 @@
 // Persistent batched IRKGL16 kernel for systems with very few position
 // components (Dq <= kLaneMaxDq): one lane integrates one instance, holding all
-// 8 x Dq stage values and increments in registers.  KIND == kUserOde runs the
+// S x Dq stage values and increments in registers (S = 8 for IRKGL16; 2, 4
+// or 6 for the lower-order members of the family).  KIND == kUserOde runs the
 // first-order form instead (section 2.4, eqs. Yi2 / yn2; section 2.5, eqs.
 // IRK_init / IRK_FP: y' = f(t, y), Dq = D components, stages
 // Y_i = y + sum_j mu_ij L_j, update y + sum_i L_i).
@@ -34,23 +35,23 @@ namespace irk {
 
 constexpr int kLaneMaxDq = 4;
 
-// R_s = h b_s g(Q_s, t_s) for the 8 stages of one instance.
-template <int KIND, int DQ, bool EXACT>
-__device__ __forceinline__ void lane_increments(ConstTab T, const double (&Q)[DQ][kS], double h,
+// R_s = h b_s g(Q_s, t_s) for the S stages of one instance.
+template <int KIND, int DQ, bool EXACT, int S>
+__device__ __forceinline__ void lane_increments(ConstTab T, const double (&Q)[DQ][S], double h,
                                                 double G, const double* prm, int64_t step,
-                                                double (&R)[DQ][kS]) {
+                                                double (&R)[DQ][S]) {
 #pragma unroll
-  for (int s = 0; s < kS; ++s) {
+  for (int s = 0; s < S; ++s) {
     const ConstTab r = row_tab(T);
-    const double hb = h * r[kTabB + s];
+    const double hb = h * r[Tab<S>::B + s];
     double q[DQ], out[DQ];
 #pragma unroll
     for (int l = 0; l < DQ; ++l) q[l] = Q[l][s];
 #ifdef IRKGL16_USER_FORCE
-    if constexpr (KIND == kUser) user_increment<DQ>(q, hb, prm, stage_time(step, h, r[kTabC + s]), out);
+    if constexpr (KIND == kUser) user_increment<DQ>(q, hb, prm, stage_time(step, h, r[Tab<S>::C + s]), out);
 #endif
 #ifdef IRKGL16_USER_ODE
-    if constexpr (KIND == kUserOde) ode_increment<DQ>(q, hb, prm, stage_time(step, h, r[kTabC + s]), out);
+    if constexpr (KIND == kUserOde) ode_increment<DQ>(q, hb, prm, stage_time(step, h, r[Tab<S>::C + s]), out);
 #endif
     if constexpr (KIND == kKepler) kepler_increment<DQ, EXACT>(q, hb, G, out);
 #pragma unroll
@@ -61,7 +62,7 @@ __device__ __forceinline__ void lane_increments(ConstTab T, const double (&Q)[DQ
   (void)G;
 }
 
-template <int KIND, int DQ, bool EXACT>
+template <int KIND, int DQ, bool EXACT, int S = kS>
 __global__ __launch_bounds__(64) void lane_kernel(LaunchArgs a) {
   static_assert(DQ >= 1 && DQ <= kLaneMaxDq, "lane kernel: Dq out of range");
   const int lane = threadIdx.x;
@@ -76,7 +77,7 @@ __global__ __launch_bounds__(64) void lane_kernel(LaunchArgs a) {
   int64_t it_sum = 0, nonconv = 0;
   int32_t maxk = 0;
   double qh[DQ], ql[DQ], vh[DQ], vl[DQ], mind[DQ], prv[DQ];
-  double Qc[DQ][kS], R[DQ][kS];
+  double Qc[DQ][S], R[DQ][S];
 
   for (;;) {
     // ---- lanes without an instance take the next ones from the queue
@@ -126,19 +127,19 @@ __global__ __launch_bounds__(64) void lane_kernel(LaunchArgs a) {
       target = dsc.nsteps;
       if (a.step_budget > 0 && step + a.step_budget < dsc.nsteps) target = step + a.step_budget;
       if (st.status != kOk) target = step;
-      const double* S = a.state + state_off;
+      const double* St = a.state + state_off;
 #pragma unroll
       for (int l = 0; l < DQ; ++l) {
-        qh[l] = S[l];
-        ql[l] = S[DQ + l];
+        qh[l] = St[l];
+        ql[l] = St[DQ + l];
         if constexpr (KIND == kUserOde) {  // first order: no velocity state
           vh[l] = vl[l] = 0.0;
         } else {
-          vh[l] = S[2 * DQ + l];
-          vl[l] = S[3 * DQ + l];
+          vh[l] = St[2 * DQ + l];
+          vl[l] = St[3 * DQ + l];
         }
 #pragma unroll
-        for (int s = 0; s < kS; ++s) R[l][s] = S[4 * DQ + l * kS + s];
+        for (int s = 0; s < S; ++s) R[l][s] = St[4 * DQ + l * S + s];
       }
       form_guess<KIND, DQ, EXACT>(T, qh, vh, R, h, Qc);
     }
@@ -152,12 +153,12 @@ __global__ __launch_bounds__(64) void lane_kernel(LaunchArgs a) {
     while (__ballot(!conv) != 0) {
       ++k;
       if (!conv) {
-        lane_increments<KIND, DQ, EXACT>(T, Qc, h, G, prm, step, R);
+        lane_increments<KIND, DQ, EXACT, S>(T, Qc, h, G, prm, step, R);
         double dmax[DQ], nf[DQ];
 #pragma unroll
         for (int l = 0; l < DQ; ++l) dmax[l] = nf[l] = 0.0;
 #pragma unroll
-        for (int s = 0; s < kS; ++s) {
+        for (int s = 0; s < S; ++s) {
           const ConstTab r = row_tab(T);
 #pragma unroll
           for (int l = 0; l < DQ; ++l) {
@@ -219,17 +220,17 @@ __global__ __launch_bounds__(64) void lane_kernel(LaunchArgs a) {
           }
         }
         if (step >= target) {
-          double* S = a.state + state_off;
+          double* St = a.state + state_off;
 #pragma unroll
           for (int l = 0; l < DQ; ++l) {
-            S[l] = qh[l];
-            S[DQ + l] = ql[l];
+            St[l] = qh[l];
+            St[DQ + l] = ql[l];
             if constexpr (KIND != kUserOde) {
-              S[2 * DQ + l] = vh[l];
-              S[3 * DQ + l] = vl[l];
+              St[2 * DQ + l] = vh[l];
+              St[3 * DQ + l] = vl[l];
             }
 #pragma unroll
-            for (int s = 0; s < kS; ++s) S[4 * DQ + l * kS + s] = R[l][s];
+            for (int s = 0; s < S; ++s) St[4 * DQ + l * S + s] = R[l][s];
           }
           InstStat st;
           st.steps_done = step;

@@ -119,6 +119,7 @@ struct irkgl16_ctx {
   irk::TuneTable tune;  // launch shapes (read at creation)
   irk::UserKernel* user = nullptr;  // run-time compiled force (irkgl16_create_user)
   bool ode = false;                 // first-order form: state y only, no p in or out
+  int stages = 8;                   // s of the s-stage member (2, 4, 6: user contexts only)
 
   // last call
   bool have_last = false;
@@ -185,6 +186,12 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
       if (rc != IRKGL16_OK) return rc;
     }
   }
+  {
+    // The lower-order members run only on the run-time compiled kernels.
+    const int st = (opt && opt->stages > 0) ? opt->stages : irk::kS;
+    if ((opt && opt->stages < 0) || !irk::stages_supported(st) || (st != irk::kS && !user))
+      return IRKGL16_EINVAL;
+  }
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return IRKGL16_EDEVICE;
   int dev = 0;
@@ -202,6 +209,7 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
     c->max_iter = opt->max_iter > 0 ? opt->max_iter : 100;
     c->record = opt->record_iters != 0;
     c->flags = opt->flags;
+    c->stages = opt->stages > 0 ? opt->stages : irk::kS;
   }
   if (c->max_iter > 255 && c->record) c->max_iter = 255;  // counts stored as bytes
 
@@ -209,6 +217,7 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
     delete c;
     return rc;
   };
+
 
   // Problem constants and state layout.
   std::vector<double> params;
@@ -273,7 +282,7 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
     std::string log;
     const int rc = irk::user_kernel_create(user->src, user->dq,
                                            (c->flags & IRKGL16_REPRODUCIBLE) != 0, user->ode,
-                                           &c->user, &log);
+                                           c->stages, &c->user, &log);
     c->ode = user->ode;
     if (rc != 0) return fail(rc == -1 ? IRKGL16_EINVAL : IRKGL16_EDEVICE);
   }
@@ -315,18 +324,14 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
       (rc = alloc_try(c->d_heads, sizeof(int32_t) * std::max<size_t>(c->classes.size(), 1))))
     return fail(rc);
   {
-    // Coefficient table (layout described in device_common.h).
-    std::vector<double> tab(irk::kTabSize);
-    for (int i = 0; i < irk::kS; ++i) {
-      tab[irk::kTabC + i] = irk::kC[i];
-      tab[irk::kTabB + i] = irk::kB[i];
-      for (int j = 0; j < irk::kS; ++j) {
-        tab[irk::kTabEta + i * irk::kS + j] = irk::kEta[i][j];
-        tab[irk::kTabMu + i * irk::kS + j] = irk::kMu[i][j];
-        tab[irk::kTabNu + i * irk::kS + j] = irk::kNu[i][j];
-        tab[irk::kTabK + i * irk::kS + j] = irk::kK[i][j];
-      }
-    }
+    // Coefficient table of the context's member (layout Tab<s> of device_common.h).
+    const double* src = irk::kTabS8;
+    size_t n = sizeof(irk::kTabS8) / sizeof(double);
+    if (c->stages == 2) src = irk::kTabS2, n = sizeof(irk::kTabS2) / sizeof(double);
+    if (c->stages == 4) src = irk::kTabS4, n = sizeof(irk::kTabS4) / sizeof(double);
+    if (c->stages == 6) src = irk::kTabS6, n = sizeof(irk::kTabS6) / sizeof(double);
+    std::vector<double> tab(irk::kTabSize, 0.0);
+    std::copy(src, src + n, tab.begin());
     if ((rc = alloc_try(c->d_tab, sizeof(double) * tab.size()))) return fail(rc);
     if (hipMemcpy(c->d_tab.p, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice) !=
         hipSuccess)

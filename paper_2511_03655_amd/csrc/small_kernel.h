@@ -35,12 +35,14 @@
 
 namespace irk {
 
+constexpr int kSlot = 8;  // lanes per slot (one instance per slot)
+
 // Reads the stage positions from column `sub` of the slot tile and overwrites
 // the same column with the increments R_sub = h b_sub g(Q_sub): a lane only
 // touches its own column, so no barrier is needed between the read and the
 // write.  Ms: the slot's masses (LDS); coef = (h b_sub) and G; prm: the
 // instance's parameters of a user force; t: the stage time (user force only).
-template <int KIND, int NB, int D, bool EXACT>
+template <int KIND, int NB, int D, bool EXACT, int S = kS>
 __device__ __forceinline__ void stage_increment(double* __restrict__ Xs, int sub,
                                                 const double* __restrict__ Ms, double eps2,
                                                 double hb, double G, const double* prm,
@@ -50,10 +52,10 @@ __device__ __forceinline__ void stage_increment(double* __restrict__ Xs, int sub
   if constexpr (KIND == kUser) {  // R = h b_sub g(Q_sub, t_sub), g from the caller's source
     double q[DQ], r[DQ];
 #pragma unroll
-    for (int l = 0; l < DQ; ++l) q[l] = Xs[l * kS + sub];
+    for (int l = 0; l < DQ; ++l) q[l] = Xs[l * S + sub];
     user_increment<DQ>(q, hb, prm, t, r);
 #pragma unroll
-    for (int l = 0; l < DQ; ++l) Xs[l * kS + sub] = r[l];
+    for (int l = 0; l < DQ; ++l) Xs[l * S + sub] = r[l];
     return;
   }
 #endif
@@ -61,10 +63,10 @@ __device__ __forceinline__ void stage_increment(double* __restrict__ Xs, int sub
   if constexpr (KIND == kUserOde) {  // L = h b_sub f(t_sub, Y_sub), first-order form
     double y[DQ], r[DQ];
 #pragma unroll
-    for (int l = 0; l < DQ; ++l) y[l] = Xs[l * kS + sub];
+    for (int l = 0; l < DQ; ++l) y[l] = Xs[l * S + sub];
     ode_increment<DQ>(y, hb, prm, t, r);
 #pragma unroll
-    for (int l = 0; l < DQ; ++l) Xs[l * kS + sub] = r[l];
+    for (int l = 0; l < DQ; ++l) Xs[l * S + sub] = r[l];
     return;
   }
 #endif
@@ -73,10 +75,10 @@ __device__ __forceinline__ void stage_increment(double* __restrict__ Xs, int sub
   if constexpr (KIND == kKepler) {
     double q[DQ], r[DQ];
 #pragma unroll
-    for (int l = 0; l < DQ; ++l) q[l] = Xs[l * kS + sub];
+    for (int l = 0; l < DQ; ++l) q[l] = Xs[l * S + sub];
     kepler_increment<DQ, EXACT>(q, hb, G, r);
 #pragma unroll
-    for (int l = 0; l < DQ; ++l) Xs[l * kS + sub] = r[l];
+    for (int l = 0; l < DQ; ++l) Xs[l * S + sub] = r[l];
   } else if constexpr (EXACT) {
     // Ordered pairs, b ascending for every a, as in the force's definition.
     double out[DQ];
@@ -91,7 +93,7 @@ __device__ __forceinline__ void stage_increment(double* __restrict__ Xs, int sub
         double dx[D], r2 = 0.0;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-          dx[k] = Xs[(b * D + k) * kS + sub] - Xs[(a * D + k) * kS + sub];
+          dx[k] = Xs[(b * D + k) * S + sub] - Xs[(a * D + k) * S + sub];
           r2 = r2 + dx[k] * dx[k];
         }
         r2 = r2 + eps2;
@@ -103,7 +105,7 @@ __device__ __forceinline__ void stage_increment(double* __restrict__ Xs, int sub
       for (int k = 0; k < D; ++k) out[a * D + k] = hb * (G * acc[k]);
     }
 #pragma unroll
-    for (int l = 0; l < DQ; ++l) Xs[l * kS + sub] = out[l];
+    for (int l = 0; l < DQ; ++l) Xs[l * S + sub] = out[l];
   } else {
     double m[NB];
 #pragma unroll
@@ -118,7 +120,7 @@ __device__ __forceinline__ void stage_increment(double* __restrict__ Xs, int sub
       for (int b = a + 1; b < NB; ++b) {
         double dx[D];
 #pragma unroll
-        for (int k = 0; k < D; ++k) dx[k] = Xs[(b * D + k) * kS + sub] - Xs[(a * D + k) * kS + sub];
+        for (int k = 0; k < D; ++k) dx[k] = Xs[(b * D + k) * S + sub] - Xs[(a * D + k) * S + sub];
         double r2 = fma(dx[0], dx[0], eps2);
 #pragma unroll
         for (int k = 1; k < D; ++k) r2 = fma(dx[k], dx[k], r2);
@@ -133,14 +135,14 @@ __device__ __forceinline__ void stage_increment(double* __restrict__ Xs, int sub
     }
     const double coef = hb * G;
 #pragma unroll
-    for (int l = 0; l < DQ; ++l) Xs[l * kS + sub] = coef * acc[l];
+    for (int l = 0; l < DQ; ++l) Xs[l * S + sub] = coef * acc[l];
   }
 }
 
-template <int DQ>
+template <int DQ, int S = kS>
 struct SmallTile {
   // Slot tiles padded so that consecutive slots start on different LDS banks.
-  static constexpr int kStride = ((DQ * kS * 2) % 32 == 0) ? DQ * kS + 8 : DQ * kS;
+  static constexpr int kStride = ((DQ * S * 2) % 32 == 0) ? DQ * S + 8 : DQ * S;
 };
 
 // Per-slot bookkeeping, kept in LDS rather than replicated in 8 lanes' VGPRs.
@@ -153,11 +155,11 @@ struct SlotMeta {
   int32_t inst, maxk, kslot, flags;  // flags: 1 dead, 2 capped
 };
 
-template <int KIND, int NB, int D, bool EXACT>
+template <int KIND, int NB, int D, bool EXACT, int S = kS>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void small_kernel(LaunchArgs a) {
   constexpr int DQ = NB * D;
-  constexpr int CPL = (DQ + kS - 1) / kS;  // components owned per lane
-  constexpr int TS = SmallTile<DQ>::kStride;
+  constexpr int CPL = (DQ + kSlot - 1) / kSlot;  // components owned per lane
+  constexpr int TS = SmallTile<DQ, S>::kStride;
   __shared__ double X[8 * TS];
   __shared__ SlotMeta<NB> meta[8];
   __shared__ int32_t slot_inst[8];
@@ -172,13 +174,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
   const ConstTab T = const_tab(a.tab);
   // Owned component cc is c = sub + 8 cc; lanes past Dq compute on a clamped
   // copy and never store.
-  auto comp = [&](int cc) { return sub + kS * cc; };
-  auto owns = [&](int cc) { return sub + kS * cc < DQ; };
-  auto cidx = [&](int cc) { return (sub + kS * cc < DQ) ? sub + kS * cc : DQ - 1; };
+  auto comp = [&](int cc) { return sub + kSlot * cc; };
+  auto owns = [&](int cc) { return sub + kSlot * cc < DQ; };
+  auto cidx = [&](int cc) { return (sub + kSlot * cc < DQ) ? sub + kSlot * cc : DQ - 1; };
 
   int inst = -1;
   double qh[CPL] = {}, ql[CPL] = {}, vh[CPL] = {}, vl[CPL] = {}, mind[CPL] = {}, prv[CPL] = {};
-  double Qc[CPL][kS] = {};
+  double Qc[CPL][S] = {};
 
   if (lane == 0) qdone = 0;
   if (lane < 8) {
@@ -233,17 +235,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
     __syncthreads();
     if (fresh) {  // component state of the new instance
       inst = cur;
-      const double* S = a.state + M.state_off;
-      double Rp[CPL][kS];
+      const double* St = a.state + M.state_off;
+      double Rp[CPL][S];
 #pragma unroll
       for (int cc = 0; cc < CPL; ++cc) {
         const int c = cidx(cc);
-        qh[cc] = S[c];
-        ql[cc] = S[DQ + c];
-        vh[cc] = S[2 * DQ + c];
-        vl[cc] = S[3 * DQ + c];
+        qh[cc] = St[c];
+        ql[cc] = St[DQ + c];
+        vh[cc] = St[2 * DQ + c];
+        vl[cc] = St[3 * DQ + c];
 #pragma unroll
-        for (int s = 0; s < kS; ++s) Rp[cc][s] = S[4 * DQ + c * kS + s];
+        for (int s = 0; s < S; ++s) Rp[cc][s] = St[4 * DQ + c * S + s];
       }
       form_guess<KIND, CPL, EXACT>(T, qh, vh, Rp, M.h, Qc);
     }
@@ -262,28 +264,28 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
         for (int cc = 0; cc < CPL; ++cc) {
           if (owns(cc)) {
 #pragma unroll
-            for (int s = 0; s < kS; ++s) Xs[comp(cc) * kS + s] = Qc[cc][s];
+            for (int s = 0; s < S; ++s) Xs[comp(cc) * S + s] = Qc[cc][s];
           }
         }
       }
       __syncthreads();
-      if (!conv)
-        stage_increment<KIND, NB, D, EXACT>(Xs, sub, M.m, M.eps2, h * T[kTabB + sub], M.G,
-                                            M.prm_off >= 0 ? a.params + M.prm_off : nullptr,
-                                            stage_time(M.step, h, T[kTabC + sub]));
+      if (!conv && sub < S)  // lanes past the stage count idle in this role
+        stage_increment<KIND, NB, D, EXACT, S>(Xs, sub, M.m, M.eps2, h * T[Tab<S>::B + sub], M.G,
+                                               M.prm_off >= 0 ? a.params + M.prm_off : nullptr,
+                                               stage_time(M.step, h, T[Tab<S>::C + sub]));
       __syncthreads();
       bool ok = true, bad = false;
       if (!conv) {
-        double R[CPL][kS], dmax[CPL], nf[CPL];
+        double R[CPL][S], dmax[CPL], nf[CPL];
 #pragma unroll
         for (int cc = 0; cc < CPL; ++cc) {
           dmax[cc] = 0.0;
           nf[cc] = 0.0;
 #pragma unroll
-          for (int s = 0; s < kS; ++s) R[cc][s] = Xs[cidx(cc) * kS + s];
+          for (int s = 0; s < S; ++s) R[cc][s] = Xs[cidx(cc) * S + s];
         }
 #pragma unroll
-        for (int s = 0; s < kS; ++s) {
+        for (int s = 0; s < S; ++s) {
           const ConstTab r = row_tab(T);
 #pragma unroll
           for (int cc = 0; cc < CPL; ++cc) {
@@ -345,13 +347,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
         const int64_t step = step0 + 1;
         const bool frame = (step % stride) == 0;
         const bool last = step >= M.target;
-        double* S = a.state + M.state_off;
-        double R[CPL][kS];
+        double* St = a.state + M.state_off;
+        double R[CPL][S];
         const ConstTab r = row_tab(T);
 #pragma unroll
         for (int cc = 0; cc < CPL; ++cc) {
 #pragma unroll
-          for (int s = 0; s < kS; ++s) R[cc][s] = Xs[cidx(cc) * kS + s];
+          for (int s = 0; s < S; ++s) R[cc][s] = Xs[cidx(cc) * S + s];
           form_update<KIND, EXACT>(r, R[cc], h, qh[cc], ql[cc], vh[cc], vl[cc]);
           if (owns(cc)) {
             const int c = comp(cc);
@@ -361,12 +363,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
               if constexpr (KIND != kUserOde) a.pout[out_off + f * DQ + c] = M.m[c / D] * vh[cc];
             }
             if (last) {
-              S[c] = qh[cc];
-              S[DQ + c] = ql[cc];
-              S[2 * DQ + c] = vh[cc];
-              S[3 * DQ + c] = vl[cc];
+              St[c] = qh[cc];
+              St[DQ + c] = ql[cc];
+              St[2 * DQ + c] = vh[cc];
+              St[3 * DQ + c] = vl[cc];
 #pragma unroll
-              for (int s = 0; s < kS; ++s) S[4 * DQ + c * kS + s] = R[cc][s];
+              for (int s = 0; s < S; ++s) St[4 * DQ + c * S + s] = R[cc][s];
             }
           }
         }

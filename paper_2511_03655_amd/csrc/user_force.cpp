@@ -13,8 +13,9 @@
 //
 // with the device headers served from copies embedded in this library at
 // build time, so the run-time kernel is the same code as the ahead-of-time
-// one.  Compiled code objects are cached per process by (source, dq, form,
-// arithmetic mode).
+// one.  The kernels are instantiated for the context's stage count (8, or 2,
+// 4, 6 for the lower-order members of the family).  Compiled code objects are
+// cached per process by (source, dq, form, arithmetic mode, stage count).
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
@@ -39,12 +40,14 @@ constexpr int kNumRtcHeaders = (int)(sizeof(kRtcHeaderNames) / sizeof(kRtcHeader
 
 bool use_lane_kernel(int dq) { return dq <= kLaneMaxDqHost; }
 
-std::string kernel_expr(int dq, bool exact, bool ode) {
+std::string kernel_expr(int dq, bool exact, bool ode, int stages) {
   const std::string mode = exact ? "true" : "false";
   const std::string kind = std::to_string(ode ? kUserOde : kUser);
+  const std::string st = std::to_string(stages);
   if (use_lane_kernel(dq))
-    return "&irk::lane_kernel<" + kind + ", " + std::to_string(dq) + ", " + mode + ">";
-  return "&irk::small_kernel<" + kind + ", 1, " + std::to_string(dq) + ", " + mode + ">";
+    return "&irk::lane_kernel<" + kind + ", " + std::to_string(dq) + ", " + mode + ", " + st + ">";
+  return "&irk::small_kernel<" + kind + ", 1, " + std::to_string(dq) + ", " + mode + ", " + st +
+         ">";
 }
 
 struct Compiled {
@@ -53,11 +56,12 @@ struct Compiled {
 };
 
 std::mutex g_cache_mu;
-std::map<std::tuple<std::string, int, bool, bool>, Compiled> g_cache;
+std::map<std::tuple<std::string, int, bool, bool, int>, Compiled> g_cache;
 
-// Compiles the program for one (source, dq, form, mode); on failure returns
-// false and the compiler log in *log.
-bool compile(const char* src, int dq, bool exact, bool ode, Compiled* out, std::string* log) {
+// Compiles the program for one (source, dq, form, mode, stage count); on
+// failure returns false and the compiler log in *log.
+bool compile(const char* src, int dq, bool exact, bool ode, int stages, Compiled* out,
+             std::string* log) {
   std::string prog = std::string(ode ? "#define IRKGL16_USER_ODE 1" : "#define IRKGL16_USER_FORCE 1") +
                      "\n#define IRKGL16_DQ " + std::to_string(dq) +
                      "\n#line 1 \"user_force\"\n" + src + "\n#line 1 \"irkgl16_rtc\"\n" +
@@ -69,7 +73,7 @@ bool compile(const char* src, int dq, bool exact, bool ode, Compiled* out, std::
     *log = "hiprtcCreateProgram failed";
     return false;
   }
-  const std::string expr = kernel_expr(dq, exact, ode);
+  const std::string expr = kernel_expr(dq, exact, ode, stages);
   bool ok = hiprtcAddNameExpression(p, expr.c_str()) == HIPRTC_SUCCESS;
   const char* opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off",
                         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
@@ -100,9 +104,9 @@ bool compile(const char* src, int dq, bool exact, bool ode, Compiled* out, std::
   return ok;
 }
 
-bool compile_cached(const char* src, int dq, bool exact, bool ode, Compiled* out,
+bool compile_cached(const char* src, int dq, bool exact, bool ode, int stages, Compiled* out,
                     std::string* log) {
-  const auto key = std::make_tuple(std::string(src), dq, exact, ode);
+  const auto key = std::make_tuple(std::string(src), dq, exact, ode, stages);
   {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     auto it = g_cache.find(key);
@@ -111,7 +115,7 @@ bool compile_cached(const char* src, int dq, bool exact, bool ode, Compiled* out
       return true;
     }
   }
-  if (!compile(src, dq, exact, ode, out, log)) return false;
+  if (!compile(src, dq, exact, ode, stages, out, log)) return false;
   std::lock_guard<std::mutex> lk(g_cache_mu);
   g_cache[key] = *out;
   return true;
@@ -121,6 +125,8 @@ bool compile_cached(const char* src, int dq, bool exact, bool ode, Compiled* out
 
 bool user_dq_supported(int dq) { return dq >= 1 && dq <= kUserMaxDq; }
 
+bool stages_supported(int s) { return s == 2 || s == 4 || s == 6 || s == 8; }
+
 int user_compile_check(const char* src, int dq, bool ode, std::string* log) {
   log->clear();
   if (!src || !user_dq_supported(dq)) {
@@ -128,20 +134,21 @@ int user_compile_check(const char* src, int dq, bool ode, std::string* log) {
     return -1;
   }
   Compiled c;
-  return compile_cached(src, dq, false, ode, &c, log) ? 0 : -1;
+  return compile_cached(src, dq, false, ode, kS, &c, log) ? 0 : -1;
 }
 
-int user_kernel_create(const char* src, int dq, bool exact, bool ode, UserKernel** out,
-                       std::string* log) {
+int user_kernel_create(const char* src, int dq, bool exact, bool ode, int stages,
+                       UserKernel** out, std::string* log) {
   *out = nullptr;
   log->clear();
-  if (!src || !user_dq_supported(dq)) return -1;
+  if (!src || !user_dq_supported(dq) || !stages_supported(stages)) return -1;
   Compiled c;
-  if (!compile_cached(src, dq, exact, ode, &c, log)) return -1;
+  if (!compile_cached(src, dq, exact, ode, stages, &c, log)) return -1;
   UserKernel* k = new UserKernel();
   k->dq = dq;
   k->exact = exact;
   k->ode = ode;
+  k->stages = stages;
   k->lanes_per_inst = use_lane_kernel(dq) ? 1 : 8;
   if (hipModuleLoadData(&k->mod, c.code.data()) != hipSuccess ||
       hipModuleGetFunction(&k->fn, k->mod, c.lowered.c_str()) != hipSuccess) {

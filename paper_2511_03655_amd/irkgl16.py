@@ -38,7 +38,8 @@ class irkgl16_problem(C.Structure):
 
 
 class irkgl16_options(C.Structure):
-    _fields_ = [("max_iter", C.c_int32), ("record_iters", C.c_int32), ("flags", C.c_uint32)]
+    _fields_ = [("max_iter", C.c_int32), ("record_iters", C.c_int32), ("flags", C.c_uint32),
+                ("stages", C.c_int32)]
 
 
 class irkgl16_stats(C.Structure):
@@ -158,14 +159,14 @@ def irkgl16_create(problems, max_iter=0, record_iters=False, flags=0, stream=Non
 
 
 def irkgl16_create_user(force_src, dq, params, n_inst, max_iter=0, record_iters=False, flags=0,
-                        stream=None):
+                        stream=None, stages=0):
     """Context for n_inst instances of a force given as device source.
 
     params: array of shape (n_inst, n_params) (or None for no parameters).
     """
     prm = None if params is None else np.ascontiguousarray(params, np.float64).reshape(n_inst, -1)
     n_params = 0 if prm is None else prm.shape[1]
-    opt = irkgl16_options(int(max_iter), int(bool(record_iters)), int(flags))
+    opt = irkgl16_options(int(max_iter), int(bool(record_iters)), int(flags), int(stages))
     if stream is not None and hasattr(stream, "cuda_stream"):
         stream = stream.cuda_stream
     ctx = C.c_void_p()
@@ -186,11 +187,11 @@ def irkgl16_user_compile_check(force_src, dq, log_len=1 << 16):
 
 
 def irkgl16_create_ode(rhs_src, D, params, n_inst, max_iter=0, record_iters=False, flags=0,
-                       stream=None):
+                       stream=None, stages=0):
     """First-order context (y' = f(t, y)) for n_inst instances of D components."""
     prm = None if params is None else np.ascontiguousarray(params, np.float64).reshape(n_inst, -1)
     n_params = 0 if prm is None else prm.shape[1]
-    opt = irkgl16_options(int(max_iter), int(bool(record_iters)), int(flags))
+    opt = irkgl16_options(int(max_iter), int(bool(record_iters)), int(flags), int(stages))
     if stream is not None and hasattr(stream, "cuda_stream"):
         stream = stream.cuda_stream
     ctx = C.c_void_p()
@@ -242,7 +243,7 @@ class Integrator:
 
     @classmethod
     def user(cls, force_src, dq, n_inst, params=None, max_iter=0, record_iters=False, flags=0,
-             stream=None):
+             stream=None, stages=0):
         """Integrator of n_inst instances of a user force (irkgl16_create_user)."""
         self = cls.__new__(cls)
         self.problems = [dict(kind=-1, n=1, d=int(dq))] * int(n_inst)
@@ -251,12 +252,12 @@ class Integrator:
         self.record_iters = bool(record_iters)
         self.ctx = None
         self.ctx = irkgl16_create_user(force_src, dq, params, n_inst, max_iter, record_iters,
-                                       flags, stream)
+                                       flags, stream, stages)
         return self
 
     @classmethod
     def ode(cls, rhs_src, D, n_inst, params=None, max_iter=0, record_iters=False, flags=0,
-            stream=None):
+            stream=None, stages=0):
         """Integrator of n_inst first-order instances (irkgl16_create_ode): y0 is
         passed as q0; integrate returns the y frames as q_out (p_out is None)."""
         self = cls.__new__(cls)
@@ -267,7 +268,7 @@ class Integrator:
         self.is_ode = True
         self.ctx = None
         self.ctx = irkgl16_create_ode(rhs_src, D, params, n_inst, max_iter, record_iters, flags,
-                                      stream)
+                                      stream, stages)
         return self
 
     def close(self):
