@@ -142,7 +142,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-served", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "henon", "sbh"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "henon", "sbh", "stages"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -670,8 +670,75 @@ def run_sbh(args):
                     "cpu_baseline": cpu})
 
 
+def run_stages(args):
+    """Work-precision of the s-stage members (s = 2, 4, 6, 8) on a Henon-Heiles
+    ensemble over a fixed time span: energy error against GPU time and force
+    evaluations, for several step sizes per s (the comparison of the paper's
+    section 5.2, here on the GPU)."""
+    import torch
+    from paper_2511_03655_amd import irkgl16 as K
+    from paper_2511_03655_amd import user_forces as UF
+    from paper_2511_03655_amd import workloads as W
+    n_orb, periods, n_frames = 16384, 50, 50
+    q0, p0 = W.henon_heiles_ensemble(n_orb)
+    q0, p0 = q0.ravel(), p0.ravel()
+    steps_per_period = {8: (4, 5, 6, 8, 12, 16, 32), 6: (6, 8, 10, 12, 16, 24, 32),
+                        4: (16, 24, 32, 48, 64, 96), 2: (64, 128, 256, 512, 1024, 2048)}
+
+    def energy(q, p):
+        return 0.5 * (p ** 2).sum(-1) + 0.5 * (q ** 2).sum(-1) + q[..., 0] ** 2 * q[..., 1] \
+            - q[..., 1] ** 3 / 3
+
+    rows = {}
+    best = None
+    for s, nps in steps_per_period.items():
+        stream = torch.cuda.Stream()
+        integ = K.Integrator.user(UF.HENON_HEILES, 2, n_orb, flags=K.IRKGL16_DEVICE_PTRS,
+                                  stream=stream, stages=s)
+        out = []
+        for m in nps:
+            nsteps = periods * m
+            h = 2 * np.pi / m
+            ns = np.full(n_orb, nsteps, np.int64)
+            sd = np.full(n_orb, nsteps // n_frames, np.int64)
+            dt, st, rc, qo, po = _timed_gpu(integ, q0, p0, np.full(n_orb, h), ns, sd)
+            q = qo.cpu().numpy().reshape(n_orb, n_frames + 1, 2)
+            p = po.cpu().numpy().reshape(n_orb, n_frames + 1, 2)
+            E = energy(q, p)
+            per_orbit = np.max(np.abs(E / E[:, :1] - 1), axis=1)
+            err = float(np.median(per_orbit)) if np.all(np.isfinite(per_orbit)) else float("inf")
+            out.append({"h": h, "steps_per_orbit": nsteps, "energy_error": err,
+                        "gpu_ms": st["device_ms"], "mean_iterations_per_step":
+                        st["iterations"] / (n_orb * nsteps),
+                        "force_evals_per_orbit": s * st["iterations"] / n_orb})
+            print(f"stages: s={s} steps/period={m} err={err:.2e} {st['device_ms']:.1f} ms",
+                  file=sys.stderr, flush=True)
+        rows[s] = out
+        integ.close()
+    # cheapest run (GPU time) reaching each target precision, per s
+    targets = (1e-10, 1e-12, 1e-13)
+    fastest = {}
+    for tgt in targets:
+        cand = {s: min((r["gpu_ms"] for r in rs if r["energy_error"] <= tgt), default=None)
+                for s, rs in rows.items()}
+        reach = {s: v for s, v in cand.items() if v is not None}
+        fastest[f"{tgt:.0e}"] = {"gpu_ms": cand, "fastest_s": min(reach, key=reach.get)
+                                 if reach else None}
+    r8 = rows[8][-1]
+    value = n_orb * r8["steps_per_orbit"] / (r8["gpu_ms"] / 1e3)
+    return _common("instance-steps/s", value,
+                   {"workload": f"{n_orb} Henon-Heiles orbits near q2=0.3, p2=0.2 at H=1/12, "
+                                f"{periods} periods (t = {periods} x 2 pi), s = 2, 4, 6, 8 "
+                                "stages at several step sizes each; value: s = 8 at the "
+                                "smallest step"},
+                   {"work_precision": {str(s): rs for s, rs in rows.items()},
+                    "error_measure": "median over orbits of max_t |H(t)/H(0) - 1| over "
+                                     f"{n_frames} frames",
+                    "cheapest_run_reaching": fastest})
+
+
 OTHER_WORKLOADS = {"c1": run_c1, "c3": run_c3, "c4": run_c4, "c5": run_c5, "henon": run_henon,
-                   "sbh": run_sbh}
+                   "sbh": run_sbh, "stages": run_stages}
 
 
 if __name__ == "__main__":
