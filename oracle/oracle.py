@@ -24,12 +24,14 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liborc.so")
-SOURCES = ["irkgl16_oracle.c", "irkgl16_dd.c", "irkgl16_ode.c"]
+SOURCES = ["irkgl16_oracle.c", "irkgl16_dd.c", "irkgl16_ode.c", "irkgl16_split.c"]
 
 KEPLER, GRAVITY, CHAIN, HARMONIC, CONST, HENON = 0, 1, 2, 10, 11, 12
 HENON_T, DRIVEN = 13, 14  # time-dependent: lambda = G, xi = beta; g = G cos t
 # first-order problems y' = f(t, y) (irkgl16_ode.c): D = n * d
 ODE_OSC, ODE_KEPLER, ODE_DAMPED, ODE_SBH, ODE_DRIVEN = 20, 21, 22, 23, 24
+# explicit splitting baselines (irkgl16_split.c)
+STRANG, SUZ90 = 1, 2
 FLAG_NO_COMPENSATION, FLAG_NAIVE_ETA, FLAG_NO_EXTRAPOLATION = 1, 2, 4
 OK, EINVAL, ENOMEM, ENONFINITE, ENOCONV = 0, -1, -2, -4, 1
 
@@ -115,6 +117,12 @@ def lib():
         L.orc_integrate_ode_batch_s.argtypes = [C.c_int32, C.c_int32, C.POINTER(Problem), dp, dp,
                                                 i64p, i64p, C.c_int32, dp, i64p, i32p]
         L.orc_integrate_ode_batch_s.restype = C.c_int
+        L.orc_split_integrate.argtypes = [C.POINTER(Problem), C.c_int32, dp, dp, C.c_double,
+                                          C.c_int64, C.c_int64, dp, dp, C.POINTER(Stats)]
+        L.orc_split_integrate.restype = C.c_int
+        L.orc_split_integrate_batch.argtypes = [C.c_int32, C.c_int32, C.POINTER(Problem), dp, dp,
+                                                dp, i64p, i64p, dp, dp, i32p]
+        L.orc_split_integrate_batch.restype = C.c_int
         _lib = L
     return _lib
 
@@ -424,3 +432,41 @@ def integrate_ode_batch(specs, y0, h, nsteps, stride, max_iter=100, s=8):
                                      _dp(yo), iters.ctypes.data_as(C.POINTER(C.c_int64)),
                                      status.ctypes.data_as(C.POINTER(C.c_int32)))
     return dict(y=yo, iters=iters, status=status, rc=rc)
+
+
+# ---------------------------------------------------------------- explicit splitting
+
+def split_integrate(spec, method, q0, p0, h, nsteps, stride=1):
+    """Explicit symmetric composition (STRANG or SUZ90) in ABA form, one
+    instance.  Returns dict(q, p, rc)."""
+    L = lib()
+    q0 = np.ascontiguousarray(q0, np.float64)
+    p0 = np.ascontiguousarray(p0, np.float64)
+    nf = nsteps // stride + 1
+    qo = np.empty((nf, spec.Dq))
+    po = np.empty((nf, spec.Dq))
+    st = Stats()
+    pr = spec.struct()
+    rc = L.orc_split_integrate(C.byref(pr), int(method), _dp(q0), _dp(p0), float(h),
+                               int(nsteps), int(stride), _dp(qo), _dp(po), C.byref(st))
+    return dict(q=qo, p=po, rc=rc, steps_done=st.steps_done)
+
+
+def split_integrate_batch(specs, method, q0, p0, h, nsteps, stride):
+    L = lib()
+    n = len(specs)
+    arr = (Problem * n)(*[s.struct() for s in specs])
+    q0 = np.ascontiguousarray(q0, np.float64)
+    p0 = np.ascontiguousarray(p0, np.float64)
+    h = np.ascontiguousarray(np.broadcast_to(h, (n,)), np.float64)
+    ns = np.ascontiguousarray(np.broadcast_to(nsteps, (n,)), np.int64)
+    sd = np.ascontiguousarray(np.broadcast_to(stride, (n,)), np.int64)
+    tot = int(sum(s.Dq * (int(a) // int(b) + 1) for s, a, b in zip(specs, ns, sd)))
+    qo = np.empty(tot)
+    po = np.empty(tot)
+    status = np.zeros(n, np.int32)
+    rc = L.orc_split_integrate_batch(n, int(method), arr, _dp(q0), _dp(p0), _dp(h),
+                                     ns.ctypes.data_as(C.POINTER(C.c_int64)),
+                                     sd.ctypes.data_as(C.POINTER(C.c_int64)), _dp(qo), _dp(po),
+                                     status.ctypes.data_as(C.POINTER(C.c_int32)))
+    return dict(q=qo, p=po, status=status, rc=rc)

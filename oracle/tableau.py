@@ -198,6 +198,34 @@ def dd_tables(ex=None):
     return dict(c=c, b=b, eta=eta, mu=mu, nu=nu)
 
 
+def splitting_coefficients():
+    """Explicit symmetric compositions of Strang steps (section 4, eqs. Strang,
+    comp_method, high_order_splitting), in the ABA form
+    phi^A_{a_{s+1} h} o phi^B_{b_s h} o ... o phi^B_{b_1 h} o phi^A_{a_1 h}:
+    a_1 = g_1/2, a_j = (g_{j-1} + g_j)/2, a_{s+1} = g_s/2, b_j = g_j, and the
+    drift fractions c_j = a_1 + ... + a_j at which the B flows act.
+
+    * Strang: s = 1, g = (1).
+    * SUZ90 (Suzuki 1990, order 4, s = 5): g_1 = g_2 = g_4 = g_5 =
+      1 / (4 - 4^(1/3)), g_3 = 1 - 4 g_1 (the composition is consistent, sum
+      g = 1, and fourth order, sum g^3 = 0).
+
+    Returns {name: dict(gamma, a, b, c)} with binary64 values (each rounded
+    once from DPS digits) plus the exact mpmath gammas under "gamma_exact".
+    """
+    out = {}
+    with mpmath.workdps(DPS):
+        g1 = 1 / (4 - mpmath.cbrt(4))
+        for name, gam in (("STRANG", [mpmath.mpf(1)]),
+                          ("SUZ90", [g1, g1, 1 - 4 * g1, g1, g1])):
+            s = len(gam)
+            a = [gam[0] / 2] + [(gam[j - 1] + gam[j]) / 2 for j in range(1, s)] + [gam[-1] / 2]
+            c = [mpmath.fsum(a[:j + 1]) for j in range(s)]
+            out[name] = dict(gamma=[rne(x) for x in gam], a=[rne(x) for x in a],
+                             b=[rne(x) for x in gam], c=[rne(x) for x in c], gamma_exact=gam)
+    return out
+
+
 def _emit_header(path, fp, dd, others):
     lines = [
         "/* Generated by oracle/tableau.py -- do not edit.",
@@ -237,6 +265,10 @@ def _emit_header(path, fp, dd, others):
     for nm in ("eta", "mu", "nu"):
         mat(f"ORC_DD_{nm.upper()}_HI", [[p[0] for p in row] for row in dd[nm]])
         mat(f"ORC_DD_{nm.upper()}_LO", [[p[1] for p in row] for row in dd[nm]])
+    for name, t in splitting_coefficients().items():  # explicit baselines
+        vec_s(f"ORC_{name}_A", t["a"])
+        vec_s(f"ORC_{name}_B", t["b"])
+        vec_s(f"ORC_{name}_C", t["c"])
     for st, t in others.items():  # lower stage counts (same construction)
         vec_s(f"ORC_S{st}_C", t["c"])
         vec_s(f"ORC_S{st}_B", t["b"])
