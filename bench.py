@@ -142,7 +142,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-served", action="store_true")
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "henon", "sbh", "stages"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "henon", "sbh", "stages",
+                             "explicit"])
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -737,8 +738,81 @@ def run_stages(args):
                     "cheapest_run_reaching": fastest})
 
 
+def run_explicit(args):
+    """IRKGL16 against the explicit symplectic baselines (Strang, SUZ90) on a
+    Henon-Heiles ensemble: maximum local energy error (eq. DHlocmax) against
+    GPU time and force evaluations, and the GPU time per force evaluation of
+    IRKGL16 normalised by that of the explicit methods at the IRKGL16 step
+    whose local energy error is closest to 1e-14 (the quantity of the paper's
+    Table 1, there measured on one CPU core)."""
+    import torch
+    from paper_2511_03655_amd import irkgl16 as K
+    from paper_2511_03655_amd import user_forces as UF
+    from paper_2511_03655_amd import workloads as W
+    n_orb, periods, n_err = 16384, 10, 256
+    q0, p0 = W.henon_heiles_ensemble(n_orb)
+    q0, p0 = q0.ravel(), p0.ravel()
+    methods = {"IRKGL16": (0, 8, (3, 4, 5, 6, 8, 12)),
+               "SUZ90": (K.IRKGL16_SUZ90, 5, (64, 128, 256, 512, 1024, 2048)),
+               "Strang": (K.IRKGL16_STRANG, 1, (256, 1024, 4096, 16384))}
+
+    def energy(q, p):
+        return 0.5 * (p ** 2).sum(-1) + 0.5 * (q ** 2).sum(-1) + q[..., 0] ** 2 * q[..., 1] \
+            - q[..., 1] ** 3 / 3
+
+    rows = {}
+    for name, (method, evals, nps) in methods.items():
+        stream = torch.cuda.Stream()
+        integ = K.Integrator.user(UF.HENON_HEILES, 2, n_orb, flags=K.IRKGL16_DEVICE_PTRS,
+                                  stream=stream, method=method)
+        probe = K.Integrator.user(UF.HENON_HEILES, 2, n_err, method=method)
+        out = []
+        for m in nps:
+            h = 2 * np.pi / m
+            nsteps = periods * m
+            ns = np.full(n_orb, nsteps, np.int64)
+            dt, st, rc, qo, po = _timed_gpu(integ, q0, p0, np.full(n_orb, h), ns, ns)
+            f_evals = (8 * st["iterations"] if method == 0 else evals * n_orb * nsteps)
+            # local energy error over one period, every step, on a subset
+            qe, pe, ste, _ = probe.integrate(q0[:2 * n_err], p0[:2 * n_err], h, m, 1)
+            E = energy(qe.reshape(n_err, m + 1, 2), pe.reshape(n_err, m + 1, 2))
+            loc = np.max(np.abs(np.diff(E, axis=1) / E[:, :-1]), axis=1)
+            out.append({"h": h, "steps_per_period": m, "local_energy_error": float(np.median(loc)),
+                        "gpu_ms": st["device_ms"], "force_evals_per_orbit": f_evals / n_orb,
+                        "gpu_ns_per_force_eval": st["device_ms"] * 1e6 / f_evals})
+            print(f"explicit: {name} steps/period={m} err={np.median(loc):.2e} "
+                  f"{st['device_ms']:.1f} ms", file=sys.stderr, flush=True)
+        rows[name] = out
+        integ.close()
+        probe.close()
+    ref = min(rows["IRKGL16"], key=lambda r: abs(np.log10(max(r["local_energy_error"], 1e-300))
+                                                 + 14))
+    per_eval_explicit = {n: float(np.median([r["gpu_ns_per_force_eval"] for r in rows[n]]))
+                         for n in ("SUZ90", "Strang")}
+    ratio = {n: ref["gpu_ns_per_force_eval"] / v for n, v in per_eval_explicit.items()}
+    cheapest = {}
+    for tgt in (1e-10, 1e-12, 1e-14):
+        cheapest[f"{tgt:.0e}"] = {n: min((r["gpu_ms"] for r in rs
+                                          if r["local_energy_error"] <= tgt), default=None)
+                                  for n, rs in rows.items()}
+    return _common("instance-steps/s", n_orb * periods * ref["steps_per_period"] /
+                   (ref["gpu_ms"] / 1e3),
+                   {"workload": f"{n_orb} Henon-Heiles orbits near q2=0.3, p2=0.2 at H=1/12, "
+                                f"{periods} periods; IRKGL16 against Strang and SUZ90 "
+                                "(user force compiled at run time); value: IRKGL16 at the step "
+                                "with local energy error closest to 1e-14"},
+                   {"work_precision": rows,
+                    "error_measure": f"median over {n_err} orbits of max_n |H_n/H_(n-1) - 1| "
+                                     "over one period (eq. DHlocmax)",
+                    "irkgl16_reference_step": ref,
+                    "gpu_fcn_ratio": {"irkgl16_over": ratio,
+                                      "paper_table1_cpu_simd": 0.6,
+                                      "paper_table1_cpu_seq": 2.5},
+                    "cheapest_run_reaching_local_error": cheapest})
+
+
 OTHER_WORKLOADS = {"c1": run_c1, "c3": run_c3, "c4": run_c4, "c5": run_c5, "henon": run_henon,
-                   "sbh": run_sbh, "stages": run_stages}
+                   "sbh": run_sbh, "stages": run_stages, "explicit": run_explicit}
 
 
 if __name__ == "__main__":

@@ -87,13 +87,27 @@ typedef struct {
  * the family (order 2s; section 2.2): 0 or 8 for IRKGL16; 2, 4 or 6 (IRKGL4,
  * IRKGL8, IRKGL12, coefficients built as for s = 8, section 2.4) only for
  * contexts created by irkgl16_create_user / irkgl16_create_ode; anything else
- * is IRKGL16_EINVAL. */
+ * is IRKGL16_EINVAL.  method: 0 for the implicit method; IRKGL16_STRANG or
+ * IRKGL16_SUZ90 run an explicit symplectic baseline instead (section 4: the
+ * Strang splitting of eq. Strang, or Suzuki's fourth-order composition of
+ * five Strang steps, eq. comp_method, both in the ABA form of eq.
+ * high_order_splitting with the exact flows of eq. flowAB: kicks
+ * v += b_j h g(q, t_j) at t_j = t_{n-1} + (a_1 + ... + a_j) h between drifts
+ * q += a_j h v, on the same two-double state); only for
+ * irkgl16_create_user contexts (with stages 0 or 8), else IRKGL16_EINVAL.
+ * Such a context costs 1 (Strang) or 5 (SUZ90) force evaluations per step and
+ * reports no fixed-point iterations (zero counts). */
 typedef struct {
   int32_t max_iter;
   int32_t record_iters;
   uint32_t flags;
   int32_t stages;
+  int32_t method;
 } irkgl16_options;
+
+/* irkgl16_options.method */
+#define IRKGL16_STRANG 1
+#define IRKGL16_SUZ90 2
 
 /* Results of the last irkgl16_integrate call.  The three pointers are
  * optional caller-owned host arrays filled when non-NULL:

@@ -131,6 +131,43 @@ struct LaunchArgs {
   int32_t exact;         // reproducible arithmetic (see the EXACT policies below)
 };
 
+// One-instance-per-lane kernels: lanes without an instance (inst < 0) take the
+// next ones from the class queue, one atomic per wavefront for all of them
+// (single-shot launches without a queue counter take up to 64 given
+// instances once).  qdone (wave-uniform) marks an exhausted queue.  Returns
+// true for a lane that took a new instance.
+__device__ __forceinline__ bool take_lane_instance(const LaunchArgs& a, int lane, int& inst,
+                                                   bool& qdone, bool& taken) {
+  bool fresh = false;
+  if (a.queue_head) {
+    if (!qdone) {
+      const uint64_t need = __ballot(inst < 0);
+      if (need != 0) {
+        const int cnt = __popcll(need);
+        const int leader = __ffsll((unsigned long long)need) - 1;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(a.queue_head, cnt);
+        base = __shfl(base, leader, 64);
+        if (inst < 0) {
+          const int idx = base + __popcll(need & ((1ull << lane) - 1ull));
+          if (idx < a.queue_len) {
+            inst = a.queue[idx];
+            fresh = true;
+          }
+        }
+        if (base + cnt >= a.queue_len) qdone = true;
+      }
+    }
+  } else if (!taken) {
+    taken = true;
+    if (lane < a.queue_len) {
+      inst = a.queue[lane];
+      fresh = true;
+    }
+  }
+  return fresh;
+}
+
 // x (+) d on a two-double value: (s, e) = TwoSum(hi, d); t = e + lo;
 // (hi, lo) = Fast2Sum(s, t).
 __device__ __forceinline__ void dw_add(double& hi, double& lo, double d) {

@@ -125,6 +125,28 @@ def tables(S=S):
     return dict(c=cf, b=bf, eta=eta, mu=mu, nu=nu, K=K)
 
 
+def splitting_tables():
+    """Explicit baselines (section 4): symmetric compositions of Strang steps in
+    ABA form, flat [a_1..a_{s+1} | b_1..b_s | c_1..c_s] with a_1 = g_1/2,
+    a_j = (g_{j-1} + g_j)/2, a_{s+1} = g_s/2, b_j = g_j and the drift
+    fractions c_j = a_1 + ... + a_j.  Strang: g = (1).  SUZ90 (Suzuki 1990):
+    g_1 = g_2 = g_4 = g_5 = x with x the real root of 4 x^3 + (1 - 4 x)^3 = 0
+    (sum g = 1 and sum g^3 = 0), found by Newton's method; g_3 = 1 - 4 x."""
+    x = mpmath.mpf("0.4")
+    for _ in range(200):
+        f = 4 * x ** 3 + (1 - 4 * x) ** 3
+        df = 12 * x ** 2 - 12 * (1 - 4 * x) ** 2
+        x -= f / df
+    assert abs(4 * x ** 3 + (1 - 4 * x) ** 3) < mpmath.mpf(10) ** -90
+    out = {}
+    for name, g in (("Strang", [mpmath.mpf(1)]), ("Suz90", [x, x, 1 - 4 * x, x, x])):
+        s = len(g)
+        a = [g[0] / 2] + [(g[j - 1] + g[j]) / 2 for j in range(1, s)] + [g[-1] / 2]
+        c = [mpmath.fsum(a[:j + 1]) for j in range(s)]
+        out[name] = [fl(v) for v in a] + [fl(v) for v in g] + [fl(v) for v in c]
+    return out
+
+
 def emit(path):
     t = tables()
     out = ["// Generated by gen_coeffs.py -- do not edit.",
@@ -154,6 +176,9 @@ def emit(path):
         for i in range(0, len(flat), 4):
             out.append("    " + ", ".join(x.hex() for x in flat[i:i + 4]) + ",")
         out.append("};")
+    for name, flat in splitting_tables().items():
+        out.append(f"constexpr double kSplit{name}[{len(flat)}] = {{" +
+                   ", ".join(x.hex() for x in flat) + "};")
     vec("kC", t["c"])
     vec("kB", t["b"])
     mat("kEta", t["eta"])

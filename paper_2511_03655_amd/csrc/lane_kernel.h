@@ -81,33 +81,7 @@ __global__ __launch_bounds__(64) void lane_kernel(LaunchArgs a) {
 
   for (;;) {
     // ---- lanes without an instance take the next ones from the queue
-    bool fresh = false;
-    if (a.queue_head) {
-      if (!qdone) {
-        const uint64_t need = __ballot(inst < 0);
-        if (need != 0) {
-          const int cnt = __popcll(need);
-          const int leader = __ffsll((unsigned long long)need) - 1;
-          int base = 0;
-          if (lane == leader) base = atomicAdd(a.queue_head, cnt);
-          base = __shfl(base, leader, 64);
-          if (inst < 0) {
-            const int idx = base + __popcll(need & ((1ull << lane) - 1ull));
-            if (idx < a.queue_len) {
-              inst = a.queue[idx];
-              fresh = true;
-            }
-          }
-          if (base + cnt >= a.queue_len) qdone = true;
-        }
-      }
-    } else if (!taken) {  // single-shot launch: up to 64 given instances
-      taken = true;
-      if (lane < a.queue_len) {
-        inst = a.queue[lane];
-        fresh = true;
-      }
-    }
+    const bool fresh = take_lane_instance(a, lane, inst, qdone, taken);
     if (__ballot(inst >= 0) == 0) break;
 
     if (fresh) {  // bookkeeping and state of a newly taken instance

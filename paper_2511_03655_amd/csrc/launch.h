@@ -59,12 +59,13 @@ struct UserKernel {
   bool exact = false;
   bool ode = false;        // first-order form (irkgl16_user_rhs)
   int stages = 8;          // s of the s-stage member (2, 4, 6, 8)
+  int method = 0;          // 0: IRKGL; 1: Strang; 2: SUZ90 (explicit baselines)
 };
 bool user_dq_supported(int dq);
 bool stages_supported(int s);  // 2, 4, 6, 8
 // 0 on success; -1 compile error (log filled); -3 HIP error.
 int user_compile_check(const char* src, int dq, bool ode, std::string* log);
-int user_kernel_create(const char* src, int dq, bool exact, bool ode, int stages,
+int user_kernel_create(const char* src, int dq, bool exact, bool ode, int stages, int method,
                        UserKernel** out, std::string* log);
 void user_kernel_free(UserKernel* k);
 hipError_t launch_user(const UserKernel& k, const LaunchArgs& a, int n_items, int num_cus,

@@ -120,6 +120,7 @@ struct irkgl16_ctx {
   irk::UserKernel* user = nullptr;  // run-time compiled force (irkgl16_create_user)
   bool ode = false;                 // first-order form: state y only, no p in or out
   int stages = 8;                   // s of the s-stage member (2, 4, 6: user contexts only)
+  int method = 0;                   // IRKGL16_STRANG / IRKGL16_SUZ90: explicit baselines
 
   // last call
   bool have_last = false;
@@ -191,6 +192,11 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
     const int st = (opt && opt->stages > 0) ? opt->stages : irk::kS;
     if ((opt && opt->stages < 0) || !irk::stages_supported(st) || (st != irk::kS && !user))
       return IRKGL16_EINVAL;
+    // The explicit baselines exist for second-order user forces only.
+    const int method = opt ? opt->method : 0;
+    if (method < 0 || method > IRKGL16_SUZ90 ||
+        (method != 0 && (!user || user->ode || (opt->stages != 0 && opt->stages != irk::kS))))
+      return IRKGL16_EINVAL;
   }
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return IRKGL16_EDEVICE;
@@ -210,6 +216,7 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
     c->record = opt->record_iters != 0;
     c->flags = opt->flags;
     c->stages = opt->stages > 0 ? opt->stages : irk::kS;
+    c->method = opt->method;
   }
   if (c->max_iter > 255 && c->record) c->max_iter = 255;  // counts stored as bytes
 
@@ -282,7 +289,7 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
     std::string log;
     const int rc = irk::user_kernel_create(user->src, user->dq,
                                            (c->flags & IRKGL16_REPRODUCIBLE) != 0, user->ode,
-                                           c->stages, &c->user, &log);
+                                           c->stages, c->method, &c->user, &log);
     c->ode = user->ode;
     if (rc != 0) return fail(rc == -1 ? IRKGL16_EINVAL : IRKGL16_EDEVICE);
   }
@@ -330,6 +337,10 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
     if (c->stages == 2) src = irk::kTabS2, n = sizeof(irk::kTabS2) / sizeof(double);
     if (c->stages == 4) src = irk::kTabS4, n = sizeof(irk::kTabS4) / sizeof(double);
     if (c->stages == 6) src = irk::kTabS6, n = sizeof(irk::kTabS6) / sizeof(double);
+    if (c->method == IRKGL16_STRANG)
+      src = irk::kSplitStrang, n = sizeof(irk::kSplitStrang) / sizeof(double);
+    if (c->method == IRKGL16_SUZ90)
+      src = irk::kSplitSuz90, n = sizeof(irk::kSplitSuz90) / sizeof(double);
     std::vector<double> tab(irk::kTabSize, 0.0);
     std::copy(src, src + n, tab.begin());
     if ((rc = alloc_try(c->d_tab, sizeof(double) * tab.size()))) return fail(rc);

@@ -10,6 +10,7 @@
 //     <caller's source, which defines irkgl16_user_force (or irkgl16_user_rhs)>
 //     #include "lane_kernel.h"     (dq <= kLaneMaxDq: one instance per lane)
 //     #include "small_kernel.h"    (otherwise: one instance per 8-lane slot)
+//     #include "split_kernel.h"    (explicit baselines: one instance per lane)
 //
 // with the device headers served from copies embedded in this library at
 // build time, so the run-time kernel is the same code as the ahead-of-time
@@ -40,7 +41,13 @@ constexpr int kNumRtcHeaders = (int)(sizeof(kRtcHeaderNames) / sizeof(kRtcHeader
 
 bool use_lane_kernel(int dq) { return dq <= kLaneMaxDqHost; }
 
-std::string kernel_expr(int dq, bool exact, bool ode, int stages) {
+// Kicks per step of an explicit method (0: not explicit).
+int split_kicks(int method) { return method == 1 ? 1 : method == 2 ? 5 : 0; }
+
+std::string kernel_expr(int dq, bool exact, bool ode, int stages, int method) {
+  if (split_kicks(method))
+    return "&irk::split_kernel<" + std::to_string(kUser) + ", " + std::to_string(dq) + ", " +
+           std::to_string(split_kicks(method)) + ">";
   const std::string mode = exact ? "true" : "false";
   const std::string kind = std::to_string(ode ? kUserOde : kUser);
   const std::string st = std::to_string(stages);
@@ -56,24 +63,25 @@ struct Compiled {
 };
 
 std::mutex g_cache_mu;
-std::map<std::tuple<std::string, int, bool, bool, int>, Compiled> g_cache;
+std::map<std::tuple<std::string, int, bool, bool, int, int>, Compiled> g_cache;
 
 // Compiles the program for one (source, dq, form, mode, stage count); on
 // failure returns false and the compiler log in *log.
-bool compile(const char* src, int dq, bool exact, bool ode, int stages, Compiled* out,
-             std::string* log) {
+bool compile(const char* src, int dq, bool exact, bool ode, int stages, int method,
+             Compiled* out, std::string* log) {
   std::string prog = std::string(ode ? "#define IRKGL16_USER_ODE 1" : "#define IRKGL16_USER_FORCE 1") +
                      "\n#define IRKGL16_DQ " + std::to_string(dq) +
                      "\n#line 1 \"user_force\"\n" + src + "\n#line 1 \"irkgl16_rtc\"\n" +
-                     (use_lane_kernel(dq) ? "#include \"lane_kernel.h\"\n"
-                                          : "#include \"small_kernel.h\"\n");
+                     (split_kicks(method)   ? "#include \"split_kernel.h\"\n"
+                      : use_lane_kernel(dq) ? "#include \"lane_kernel.h\"\n"
+                                            : "#include \"small_kernel.h\"\n");
   hiprtcProgram p;
   if (hiprtcCreateProgram(&p, prog.c_str(), "irkgl16_user.hip", kNumRtcHeaders, kRtcHeaderTexts,
                           kRtcHeaderNames) != HIPRTC_SUCCESS) {
     *log = "hiprtcCreateProgram failed";
     return false;
   }
-  const std::string expr = kernel_expr(dq, exact, ode, stages);
+  const std::string expr = kernel_expr(dq, exact, ode, stages, method);
   bool ok = hiprtcAddNameExpression(p, expr.c_str()) == HIPRTC_SUCCESS;
   const char* opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off",
                         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
@@ -104,9 +112,9 @@ bool compile(const char* src, int dq, bool exact, bool ode, int stages, Compiled
   return ok;
 }
 
-bool compile_cached(const char* src, int dq, bool exact, bool ode, int stages, Compiled* out,
-                    std::string* log) {
-  const auto key = std::make_tuple(std::string(src), dq, exact, ode, stages);
+bool compile_cached(const char* src, int dq, bool exact, bool ode, int stages, int method,
+                    Compiled* out, std::string* log) {
+  const auto key = std::make_tuple(std::string(src), dq, exact, ode, stages, method);
   {
     std::lock_guard<std::mutex> lk(g_cache_mu);
     auto it = g_cache.find(key);
@@ -115,7 +123,7 @@ bool compile_cached(const char* src, int dq, bool exact, bool ode, int stages, C
       return true;
     }
   }
-  if (!compile(src, dq, exact, ode, stages, out, log)) return false;
+  if (!compile(src, dq, exact, ode, stages, method, out, log)) return false;
   std::lock_guard<std::mutex> lk(g_cache_mu);
   g_cache[key] = *out;
   return true;
@@ -134,22 +142,24 @@ int user_compile_check(const char* src, int dq, bool ode, std::string* log) {
     return -1;
   }
   Compiled c;
-  return compile_cached(src, dq, false, ode, kS, &c, log) ? 0 : -1;
+  return compile_cached(src, dq, false, ode, kS, 0, &c, log) ? 0 : -1;
 }
 
-int user_kernel_create(const char* src, int dq, bool exact, bool ode, int stages,
+int user_kernel_create(const char* src, int dq, bool exact, bool ode, int stages, int method,
                        UserKernel** out, std::string* log) {
   *out = nullptr;
   log->clear();
   if (!src || !user_dq_supported(dq) || !stages_supported(stages)) return -1;
+  if (method != 0 && (ode || !split_kicks(method))) return -1;
   Compiled c;
-  if (!compile_cached(src, dq, exact, ode, stages, &c, log)) return -1;
+  if (!compile_cached(src, dq, exact, ode, stages, method, &c, log)) return -1;
   UserKernel* k = new UserKernel();
   k->dq = dq;
   k->exact = exact;
   k->ode = ode;
   k->stages = stages;
-  k->lanes_per_inst = use_lane_kernel(dq) ? 1 : 8;
+  k->method = method;
+  k->lanes_per_inst = (split_kicks(method) || use_lane_kernel(dq)) ? 1 : 8;
   if (hipModuleLoadData(&k->mod, c.code.data()) != hipSuccess ||
       hipModuleGetFunction(&k->fn, k->mod, c.lowered.c_str()) != hipSuccess) {
     user_kernel_free(k);

@@ -24,6 +24,7 @@ IRKGL16_OK, IRKGL16_EINVAL, IRKGL16_ENOMEM, IRKGL16_EDEVICE = 0, -1, -2, -3
 IRKGL16_ENONFINITE, IRKGL16_ENOCONV = -4, 1
 IRKGL16_KEPLER, IRKGL16_GRAVITY, IRKGL16_CHAIN = 0, 1, 2
 IRKGL16_DEVICE_PTRS, IRKGL16_PLAIN, IRKGL16_REPRODUCIBLE, IRKGL16_GRAPH = 1, 2, 4, 8
+IRKGL16_STRANG, IRKGL16_SUZ90 = 1, 2  # irkgl16_options.method: explicit baselines
 
 EXPORTED = ["irkgl16_create", "irkgl16_integrate", "irkgl16_last_stats", "irkgl16_destroy",
             "irkgl16_strerror", "irkgl16_server_create", "irkgl16_submit", "irkgl16_poll",
@@ -39,7 +40,7 @@ class irkgl16_problem(C.Structure):
 
 class irkgl16_options(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("record_iters", C.c_int32), ("flags", C.c_uint32),
-                ("stages", C.c_int32)]
+                ("stages", C.c_int32), ("method", C.c_int32)]
 
 
 class irkgl16_stats(C.Structure):
@@ -159,14 +160,15 @@ def irkgl16_create(problems, max_iter=0, record_iters=False, flags=0, stream=Non
 
 
 def irkgl16_create_user(force_src, dq, params, n_inst, max_iter=0, record_iters=False, flags=0,
-                        stream=None, stages=0):
+                        stream=None, stages=0, method=0):
     """Context for n_inst instances of a force given as device source.
 
     params: array of shape (n_inst, n_params) (or None for no parameters).
     """
     prm = None if params is None else np.ascontiguousarray(params, np.float64).reshape(n_inst, -1)
     n_params = 0 if prm is None else prm.shape[1]
-    opt = irkgl16_options(int(max_iter), int(bool(record_iters)), int(flags), int(stages))
+    opt = irkgl16_options(int(max_iter), int(bool(record_iters)), int(flags), int(stages),
+                          int(method))
     if stream is not None and hasattr(stream, "cuda_stream"):
         stream = stream.cuda_stream
     ctx = C.c_void_p()
@@ -243,7 +245,7 @@ class Integrator:
 
     @classmethod
     def user(cls, force_src, dq, n_inst, params=None, max_iter=0, record_iters=False, flags=0,
-             stream=None, stages=0):
+             stream=None, stages=0, method=0):
         """Integrator of n_inst instances of a user force (irkgl16_create_user)."""
         self = cls.__new__(cls)
         self.problems = [dict(kind=-1, n=1, d=int(dq))] * int(n_inst)
@@ -252,7 +254,7 @@ class Integrator:
         self.record_iters = bool(record_iters)
         self.ctx = None
         self.ctx = irkgl16_create_user(force_src, dq, params, n_inst, max_iter, record_iters,
-                                       flags, stream, stages)
+                                       flags, stream, stages, method)
         return self
 
     @classmethod

@@ -221,3 +221,34 @@ def test_product_tables_of_every_stage_count_match_oracle():
         want = np.concatenate([fp["c"], fp["b"], np.ravel(fp["eta"]), np.ravel(fp["mu"]),
                                np.ravel(fp["nu"])])
         assert np.array_equal(flat[:2 * s + 3 * s * s], want), s
+
+
+def test_explicit_method_validation():
+    """Explicit baselines only for second-order user contexts with s = 8;
+    rejected before any device work."""
+    from paper_2511_03655_amd import user_forces as UF
+    L = K.lib()
+    arr = (K.irkgl16_problem * 1)()
+    arr[0] = K.irkgl16_problem(0, 1, 2, None, None, 1.0, 0.0, 0.0)
+    ctx = C.c_void_p()
+    opt = K.irkgl16_options(0, 0, 0, 0, K.IRKGL16_STRANG)
+    assert L.irkgl16_create(C.byref(ctx), arr, 1, C.byref(opt), None) == K.IRKGL16_EINVAL
+    for kw in (dict(method=3), dict(method=-1), dict(method=K.IRKGL16_SUZ90, stages=4)):
+        with pytest.raises(K.IRKGL16Error) as e:
+            K.irkgl16_create_user(UF.HENON_HEILES, 2, None, 2, **kw)
+        assert e.value.code == K.IRKGL16_EINVAL, kw
+    opt = K.irkgl16_options(0, 0, 0, 0, K.IRKGL16_SUZ90)
+    assert L.irkgl16_create_ode(C.byref(ctx), UF.OSC_RHS.encode(), 2, 0, None, 1, C.byref(opt),
+                                None) == K.IRKGL16_EINVAL
+
+
+def test_product_splitting_tables_match_oracle():
+    """The library's explicit-method tables (its own root finding for
+    Suzuki's coefficient) equal the oracle's closed-form ones."""
+    from oracle import tableau as T
+    src = open(os.path.join(ROOT, "paper_2511_03655_amd", "csrc", "irkgl16_coeffs.h")).read()
+    co = T.splitting_coefficients()
+    for nm, key in (("Strang", "STRANG"), ("Suz90", "SUZ90")):
+        m = re.search(rf"kSplit{nm}\[\d+\] = \{{(.*?)\}};", src, re.S)
+        flat = [float.fromhex(x) for x in re.findall(r"-?0x[0-9a-fp.+-]+", m.group(1))]
+        assert flat == co[key]["a"] + co[key]["b"] + co[key]["c"], nm
