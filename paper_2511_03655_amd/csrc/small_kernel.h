@@ -253,6 +253,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
     // ---- one step, all live slots in lockstep
     const bool live = (inst >= 0) && (M.step < M.target);
     const double h = M.h;
+    // This lane's stage coefficient and time, fixed for the step (read once:
+    // the index is lane-dependent, so it is a vector load).
+    const int sub_s = sub < S ? sub : S - 1;
+    const double hb_sub = h * T[Tab<S>::B + sub_s];
+    const double t_sub = stage_time(M.step, h, T[Tab<S>::C + sub_s]);
     bool conv = !live;
 #pragma unroll
     for (int cc = 0; cc < CPL; ++cc) mind[cc] = prv[cc] = __builtin_inf();
@@ -270,9 +275,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
       }
       __syncthreads();
       if (!conv && sub < S)  // lanes past the stage count idle in this role
-        stage_increment<KIND, NB, D, EXACT, S>(Xs, sub, M.m, M.eps2, h * T[Tab<S>::B + sub], M.G,
+        stage_increment<KIND, NB, D, EXACT, S>(Xs, sub, M.m, M.eps2, hb_sub, M.G,
                                                M.prm_off >= 0 ? a.params + M.prm_off : nullptr,
-                                               stage_time(M.step, h, T[Tab<S>::C + sub]));
+                                               t_sub);
       __syncthreads();
       bool ok = true, bad = false;
       if (!conv) {
