@@ -13,7 +13,9 @@ enqueued on the stream given at creation and the caller synchronizes.
 from __future__ import annotations
 
 import ctypes as C
+import importlib.util
 import os
+import sys
 
 import numpy as np
 
@@ -76,6 +78,13 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run paper_2511_03655_amd/build.py")
+        # torch ships its own HIP runtime and asks for it under a name that a
+        # runtime loaded for this library does not answer to: loading this
+        # library first leaves two HIP runtimes in the process, and the second
+        # (torch's) finds no device.  Loaded after torch, this library binds to
+        # torch's copy, so one runtime serves both.
+        if "torch" not in sys.modules and importlib.util.find_spec("torch") is not None:
+            import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         dp, i64p = C.POINTER(C.c_double), C.POINTER(C.c_int64)
         L.irkgl16_create.argtypes = [C.POINTER(C.c_void_p), C.POINTER(irkgl16_problem), C.c_int32,
@@ -274,9 +283,10 @@ class Integrator:
         return self
 
     def close(self):
-        if getattr(self, "ctx", None):
-            irkgl16_destroy(self.ctx)
+        ctx = getattr(self, "ctx", None)
+        if ctx and _lib is not None:
             self.ctx = None
+            _lib.irkgl16_destroy(ctx)
 
     __del__ = close
 

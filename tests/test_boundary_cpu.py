@@ -252,3 +252,21 @@ def test_product_splitting_tables_match_oracle():
         m = re.search(rf"kSplit{nm}\[\d+\] = \{{(.*?)\}};", src, re.S)
         flat = [float.fromhex(x) for x in re.findall(r"-?0x[0-9a-fp.+-]+", m.group(1))]
         assert flat == co[key]["a"] + co[key]["b"] + co[key]["c"], nm
+
+
+def test_one_hip_runtime_with_torch():
+    """Loading the library in a fresh process and then importing torch leaves
+    a single HIP runtime mapped (torch's bundled copy would otherwise come in
+    beside the one this library links, and find no device)."""
+    import subprocess
+    import sys
+    code = ("import re; from paper_2511_03655_amd import irkgl16 as K; K.lib(); import torch; "
+            "m = open('/proc/self/maps').read(); "
+            "print(sorted(set(re.findall(r'\\S*libamdhip64\\S*', m))))")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                         cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                         timeout=300)
+    assert out.returncode == 0, out.stderr
+    import ast
+    paths = ast.literal_eval(out.stdout.strip().splitlines()[-1])
+    assert len(paths) == 1, paths
