@@ -129,7 +129,15 @@ struct LaunchArgs {
   int32_t* queue_head;   // atomic work counter (zeroed by the prepare kernel)
   int64_t step_budget;   // max steps per instance in this launch (<= 0: all)
   int32_t exact;         // reproducible arithmetic (see the EXACT policies below)
+  // If set, the queue length in device memory (written by an earlier kernel
+  // of the same call); replaces queue_len for launches with a queue counter.
+  const int32_t* queue_len_dev = nullptr;
 };
+
+// Length of a launch's class queue.
+__device__ __forceinline__ int32_t queue_length(const LaunchArgs& a) {
+  return a.queue_len_dev ? *a.queue_len_dev : a.queue_len;
+}
 
 // One-instance-per-lane kernels: lanes without an instance (inst < 0) take the
 // next ones from the class queue, one atomic per wavefront for all of them
@@ -150,12 +158,12 @@ __device__ __forceinline__ bool take_lane_instance(const LaunchArgs& a, int lane
         base = __shfl(base, leader, 64);
         if (inst < 0) {
           const int idx = base + __popcll(need & ((1ull << lane) - 1ull));
-          if (idx < a.queue_len) {
+          if (idx < queue_length(a)) {
             inst = a.queue[idx];
             fresh = true;
           }
         }
-        if (base + cnt >= a.queue_len) qdone = true;
+        if (base + cnt >= queue_length(a)) qdone = true;
       }
     }
   } else if (!taken) {
@@ -228,6 +236,36 @@ __device__ __forceinline__ bool track_finite(double acc, double nf) {
   return finite(acc) && nf == 0.0;
 }
 
+// A double taken from another lane of the wavefront by a DPP pattern (CTRL:
+// 0xB1 = lane xor 1 and 0x4E = lane xor 2 within a quad, 0x141 = mirror
+// within each 8-lane half row).  Every lane of the group must be active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_double(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Combines a tracked maximum (max_track) over aligned groups of G = 2, 4 or 8
+// lanes: the maximum is exact in any order and a non-finite mark anywhere
+// reaches every lane of the group.
+template <int G>
+__device__ __forceinline__ void group_track(double& acc, double& nf) {
+  static_assert(G == 1 || G == 2 || G == 4 || G == 8, "group of 1, 2, 4 or 8 lanes");
+  if constexpr (G >= 2) {
+    acc = fmax(acc, dpp_double<0xB1>(acc));
+    nf = nf + dpp_double<0xB1>(nf);
+  }
+  if constexpr (G >= 4) {
+    acc = fmax(acc, dpp_double<0x4E>(acc));
+    nf = nf + dpp_double<0x4E>(nf);
+  }
+  if constexpr (G >= 8) {  // quads are uniform now: the mirror pairs quad 0 with quad 1
+    acc = fmax(acc, dpp_double<0x141>(acc));
+    nf = nf + dpp_double<0x141>(nf);
+  }
+}
+
 
 // ---------------------------------------------------------------------------
 // Arithmetic policies.  EXACT = false: fused multiply-adds and the refined
@@ -241,8 +279,8 @@ __device__ __forceinline__ bool track_finite(double acc, double nf) {
 // length of the stage arrays; 8 for IRKGL16) and read the table of Tab<S>.
 
 // sum_j w[off + j] x[j], j = 0..S-1
-template <bool EXACT, int S>
-__device__ __forceinline__ double row_dot(ConstTab w, int off, const double (&x)[S]) {
+template <bool EXACT, int S, class W>
+__device__ __forceinline__ double row_dot(W w, int off, const double (&x)[S]) {
   if constexpr (EXACT) {
     double s = 0.0;
 #pragma unroll
@@ -258,8 +296,8 @@ __device__ __forceinline__ double row_dot(ConstTab w, int off, const double (&x)
 
 // Stage value q + h (c_s v + sum_j M_sj R_j) with M = eta (eqs. Qi2 /
 // IRK_FP2), or M = K for the folded initial guess.
-template <bool EXACT, int S>
-__device__ __forceinline__ double stage_value(ConstTab w, int s, double q, double v, double h,
+template <bool EXACT, int S, class W>
+__device__ __forceinline__ double stage_value(W w, int s, double q, double v, double h,
                                               const double (&R)[S], int mat = Tab<S>::Eta) {
   if constexpr (EXACT) {
     return q + h * (w[Tab<S>::C + s] * v + row_dot<true>(w, mat + s * S, R));
@@ -374,8 +412,8 @@ __device__ __forceinline__ void initial_guess(ConstTab T, const double (&qh)[CPL
 // ---- first-order (mu) form, eqs. Yi2 / yn2, IRK_init / IRK_FP
 // Stage value Y_s = y + sum_j M_sj L_j with M = mu (iteration) or nu (initial
 // guess from the previous step's increments).
-template <bool EXACT, int S>
-__device__ __forceinline__ double ode_stage_value(ConstTab w, int s, double y, const double (&L)[S],
+template <bool EXACT, int S, class W>
+__device__ __forceinline__ double ode_stage_value(W w, int s, double y, const double (&L)[S],
                                                   int mat) {
   return y + row_dot<EXACT>(w, mat + s * S, L);
 }
@@ -427,9 +465,28 @@ __device__ __forceinline__ void form_guess(ConstTab T, const double (&qh)[CPL],
   }
 }
 
+// Initial guess of one stage s of one component: the same operations, in the
+// same order, as form_guess for that stage (the table may be indexed with a
+// lane-dependent s).
+template <int KIND, bool EXACT, int S, class W>
+__device__ __forceinline__ double guess_stage(W T, int s, double q, double v,
+                                              const double (&Rp)[S], double h) {
+  if constexpr (KIND == kUserOde) {
+    return ode_stage_value<EXACT>(T, s, q, Rp, Tab<S>::Nu);
+  } else if constexpr (!EXACT) {
+    return stage_value<false>(T, s, q, v, h, Rp, Tab<S>::K);
+  } else {
+    double L0[S];
+#pragma unroll
+    for (int j = 0; j < S; ++j)
+      L0[j] = (h * T[Tab<S>::B + j]) * (v + row_dot<true>(T, Tab<S>::Nu + j * S, Rp));
+    return q + row_dot<true>(T, Tab<S>::Mu + s * S, L0);
+  }
+}
+
 // New stage value of one component from the current increments.
-template <int KIND, bool EXACT, int S>
-__device__ __forceinline__ double form_stage_value(ConstTab r, int s, double q, double v, double h,
+template <int KIND, bool EXACT, int S, class W>
+__device__ __forceinline__ double form_stage_value(W r, int s, double q, double v, double h,
                                                    const double (&R)[S]) {
   if constexpr (KIND == kUserOde) {
     return ode_stage_value<EXACT>(r, s, q, R, Tab<S>::Mu);

@@ -130,7 +130,7 @@ __global__ __launch_bounds__(8 * NPMAX) void stage_kernel(LaunchArgs a, int np) 
       int id = -1;
       if (a.queue_head) {
         const int idx = atomicAdd(a.queue_head, 1);
-        if (idx < a.queue_len) id = a.queue[idx];
+        if (idx < queue_length(a)) id = a.queue[idx];
       } else if (round == 0 && (int)blockIdx.x < a.queue_len) {
         id = a.queue[blockIdx.x];
       }

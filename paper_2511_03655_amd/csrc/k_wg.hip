@@ -134,7 +134,7 @@ __global__ __launch_bounds__(MAXT) void wg_kernel(LaunchArgs a, int S) {
     if (u == 0 && slot_inst[slot] < 0 && !*qdone) {
       if (a.queue_head) {
         const int idx = atomicAdd(a.queue_head, 1);
-        if (idx < a.queue_len)
+        if (idx < queue_length(a))
           slot_inst[slot] = a.queue[idx];
         else
           *qdone = 1;

@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
@@ -107,6 +108,10 @@ struct irkgl16_ctx {
   int64_t total_dq = 0;
 
   DevBuf d_tab, d_desc, d_stat, d_state, d_params, d_queue, d_heads, d_plainq;
+  DevBuf d_queue2, d_prev;  // chunked calls: reordered queues, per-instance counters
+  DevBuf d_qprom, d_counts, d_heads_prom;  // promoted queues, queue lengths, their heads
+  int chunks = 0;            // chunks per call (0: automatic)
+  double promote_k = 5.0;    // promotion threshold, iterations per step (0: never)
   DevBuf d_q0, d_p0, d_qout, d_pout, d_iters, d_large;
   int large_nmax = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -295,6 +300,11 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
   }
   // Launch shapes from the tuning table.
   c->tune = irk::load_tune_table();
+  // Chunks per call of the batched classes (0 or unset: automatic).
+  if (const char* ch = std::getenv("IRKGL16_CHUNKS")) c->chunks = std::max(0, std::atoi(ch));
+  // Iterations per step from which a small-system instance moves to the
+  // stage-parallel kernel for the next chunk (0: never).
+  if (const char* pk = std::getenv("IRKGL16_PROMOTE_K")) c->promote_k = std::max(0.0, std::atof(pk));
   for (auto& kc : c->classes)
     if (kc.cls == irk::kClassWg)
       kc.tune.wg_block = c->tune.get(irk::wg_tune_key(kc.kind, kc.d, kc.size), 0);
@@ -327,6 +337,11 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
       (rc = alloc_try(c->d_state, sizeof(double) * (size_t)std::max<int64_t>(state_off, 1))) ||
       (rc = alloc_try(c->d_params, sizeof(double) * std::max<size_t>(params.size(), 1))) ||
       (rc = alloc_try(c->d_queue, sizeof(int32_t) * std::max<size_t>(queue_len, 1))) ||
+      (rc = alloc_try(c->d_queue2, sizeof(int32_t) * std::max<size_t>(queue_len, 1))) ||
+      (rc = alloc_try(c->d_prev, sizeof(int64_t) * 2 * (size_t)std::max(n_inst, 1))) ||
+      (rc = alloc_try(c->d_qprom, sizeof(int32_t) * std::max<size_t>(queue_len, 1))) ||
+      (rc = alloc_try(c->d_counts, sizeof(int32_t) * 2 * std::max<size_t>(c->classes.size(), 1))) ||
+      (rc = alloc_try(c->d_heads_prom, sizeof(int32_t) * std::max<size_t>(c->classes.size(), 1))) ||
       (rc = alloc_try(c->d_plainq, sizeof(int32_t) * std::max<size_t>(plainq.size(), 1))) ||
       (rc = alloc_try(c->d_heads, sizeof(int32_t) * std::max<size_t>(c->classes.size(), 1))))
     return fail(rc);
@@ -370,6 +385,16 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
     return fail(IRKGL16_EDEVICE);
   *out = c;
   return IRKGL16_OK;
+}
+
+// Chunks per call for the batched classes: `fixed` if positive, else one
+// chunk per 64 steps of the longest integration, at most 16.
+static int chunk_count(int fixed, int64_t max_steps) {
+  constexpr int64_t kMinChunkSteps = 64;
+  constexpr int kMaxChunks = 16;
+  if (max_steps <= 0) return 1;
+  if (fixed > 0) return (int)std::min<int64_t>(fixed, max_steps);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxChunks, max_steps / kMinChunkSteps));
 }
 
 static irk::LaunchArgs base_args(irkgl16_ctx* c, double* qout, double* pout) {
@@ -566,7 +591,7 @@ static int integrate_impl(irkgl16_ctx* c, const double* q0, const double* p0, co
   HIP_TRY(irk::launch_prepare(c->d_desc.as<irk::InstDesc>(), c->d_stat.as<irk::InstStat>(),
                               c->d_state.as<double>(), c->d_params.as<double>(), dq0, dp0, dqo,
                               dpo, c->record ? c->d_iters.as<uint8_t>() : nullptr,
-                              c->d_heads.as<int32_t>(), (int)c->classes.size(), n, c->stream));
+                              c->d_heads.as<int32_t>(), (int)c->classes.size(), n, c->stream, nullptr, c->d_prev.as<int64_t>()));
   irk::LaunchArgs a = base_args(c, dqo, dpo);
   if ((c->flags & IRKGL16_PLAIN) && (c->flags & IRKGL16_GRAPH)) {
     // Plain form with the step loop in a graph: one step's launches (one per
@@ -588,25 +613,90 @@ static int integrate_impl(irkgl16_ctx* c, const double* q0, const double* p0, co
     // The whole-GPU class (cooperative launches) runs alone on the main
     // stream after the others; the batched classes run concurrently, one
     // auxiliary stream per class (round robin), joined back into the stream.
-    HIP_TRY(hipEventRecord(c->ev_fork, c->stream));
-    std::vector<char> used(c->aux.size(), 0);
-    int slot = 0;
-    for (size_t k = 0; k < c->classes.size(); ++k) {
-      const auto& kc = c->classes[k];
-      if (kc.cls == irk::kClassLarge) continue;
-      irk::LaunchArgs ca = a;
-      ca.queue = c->d_queue.as<int32_t>() + kc.queue_off;
-      ca.queue_len = (int32_t)kc.ids.size();
-      ca.queue_head = c->d_heads.as<int32_t>() + k;
-      const int j = slot++ % (int)c->aux.size();
-      if (!used[j]) HIP_TRY(hipStreamWaitEvent(c->aux[j], c->ev_fork, 0));
-      used[j] = 1;
-      HIP_TRY(launch_class(c, kc, ca, (int)kc.ids.size(), c->aux[j]));
-    }
-    for (size_t j = 0; j < c->aux.size(); ++j) {
-      if (!used[j]) continue;
-      HIP_TRY(hipEventRecord(c->aux_done[j], c->aux[j]));
-      HIP_TRY(hipStreamWaitEvent(c->stream, c->aux_done[j], 0));
+    // A long call runs the batched classes in chunks (a step budget per
+    // launch); between chunks each class queue is reordered so that the
+    // instances with the most estimated work left start first -- an instance
+    // whose fixed-point iteration has slowed down would otherwise be pulled
+    // late and finish long after the rest.  Every launch resumes each
+    // instance's state exactly, so chunking never changes results.
+    int64_t max_steps = 0;
+    for (const auto& kc : c->classes)
+      if (kc.cls != irk::kClassLarge)
+        for (int32_t id : kc.ids) max_steps = std::max(max_steps, nsteps[id]);
+    const int nchunks = chunk_count(c->chunks, max_steps);
+    const int64_t budget = nchunks > 1 ? (max_steps + nchunks - 1) / nchunks : 0;
+    // A gravitational small-system instance whose last chunk needed many
+    // iterations per step runs its next chunk on the stage-parallel kernel
+    // (a wavefront per system instead of 8 lanes: a much shorter iteration),
+    // concurrently with the rest; the two kernels compute the same arithmetic,
+    // so results do not depend on which one ran a step.
+    auto promotable = [&](const KernelClass& kc) {
+      return c->promote_k > 0.0 && kc.cls == irk::kClassSmall && kc.kind == irk::kGravity &&
+             irk::stage_class_supported(kc.kind, kc.size, kc.d);
+    };
+    // The first chunk takes each class's full member list (d_queue, never
+    // written during the call); later chunks take the order kernel's normal
+    // queue (d_queue2, built from the full member list each time) and, for
+    // promotable classes, its promoted queue (d_qprom).
+    const int32_t* members = c->d_queue.as<int32_t>();
+    int32_t* qnorm = c->d_queue2.as<int32_t>();
+    int32_t* counts = c->d_counts.as<int32_t>();
+    for (int ch = 0; ch < nchunks && max_steps > 0; ++ch) {
+      HIP_TRY(hipEventRecord(c->ev_fork, c->stream));
+      std::vector<char> used(c->aux.size(), 0);
+      int slot = 0;
+      auto on_aux = [&](const KernelClass& kc, const irk::LaunchArgs& la, int n_items) -> hipError_t {
+        const int j = slot++ % (int)c->aux.size();
+        if (!used[j]) {
+          const hipError_t e = hipStreamWaitEvent(c->aux[j], c->ev_fork, 0);
+          if (e != hipSuccess) return e;
+        }
+        used[j] = 1;
+        return launch_class(c, kc, la, n_items, c->aux[j]);
+      };
+      for (size_t k = 0; k < c->classes.size(); ++k) {
+        const auto& kc = c->classes[k];
+        if (kc.cls == irk::kClassLarge) continue;
+        irk::LaunchArgs ca = a;
+        ca.queue = (ch == 0 ? members : qnorm) + kc.queue_off;
+        ca.queue_len = (int32_t)kc.ids.size();
+        ca.queue_head = c->d_heads.as<int32_t>() + k;
+        ca.step_budget = budget;
+        if (ch > 0) ca.queue_len_dev = counts + 2 * k;  // set by the order kernel
+        HIP_TRY(on_aux(kc, ca, (int)kc.ids.size()));
+        if (ch > 0 && promotable(kc)) {
+          KernelClass ks = kc;
+          ks.cls = irk::kClassStage;
+          ks.size = irk::stage_np(kc.size);
+          irk::LaunchArgs pa = ca;
+          pa.queue = c->d_qprom.as<int32_t>() + kc.queue_off;
+          pa.queue_len_dev = counts + 2 * k + 1;
+          pa.queue_head = c->d_heads_prom.as<int32_t>() + k;
+          HIP_TRY(on_aux(ks, pa, std::min((int)kc.ids.size(), c->num_cus)));
+        }
+      }
+      for (size_t j = 0; j < c->aux.size(); ++j) {
+        if (!used[j]) continue;
+        HIP_TRY(hipEventRecord(c->aux_done[j], c->aux[j]));
+        HIP_TRY(hipStreamWaitEvent(c->stream, c->aux_done[j], 0));
+      }
+      if (ch + 1 == nchunks) {
+        if (nchunks > 1)
+          HIP_TRY(irk::launch_nan_fill(c->d_desc.as<irk::InstDesc>(), c->d_stat.as<irk::InstStat>(),
+                                       dqo, dpo, n, c->stream));
+        break;
+      }
+      for (size_t k = 0; k < c->classes.size(); ++k) {
+        const auto& kc = c->classes[k];
+        if (kc.cls == irk::kClassLarge) continue;
+        HIP_TRY(irk::launch_order(members + kc.queue_off, qnorm + kc.queue_off,
+                                  (int32_t)kc.ids.size(), c->d_desc.as<irk::InstDesc>(),
+                                  c->d_stat.as<irk::InstStat>(), c->d_prev.as<int64_t>(),
+                                  c->d_heads.as<int32_t>() + k,
+                                  c->d_qprom.as<int32_t>() + kc.queue_off, counts + 2 * k,
+                                  c->d_heads_prom.as<int32_t>() + k,
+                                  promotable(kc) ? c->promote_k : 0.0, c->stream));
+      }
     }
     for (size_t k = 0; k < c->classes.size(); ++k) {
       const auto& kc = c->classes[k];

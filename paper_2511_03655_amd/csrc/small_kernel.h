@@ -152,15 +152,27 @@ struct SlotMeta {
   double h, G, eps2;
   double m[NB];
   int64_t prm_off;                   // user-force parameters in the params arena, or -1
-  int32_t inst, maxk, kslot, flags;  // flags: 1 dead, 2 capped
+  int32_t inst, maxk;
 };
 
 template <int KIND, int NB, int D, bool EXACT, int S = kS>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void small_kernel(LaunchArgs a) {
   constexpr int DQ = NB * D;
-  constexpr int CPL = (DQ + kSlot - 1) / kSlot;  // components owned per lane
+  // Tail split: when Dq = 8 m + t with m >= 1 and t = 1, 2 or 4 (and one lane
+  // per stage), the t components left after m full rounds are spread over
+  // the slot by stage -- 8 / t lanes per tail component, t stages per lane --
+  // instead of a last round in which 8 - t lanes would idle.  The lanes of a
+  // tail group combine their increment norms with DPP.
+  constexpr int NFULL = DQ / kSlot;
+  constexpr int TAIL = DQ - NFULL * kSlot;
+  constexpr bool SPLIT = (S == kSlot) && NFULL >= 1 && (TAIL == 1 || TAIL == 2 || TAIL == 4);
+  constexpr int CPL = SPLIT ? NFULL : (DQ + kSlot - 1) / kSlot;  // components owned per lane
+  constexpr int TG = SPLIT ? kSlot / TAIL : 1;  // lanes per tail component
+  constexpr int TSL = SPLIT ? TAIL : 1;         // tail stages per lane
   constexpr int TS = SmallTile<DQ, S>::kStride;
   __shared__ double X[8 * TS];
+  // Coefficient table for rows picked by a lane-dependent stage (tail split).
+  __shared__ double TabL[SPLIT ? Tab<S>::Size : 1];
   __shared__ SlotMeta<NB> meta[8];
   __shared__ int32_t slot_inst[8];
   __shared__ int32_t qdone;
@@ -177,11 +189,35 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
   auto comp = [&](int cc) { return sub + kSlot * cc; };
   auto owns = [&](int cc) { return sub + kSlot * cc < DQ; };
   auto cidx = [&](int cc) { return (sub + kSlot * cc < DQ) ? sub + kSlot * cc : DQ - 1; };
+  // Tail split: this lane's tail component and its first stage.
+  const int tcomp = NFULL * kSlot + sub / TG;
+  const int tst0 = (sub % TG) * TSL;
+  const bool tlead = (sub % TG) == 0;  // writes the tail component's outputs
 
   int inst = -1;
   double qh[CPL] = {}, ql[CPL] = {}, vh[CPL] = {}, vl[CPL] = {}, mind[CPL] = {}, prv[CPL] = {};
   double Qc[CPL][S] = {};
+  double tqh = 0.0, tql = 0.0, tvh = 0.0, tvl = 0.0, tmind = 0.0, tprv = 0.0;
+  double tQ[TSL] = {};
 
+  // Per step: iteration count, stopping-rule history, and this lane's stage
+  // weight h b_sub and time t_sub (lane-dependent index: a vector load, once
+  // per step).
+  int k = 0;
+  double hb_sub = 0.0, t_sub = 0.0;
+  const int sub_s = sub < S ? sub : S - 1;
+  auto begin_step = [&](int64_t step) {
+    k = 0;
+#pragma unroll
+    for (int cc = 0; cc < CPL; ++cc) mind[cc] = prv[cc] = __builtin_inf();
+    tmind = tprv = __builtin_inf();
+    hb_sub = M.h * T[Tab<S>::B + sub_s];
+    t_sub = stage_time(step, M.h, T[Tab<S>::C + sub_s]);
+  };
+
+  if constexpr (SPLIT) {
+    for (int i = lane; i < Tab<S>::Size; i += 64) TabL[i] = a.tab[i];
+  }
   if (lane == 0) qdone = 0;
   if (lane < 8) {
     slot_inst[lane] = -1;
@@ -193,7 +229,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
     if (lane < 8 && slot_inst[lane] < 0 && !qdone) {
       if (a.queue_head) {
         const int idx = atomicAdd(a.queue_head, 1);
-        if (idx < a.queue_len)
+        if (idx < queue_length(a))
           slot_inst[lane] = a.queue[idx];
         else
           qdone = 1;
@@ -233,8 +269,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
       for (int b = 0; b < NB; ++b) M.m[b] = (dsc.mass_off >= 0) ? a.params[dsc.mass_off + b] : 1.0;
     }
     __syncthreads();
-    if (fresh) {  // component state of the new instance
-      inst = cur;
+    if (fresh) inst = cur;
+    if (fresh && M.step < M.target) {  // component state of the new instance
       const double* St = a.state + M.state_off;
       double Rp[CPL][S];
 #pragma unroll
@@ -248,85 +284,112 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
         for (int s = 0; s < S; ++s) Rp[cc][s] = St[4 * DQ + c * S + s];
       }
       form_guess<KIND, CPL, EXACT>(T, qh, vh, Rp, M.h, Qc);
+      if constexpr (SPLIT) {
+        tqh = St[tcomp];
+        tql = St[DQ + tcomp];
+        tvh = St[2 * DQ + tcomp];
+        tvl = St[3 * DQ + tcomp];
+        double tRp[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) tRp[s] = St[4 * DQ + tcomp * S + s];
+#pragma unroll
+        for (int u = 0; u < TSL; ++u)
+          tQ[u] = guess_stage<KIND, EXACT>(TabL, tst0 + u, tqh, tvh, tRp, M.h);
+      }
     }
 
-    // ---- one step, all live slots in lockstep
+    // ---- one fixed-point iteration for every live slot.  A slot whose
+    // instance has converged finishes its step in the same pass and starts
+    // the next one, so no slot waits for a slower one (a slow instance costs
+    // only its own slot's throughput).
     const bool live = (inst >= 0) && (M.step < M.target);
     const double h = M.h;
-    // This lane's stage coefficient and time, fixed for the step (read once:
-    // the index is lane-dependent, so it is a vector load).
-    const int sub_s = sub < S ? sub : S - 1;
-    const double hb_sub = h * T[Tab<S>::B + sub_s];
-    const double t_sub = stage_time(M.step, h, T[Tab<S>::C + sub_s]);
-    bool conv = !live;
-#pragma unroll
-    for (int cc = 0; cc < CPL; ++cc) mind[cc] = prv[cc] = __builtin_inf();
-    int k = 0;
-    while (__ballot(!conv) != 0) {
+    if (fresh) begin_step(M.step);
+    if (live) {
       ++k;
-      if (!conv) {
 #pragma unroll
-        for (int cc = 0; cc < CPL; ++cc) {
-          if (owns(cc)) {
+      for (int cc = 0; cc < CPL; ++cc) {
+        if (owns(cc)) {
 #pragma unroll
-            for (int s = 0; s < S; ++s) Xs[comp(cc) * S + s] = Qc[cc][s];
-          }
+          for (int s = 0; s < S; ++s) Xs[comp(cc) * S + s] = Qc[cc][s];
         }
       }
-      __syncthreads();
-      if (!conv && sub < S)  // lanes past the stage count idle in this role
-        stage_increment<KIND, NB, D, EXACT, S>(Xs, sub, M.m, M.eps2, hb_sub, M.G,
-                                               M.prm_off >= 0 ? a.params + M.prm_off : nullptr,
-                                               t_sub);
-      __syncthreads();
-      bool ok = true, bad = false;
-      if (!conv) {
-        double R[CPL][S], dmax[CPL], nf[CPL];
+      if constexpr (SPLIT) {
 #pragma unroll
-        for (int cc = 0; cc < CPL; ++cc) {
-          dmax[cc] = 0.0;
-          nf[cc] = 0.0;
-#pragma unroll
-          for (int s = 0; s < S; ++s) R[cc][s] = Xs[cidx(cc) * S + s];
-        }
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-          const ConstTab r = row_tab(T);
-#pragma unroll
-          for (int cc = 0; cc < CPL; ++cc) {
-            const double qn = form_stage_value<KIND, EXACT>(r, s, qh[cc], vh[cc], h, R[cc]);
-            max_track(dmax[cc], nf[cc], fabs(qn - Qc[cc][s]));
-            Qc[cc][s] = qn;
-          }
-        }
-#pragma unroll
-        for (int cc = 0; cc < CPL; ++cc) {
-          if (owns(cc)) {
-            bad |= !track_finite(dmax[cc], nf[cc]);
-            ok &= stop_component(dmax[cc], mind[cc], prv[cc]);
-          }
-        }
-      }
-      const uint64_t okm = __ballot(ok);
-      const uint64_t badm = __ballot(bad);
-      const bool slot_ok = (okm & smask) == smask;
-      const bool slot_bad = (badm & smask) != 0;
-      if (!conv && (slot_ok || slot_bad || k >= a.max_iter)) {
-        conv = true;
-        if (sub == 0) {
-          M.kslot = k;
-          M.flags = (slot_bad ? 1 : 0) | ((!slot_ok && !slot_bad) ? 2 : 0);
-        }
+        for (int u = 0; u < TSL; ++u) Xs[tcomp * S + tst0 + u] = tQ[u];
       }
     }
     __syncthreads();
-
-    // ---- end of step: compensated update, output, next initial guess
-    bool release = (inst >= 0) && !live;
+    if (live && sub < S)  // lanes past the stage count idle in this role
+      stage_increment<KIND, NB, D, EXACT, S>(Xs, sub, M.m, M.eps2, hb_sub, M.G,
+                                             M.prm_off >= 0 ? a.params + M.prm_off : nullptr,
+                                             t_sub);
+    __syncthreads();
+    bool ok = true, bad = false;
     if (live) {
-      const int kslot = M.kslot;
+      double R[CPL][S], dmax[CPL], nf[CPL];
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc) {
+        dmax[cc] = 0.0;
+        nf[cc] = 0.0;
+#pragma unroll
+        for (int s = 0; s < S; ++s) R[cc][s] = Xs[cidx(cc) * S + s];
+      }
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const ConstTab r = row_tab(T);
+#pragma unroll
+        for (int cc = 0; cc < CPL; ++cc) {
+          const double qn = form_stage_value<KIND, EXACT>(r, s, qh[cc], vh[cc], h, R[cc]);
+          max_track(dmax[cc], nf[cc], fabs(qn - Qc[cc][s]));
+          Qc[cc][s] = qn;
+        }
+      }
+#pragma unroll
+      for (int cc = 0; cc < CPL; ++cc) {
+        if (owns(cc)) {
+          bad |= !track_finite(dmax[cc], nf[cc]);
+          ok &= stop_component(dmax[cc], mind[cc], prv[cc]);
+        }
+      }
+      if constexpr (SPLIT) {  // this lane's stages of its tail component
+        double tR[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) tR[s] = Xs[tcomp * S + s];
+        double tdmax = 0.0, tnf = 0.0;
+#pragma unroll
+        for (int u = 0; u < TSL; ++u) {
+          const double qn = form_stage_value<KIND, EXACT>(TabL, tst0 + u, tqh, tvh, h, tR);
+          max_track(tdmax, tnf, fabs(qn - tQ[u]));
+          tQ[u] = qn;
+        }
+        group_track<TG>(tdmax, tnf);
+        bad |= !track_finite(tdmax, tnf);
+        ok &= stop_component(tdmax, tmind, tprv);
+      }
+    }
+    const uint64_t okm = __ballot(ok);
+    const uint64_t badm = __ballot(bad);
+    const bool slot_ok = (okm & smask) == smask;
+    const bool slot_bad = (badm & smask) != 0;
+    const bool done = live && (slot_ok || slot_bad || k >= a.max_iter);
+    // A wavefront holding an instance deep in its fixed-point iteration
+    // (k >= 4 this step; typical steps take 2 or 3) takes issue priority on
+    // its SIMD: the long sequential integrations, which bound the batch's
+    // completion time, then run near their uncontended speed while the
+    // other wavefronts fill the remaining issue slots.
+    if (__ballot(live && k >= 4) != 0)
+      __builtin_amdgcn_s_setprio(2);
+    else
+      __builtin_amdgcn_s_setprio(0);
+
+    // ---- end of the step for the slots that converged: compensated update,
+    // output, next initial guess
+    bool release = (inst >= 0) && !live;
+    if (done) {
+      const int kslot = k;
       const int64_t step0 = M.step, stride = M.stride, out_off = M.out_off;
-      if (M.flags & 1) {  // non-finite: stop this instance, remaining frames NaN
+      if (slot_bad) {  // non-finite: stop this instance, remaining frames NaN
         const int64_t nf = M.target / stride;  // frames of this launch only
         for (int64_t f = step0 / stride + 1; f <= nf; ++f) {
 #pragma unroll
@@ -335,6 +398,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
               a.qout[out_off + f * DQ + comp(cc)] = __builtin_nan("");
               if constexpr (KIND != kUserOde) a.pout[out_off + f * DQ + comp(cc)] = __builtin_nan("");
             }
+          }
+          if (SPLIT && tlead) {
+            a.qout[out_off + f * DQ + tcomp] = __builtin_nan("");
+            if constexpr (KIND != kUserOde) a.pout[out_off + f * DQ + tcomp] = __builtin_nan("");
           }
         }
         if (sub == 0) {
@@ -377,12 +444,41 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
             }
           }
         }
-        if (!last) form_guess<KIND, CPL, EXACT>(T, qh, vh, R, h, Qc);
+        if (!last) {
+          form_guess<KIND, CPL, EXACT>(T, qh, vh, R, h, Qc);
+          begin_step(step);
+        }
+        if constexpr (SPLIT) {  // tail component: update (replicated), outputs, guess
+          double tR[S];
+#pragma unroll
+          for (int s = 0; s < S; ++s) tR[s] = Xs[tcomp * S + s];
+          form_update<KIND, EXACT>(r, tR, h, tqh, tql, tvh, tvl);
+          if (tlead) {
+            if (frame) {
+              const int64_t f = step / stride;
+              a.qout[out_off + f * DQ + tcomp] = tqh;
+              if constexpr (KIND != kUserOde) a.pout[out_off + f * DQ + tcomp] = M.m[tcomp / D] * tvh;
+            }
+            if (last) {
+              St[tcomp] = tqh;
+              St[DQ + tcomp] = tql;
+              St[2 * DQ + tcomp] = tvh;
+              St[3 * DQ + tcomp] = tvl;
+#pragma unroll
+              for (int s = 0; s < S; ++s) St[4 * DQ + tcomp * S + s] = tR[s];
+            }
+          }
+          if (!last) {
+#pragma unroll
+            for (int u = 0; u < TSL; ++u)
+              tQ[u] = guess_stage<KIND, EXACT>(TabL, tst0 + u, tqh, tvh, tR, h);
+          }
+        }
         if (sub == 0) {
           if (M.iters_off >= 0) a.step_iters[M.iters_off + step0] = (uint8_t)kslot;
           M.step = step;
           M.it_sum += kslot;
-          M.nonconv += (M.flags & 2) ? 1 : 0;
+          M.nonconv += slot_ok ? 0 : 1;
           if (kslot > M.maxk) M.maxk = kslot;
           if (last) {
             InstStat st;

@@ -237,3 +237,31 @@ def test_iteration_cap_reports_noconv():
     q, p, st, rc = integ.integrate(c1["q"], c1["p"], c1["h"], 5, 5)
     assert rc == K.IRKGL16_ENOCONV and st["nonconverged_steps"] == 5
     assert np.all(np.isfinite(q))
+
+
+@pytest.mark.parametrize("flags", [0, K.IRKGL16_REPRODUCIBLE])
+@pytest.mark.parametrize("promote_k", ["0", "2.0", "2.2"])
+def test_chunked_and_promoted_runs_are_bit_identical(monkeypatch, flags, promote_k):
+    """A call run in chunks, with slow instances moved to the stage-parallel
+    kernel between chunks (threshold 2.0: nearly all of them; 2.2: a mix;
+    0: none), gives bit-identical frames and iteration counts to one launch
+    per class."""
+    n, steps, stride = 256, 512, 64
+    mass, q0, p0 = W.planetary_arrays(n, 6, seed=77)
+    probs = [dict(kind=K.IRKGL16_GRAVITY, n=6, d=3, G=1.0, eps=0.0, mass=mass[i]) for i in range(n)]
+
+    def run(chunks, pk):
+        monkeypatch.setenv("IRKGL16_CHUNKS", chunks)
+        monkeypatch.setenv("IRKGL16_PROMOTE_K", pk)
+        integ = K.Integrator(probs, flags=flags, record_iters=True)
+        out = integ.integrate(q0.ravel(), p0.ravel(), 1.0, steps, stride)
+        integ.close()
+        return out
+
+    q1, p1, s1, rc1 = run("1", "0")
+    q8, p8, s8, rc8 = run("8", promote_k)
+    assert rc1 == rc8
+    assert np.array_equal(q1, q8) and np.array_equal(p1, p8)
+    assert np.array_equal(s1["step_iters"], s8["step_iters"])
+    assert np.array_equal(s1["inst_iterations"], s8["inst_iterations"])
+    assert np.array_equal(s1["inst_status"], s8["inst_status"])
