@@ -10,9 +10,12 @@ resident in HBM; the library enqueues on the bench's torch stream.
 
 Printed JSON line (rank 0):
   value          instance-steps per second of the batched persistent kernel
-  roofline       FP64 VALU roofline of the integration kernel: algorithmic
-                 flops per launch (per-instance-step formula with the kernel's
-                 own iteration counts) over the HIP-event time of the launch
+  roofline       FP64 VALU roofline of the integration call: algorithmic flops
+                 per call (per-instance-step formula with the kernels' own
+                 iteration counts) over the HIP-event time of the call on its
+                 stream -- all of its kernels: the small-system kernel's
+                 chunks, the stage-parallel kernel's chunks for promoted
+                 instances, the queue-order kernels
   cpu_baseline   the CPU oracle (OpenMP, all host cores) on a bounded sample
   plain          the plain one-launch-per-step-per-instance GPU form on a subset
   accuracy       fraction of instances whose relative energy error between the
@@ -300,8 +303,10 @@ def main():
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": traffic_from_profile(
                          "small_kernel_c2_65536x6body",
-                         ["k_small.hip", "small_kernel.h", "device_common.h", "k_prepare.hip"]),
-                     "kernel": "small_kernel<gravity, 6 bodies, d=3>",
+                         ["k_small.hip", "small_kernel.h", "device_common.h", "k_prepare.hip",
+                          "k_stage.hip", "runtime.hip"]),
+                     "kernel": "integration call: small_kernel<gravity, 6 bodies, d=3> in "
+                               "chunks, stage_kernel for promoted instances, queue-order kernels",
                      "kernel_ms": float(np.mean(kernel_ms)),
                      "algorithmic_flops_per_launch": flops},
         "accuracy": {"gate": "relative energy error first->last frame <= 1e-12",

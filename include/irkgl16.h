@@ -203,7 +203,16 @@ int irkgl16_ode_compile_check(const char *rhs_src, int32_t D, char *log, int64_t
  *         instance became non-finite are NaN.
  * stats: nullable.  In host mode the call returns when outputs are complete;
  * with IRKGL16_DEVICE_PTRS it returns after enqueueing (stats, if given, force a
- * stream synchronization).  Returns the worst status over instances. */
+ * stream synchronization).  Returns the worst status over instances.
+ * Scheduling (never changes results): the batched kernels run in chunks of
+ * ceil(max nsteps / c) steps, c = min(16, max nsteps / 64) (at least 1);
+ * between chunks a device kernel orders each class's work queue by estimated
+ * remaining work (steps left times the iterations per step of the last chunk)
+ * and moves gravitational instances of the few-body class that needed at least
+ * 5 iterations per step to the stage-parallel kernel for the next chunk (both
+ * kernels compute the same arithmetic).  Environment, read by
+ * irkgl16_create*: IRKGL16_CHUNKS = c (a positive integer; fixed chunk count),
+ * IRKGL16_PROMOTE_K = the promotion threshold (0: never). */
 int irkgl16_integrate(irkgl16_ctx *ctx, const double *q0, const double *p0, const double *h,
                       const int64_t *nsteps, const int64_t *out_stride, double *q_out,
                       double *p_out, irkgl16_stats *stats);
