@@ -120,6 +120,7 @@ struct irkgl16_ctx {
   std::vector<hipStream_t> aux;
   std::vector<hipEvent_t> aux_done;
   hipEvent_t ev_fork = nullptr;
+
   std::vector<int32_t> h_queue;
   irk::TuneTable tune;  // launch shapes (read at creation)
   irk::UserKernel* user = nullptr;  // run-time compiled force (irkgl16_create_user)
@@ -173,6 +174,26 @@ struct UserSpec {
   const double* params;  // n_inst x n_params
   bool ode;              // first-order right-hand side f(t, y) (irkgl16_create_ode)
 };
+
+// Chunks per call for a chunked class: `fixed` if positive, else one chunk
+// per 64 steps of its longest integration, at most 16.
+static int chunk_count(int fixed, int64_t max_steps) {
+  constexpr int64_t kMinChunkSteps = 64;
+  constexpr int kMaxChunks = 16;
+  if (max_steps <= 0) return 1;
+  if (fixed > 0) return (int)std::min<int64_t>(fixed, max_steps);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxChunks, max_steps / kMinChunkSteps));
+}
+
+// A gravitational few-body instance whose last chunk needed many iterations
+// per step can run its next chunk on the stage-parallel kernel (a wavefront
+// per system instead of 8 lanes: a much shorter iteration); the two kernels
+// compute the same arithmetic, so results do not depend on which one ran a
+// step.
+static bool promotable(const irkgl16_ctx* c, const KernelClass& kc) {
+  return c->promote_k > 0.0 && kc.cls == irk::kClassSmall && kc.kind == irk::kGravity &&
+         irk::stage_class_supported(kc.kind, kc.size, kc.d);
+}
 
 static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t n_inst,
                        const irkgl16_options* opt, void* hip_stream,
@@ -385,16 +406,6 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
     return fail(IRKGL16_EDEVICE);
   *out = c;
   return IRKGL16_OK;
-}
-
-// Chunks per call for the batched classes: `fixed` if positive, else one
-// chunk per 64 steps of the longest integration, at most 16.
-static int chunk_count(int fixed, int64_t max_steps) {
-  constexpr int64_t kMinChunkSteps = 64;
-  constexpr int kMaxChunks = 16;
-  if (max_steps <= 0) return 1;
-  if (fixed > 0) return (int)std::min<int64_t>(fixed, max_steps);
-  return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxChunks, max_steps / kMinChunkSteps));
 }
 
 static irk::LaunchArgs base_args(irkgl16_ctx* c, double* qout, double* pout) {
@@ -613,91 +624,108 @@ static int integrate_impl(irkgl16_ctx* c, const double* q0, const double* p0, co
     // The whole-GPU class (cooperative launches) runs alone on the main
     // stream after the others; the batched classes run concurrently, one
     // auxiliary stream per class (round robin), joined back into the stream.
-    // A long call runs the batched classes in chunks (a step budget per
-    // launch); between chunks each class queue is reordered so that the
-    // instances with the most estimated work left start first -- an instance
-    // whose fixed-point iteration has slowed down would otherwise be pulled
-    // late and finish long after the rest.  Every launch resumes each
-    // instance's state exactly, so chunking never changes results.
-    int64_t max_steps = 0;
-    for (const auto& kc : c->classes)
-      if (kc.cls != irk::kClassLarge)
-        for (int32_t id : kc.ids) max_steps = std::max(max_steps, nsteps[id]);
-    const int nchunks = chunk_count(c->chunks, max_steps);
-    const int64_t budget = nchunks > 1 ? (max_steps + nchunks - 1) / nchunks : 0;
-    // A gravitational small-system instance whose last chunk needed many
-    // iterations per step runs its next chunk on the stage-parallel kernel
-    // (a wavefront per system instead of 8 lanes: a much shorter iteration),
-    // concurrently with the rest; the two kernels compute the same arithmetic,
-    // so results do not depend on which one ran a step.
-    auto promotable = [&](const KernelClass& kc) {
-      return c->promote_k > 0.0 && kc.cls == irk::kClassSmall && kc.kind == irk::kGravity &&
-             irk::stage_class_supported(kc.kind, kc.size, kc.d);
-    };
-    // The first chunk takes each class's full member list (d_queue, never
-    // written during the call); later chunks take the order kernel's normal
-    // queue (d_queue2, built from the full member list each time) and, for
-    // promotable classes, its promoted queue (d_qprom).
+    // A class that can promote instances (or every batched class when a chunk
+    // count is given) runs in chunks of a step budget; between chunks the
+    // order kernel, on the main stream, sorts its queue by estimated remaining
+    // work and picks the instances for the stage-parallel kernel, whose chunk
+    // runs concurrently on an auxiliary stream that no class uses.  Each chunk
+    // forks the class's stream and its promotion stream from one event, so the
+    // promoted chunk is placed on the GPU as early as the class's own (a
+    // promoted chunk queued behind a full grid of the class's workgroups would
+    // wait for free wave slots), and joins both back before the next order
+    // kernel.  With every auxiliary stream taken by a class, nothing is
+    // promoted or chunked.  An instance whose iteration slows down mid-run is
+    // thus neither pulled late nor left on the slower path.  Every launch
+    // resumes each instance's state exactly, so chunking never changes
+    // results.  The first chunk takes the class's full member list (d_queue,
+    // never written during the call); later chunks take the order kernel's
+    // queues (d_queue2, d_qprom) with their lengths in device memory.
     const int32_t* members = c->d_queue.as<int32_t>();
     int32_t* qnorm = c->d_queue2.as<int32_t>();
     int32_t* counts = c->d_counts.as<int32_t>();
-    for (int ch = 0; ch < nchunks && max_steps > 0; ++ch) {
+    const int naux = (int)c->aux.size();
+    int n_batched = 0;
+    for (const auto& kc : c->classes) n_batched += kc.cls != irk::kClassLarge;
+    struct Plan {
+      int k, j, jp, nch;  // class, its stream, promotion stream (-1: none), chunks
+      int64_t budget;
+    };
+    std::vector<Plan> plans;
+    int slot = 0, prom_slot = 0, max_nch = 1;
+    for (size_t k = 0; k < c->classes.size(); ++k) {
+      const auto& kc = c->classes[k];
+      if (kc.cls == irk::kClassLarge) continue;
+      Plan pl{(int)k, slot++ % naux, -1, 1, 0};
+      const bool prom = promotable(c, kc) && n_batched < naux;
+      if (prom) pl.jp = n_batched + prom_slot++ % (naux - n_batched);
+      int64_t max_steps = 0;
+      for (int32_t id : kc.ids) max_steps = std::max(max_steps, nsteps[id]);
+      pl.nch = (prom || c->chunks > 0) ? chunk_count(c->chunks, max_steps) : 1;
+      pl.budget = pl.nch > 1 ? (max_steps + pl.nch - 1) / pl.nch : 0;
+      max_nch = std::max(max_nch, pl.nch);
+      plans.push_back(pl);
+    }
+    std::vector<char> used(c->aux.size(), 0);
+    auto fork = [&](int j) -> hipError_t {
+      used[j] = 1;
+      return hipStreamWaitEvent(c->aux[j], c->ev_fork, 0);
+    };
+    for (int ch = 0; ch < max_nch; ++ch) {
       HIP_TRY(hipEventRecord(c->ev_fork, c->stream));
-      std::vector<char> used(c->aux.size(), 0);
-      int slot = 0;
-      auto on_aux = [&](const KernelClass& kc, const irk::LaunchArgs& la, int n_items) -> hipError_t {
-        const int j = slot++ % (int)c->aux.size();
-        if (!used[j]) {
-          const hipError_t e = hipStreamWaitEvent(c->aux[j], c->ev_fork, 0);
-          if (e != hipSuccess) return e;
-        }
-        used[j] = 1;
-        return launch_class(c, kc, la, n_items, c->aux[j]);
-      };
-      for (size_t k = 0; k < c->classes.size(); ++k) {
-        const auto& kc = c->classes[k];
-        if (kc.cls == irk::kClassLarge) continue;
+      std::vector<char> step_used(c->aux.size(), 0);
+      for (const Plan& pl : plans) {
+        if (ch >= pl.nch || (ch > 0 && pl.nch == 1)) continue;
+        const auto& kc = c->classes[pl.k];
         irk::LaunchArgs ca = a;
         ca.queue = (ch == 0 ? members : qnorm) + kc.queue_off;
         ca.queue_len = (int32_t)kc.ids.size();
-        ca.queue_head = c->d_heads.as<int32_t>() + k;
-        ca.step_budget = budget;
-        if (ch > 0) ca.queue_len_dev = counts + 2 * k;  // set by the order kernel
-        HIP_TRY(on_aux(kc, ca, (int)kc.ids.size()));
-        if (ch > 0 && promotable(kc)) {
+        ca.queue_head = c->d_heads.as<int32_t>() + pl.k;
+        ca.step_budget = pl.budget;
+        if (ch > 0) ca.queue_len_dev = counts + 2 * pl.k;  // set by the order kernel
+        HIP_TRY(fork(pl.j));
+        if (pl.nch > 1) step_used[pl.j] = 1;
+        HIP_TRY(launch_class(c, kc, ca, (int)kc.ids.size(), c->aux[pl.j]));
+        if (ch > 0 && pl.jp >= 0) {
           KernelClass ks = kc;
           ks.cls = irk::kClassStage;
           ks.size = irk::stage_np(kc.size);
           irk::LaunchArgs pa = ca;
           pa.queue = c->d_qprom.as<int32_t>() + kc.queue_off;
-          pa.queue_len_dev = counts + 2 * k + 1;
-          pa.queue_head = c->d_heads_prom.as<int32_t>() + k;
-          HIP_TRY(on_aux(ks, pa, std::min((int)kc.ids.size(), c->num_cus)));
+          pa.queue_len_dev = counts + 2 * pl.k + 1;
+          pa.queue_head = c->d_heads_prom.as<int32_t>() + pl.k;
+          HIP_TRY(fork(pl.jp));
+          step_used[pl.jp] = 1;
+          HIP_TRY(launch_class(c, ks, pa, std::min((int)kc.ids.size(), c->num_cus),
+                               c->aux[pl.jp]));
         }
       }
-      for (size_t j = 0; j < c->aux.size(); ++j) {
-        if (!used[j]) continue;
+      if (ch + 1 == max_nch) break;
+      // join the chunked classes' streams, then order their next chunk
+      for (int j = 0; j < naux; ++j) {
+        if (!step_used[j]) continue;
         HIP_TRY(hipEventRecord(c->aux_done[j], c->aux[j]));
         HIP_TRY(hipStreamWaitEvent(c->stream, c->aux_done[j], 0));
       }
-      if (ch + 1 == nchunks) {
-        if (nchunks > 1)
-          HIP_TRY(irk::launch_nan_fill(c->d_desc.as<irk::InstDesc>(), c->d_stat.as<irk::InstStat>(),
-                                       dqo, dpo, n, c->stream));
-        break;
-      }
-      for (size_t k = 0; k < c->classes.size(); ++k) {
-        const auto& kc = c->classes[k];
-        if (kc.cls == irk::kClassLarge) continue;
+      for (const Plan& pl : plans) {
+        if (ch + 1 >= pl.nch) continue;
+        const auto& kc = c->classes[pl.k];
         HIP_TRY(irk::launch_order(members + kc.queue_off, qnorm + kc.queue_off,
                                   (int32_t)kc.ids.size(), c->d_desc.as<irk::InstDesc>(),
                                   c->d_stat.as<irk::InstStat>(), c->d_prev.as<int64_t>(),
-                                  c->d_heads.as<int32_t>() + k,
-                                  c->d_qprom.as<int32_t>() + kc.queue_off, counts + 2 * k,
-                                  c->d_heads_prom.as<int32_t>() + k,
-                                  promotable(kc) ? c->promote_k : 0.0, c->stream));
+                                  c->d_heads.as<int32_t>() + pl.k,
+                                  c->d_qprom.as<int32_t>() + kc.queue_off, counts + 2 * pl.k,
+                                  c->d_heads_prom.as<int32_t>() + pl.k,
+                                  pl.jp >= 0 ? c->promote_k : 0.0, c->stream));
       }
     }
+    for (int j = 0; j < naux; ++j) {
+      if (!used[j]) continue;
+      HIP_TRY(hipEventRecord(c->aux_done[j], c->aux[j]));
+      HIP_TRY(hipStreamWaitEvent(c->stream, c->aux_done[j], 0));
+    }
+    if (max_nch > 1)
+      HIP_TRY(irk::launch_nan_fill(c->d_desc.as<irk::InstDesc>(), c->d_stat.as<irk::InstStat>(),
+                                   dqo, dpo, n, c->stream));
     for (size_t k = 0; k < c->classes.size(); ++k) {
       const auto& kc = c->classes[k];
       if (kc.cls != irk::kClassLarge) continue;
