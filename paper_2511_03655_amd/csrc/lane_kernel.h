@@ -62,7 +62,13 @@ __device__ __forceinline__ void lane_increments(ConstTab T, const double (&Q)[DQ
   (void)G;
 }
 
-template <int KIND, int DQ, bool EXACT, int S = kS>
+// INDEP: lanes iterate independently (the default for first-order right-hand
+// sides) or step in lockstep (second order).  Which is faster depends on the
+// cost of the right-hand side against the end-of-step work that independent
+// lanes carry on nearly every pass: the cheap polynomial force of the
+// Henon-Heiles system runs faster in lockstep, the trigonometric right-hand
+// side of the Schwarzschild system independently.
+template <int KIND, int DQ, bool EXACT, int S = kS, bool INDEP = (KIND == kUserOde)>
 __global__ __launch_bounds__(64) void lane_kernel(LaunchArgs a) {
   static_assert(DQ >= 1 && DQ <= kLaneMaxDq, "lane kernel: Dq out of range");
   const int lane = threadIdx.x;
@@ -78,6 +84,107 @@ __global__ __launch_bounds__(64) void lane_kernel(LaunchArgs a) {
   int32_t maxk = 0;
   double qh[DQ], ql[DQ], vh[DQ], vl[DQ], mind[DQ], prv[DQ];
   double Qc[DQ][S], R[DQ][S];
+
+  // Per step: iteration count and stopping-rule history of this lane.
+  int k = 0;
+  auto begin_step = [&]() {
+    k = 0;
+#pragma unroll
+    for (int l = 0; l < DQ; ++l) mind[l] = prv[l] = __builtin_inf();
+  };
+  // One fixed-point iteration of this lane's instance: forces at the stages,
+  // new stage values, increment norm and stopping rule.
+  auto iterate = [&](bool& ok, bool& bad) {
+    lane_increments<KIND, DQ, EXACT, S>(T, Qc, h, G, prm, step, R);
+    double dmax[DQ], nf[DQ];
+#pragma unroll
+    for (int l = 0; l < DQ; ++l) dmax[l] = nf[l] = 0.0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const ConstTab r = row_tab(T);
+#pragma unroll
+      for (int l = 0; l < DQ; ++l) {
+        const double qn = form_stage_value<KIND, EXACT>(r, s, qh[l], vh[l], h, R[l]);
+        max_track(dmax[l], nf[l], fabs(qn - Qc[l][s]));
+        Qc[l][s] = qn;
+      }
+    }
+    ok = true;
+    bad = false;
+#pragma unroll
+    for (int l = 0; l < DQ; ++l) {
+      bad |= !track_finite(dmax[l], nf[l]);
+      ok &= stop_component(dmax[l], mind[l], prv[l]);
+    }
+  };
+  // End of a step after kl iterations (flags: 1 non-finite, 2 capped):
+  // compensated update, output, next initial guess.  Returns whether the
+  // instance is finished for this launch.
+  auto end_step = [&](int kl, int flags) -> bool {
+    bool rel = false;
+    if (flags & 1) {  // non-finite: stop this instance, remaining frames NaN
+      const int64_t nfr = target / stride;  // frames of this launch only
+      for (int64_t f = step / stride + 1; f <= nfr; ++f) {
+#pragma unroll
+        for (int l = 0; l < DQ; ++l) {
+          a.qout[out_off + f * DQ + l] = __builtin_nan("");
+          if constexpr (KIND != kUserOde) a.pout[out_off + f * DQ + l] = __builtin_nan("");
+        }
+      }
+      if (iters_off >= 0) a.step_iters[iters_off + step] = (uint8_t)kl;
+      InstStat st;
+      st.steps_done = step;
+      st.iterations = it_sum;
+      st.nonconv = nonconv;
+      st.max_k = maxk;
+      st.status = kNonFinite;
+      a.stat[inst] = st;
+      rel = true;
+    } else {
+      const ConstTab r = row_tab(T);
+#pragma unroll
+      for (int l = 0; l < DQ; ++l) form_update<KIND, EXACT>(r, R[l], h, qh[l], ql[l], vh[l], vl[l]);
+      if (iters_off >= 0) a.step_iters[iters_off + step] = (uint8_t)kl;
+      ++step;
+      it_sum += kl;
+      nonconv += (flags & 2) ? 1 : 0;
+      if (kl > maxk) maxk = kl;
+      if (step % stride == 0) {  // unit masses: p = v; first order: y only
+        const int64_t f = step / stride;
+#pragma unroll
+        for (int l = 0; l < DQ; ++l) {
+          a.qout[out_off + f * DQ + l] = qh[l];
+          if constexpr (KIND != kUserOde) a.pout[out_off + f * DQ + l] = vh[l];
+        }
+      }
+      if (step >= target) {
+        double* St = a.state + state_off;
+#pragma unroll
+        for (int l = 0; l < DQ; ++l) {
+          St[l] = qh[l];
+          St[DQ + l] = ql[l];
+          if constexpr (KIND != kUserOde) {
+            St[2 * DQ + l] = vh[l];
+            St[3 * DQ + l] = vl[l];
+          }
+#pragma unroll
+          for (int s = 0; s < S; ++s) St[4 * DQ + l * S + s] = R[l][s];
+        }
+        InstStat st;
+        st.steps_done = step;
+        st.iterations = it_sum;
+        st.nonconv = nonconv;
+        st.max_k = maxk;
+        st.status = kOk;
+        a.stat[inst] = st;
+        rel = true;
+      } else {
+        form_guess<KIND, DQ, EXACT>(T, qh, vh, R, h, Qc);
+        begin_step();
+      }
+    }
+    return rel;
+  };
 
   for (;;) {
     // ---- lanes without an instance take the next ones from the queue
@@ -116,108 +223,40 @@ __global__ __launch_bounds__(64) void lane_kernel(LaunchArgs a) {
         for (int s = 0; s < S; ++s) R[l][s] = St[4 * DQ + l * S + s];
       }
       form_guess<KIND, DQ, EXACT>(T, qh, vh, R, h, Qc);
+      begin_step();
     }
 
-    // ---- one step, all live lanes in lockstep
     const bool live = (inst >= 0) && (step < target);
-    bool conv = !live;
-#pragma unroll
-    for (int l = 0; l < DQ; ++l) mind[l] = prv[l] = __builtin_inf();
-    int k = 0, kl = 0, flags = 0;
-    while (__ballot(!conv) != 0) {
-      ++k;
-      if (!conv) {
-        lane_increments<KIND, DQ, EXACT, S>(T, Qc, h, G, prm, step, R);
-        double dmax[DQ], nf[DQ];
-#pragma unroll
-        for (int l = 0; l < DQ; ++l) dmax[l] = nf[l] = 0.0;
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-          const ConstTab r = row_tab(T);
-#pragma unroll
-          for (int l = 0; l < DQ; ++l) {
-            const double qn = form_stage_value<KIND, EXACT>(r, s, qh[l], vh[l], h, R[l]);
-            max_track(dmax[l], nf[l], fabs(qn - Qc[l][s]));
-            Qc[l][s] = qn;
-          }
-        }
-        bool ok = true, bad = false;
-#pragma unroll
-        for (int l = 0; l < DQ; ++l) {
-          bad |= !track_finite(dmax[l], nf[l]);
-          ok &= stop_component(dmax[l], mind[l], prv[l]);
-        }
-        if (ok || bad || k >= a.max_iter) {
-          conv = true;
-          kl = k;
-          flags = bad ? 1 : (!ok ? 2 : 0);
-        }
-      }
-    }
-
-    // ---- end of step: compensated update, output, next initial guess
     bool release = (inst >= 0) && !live;
-    if (live) {
-      if (flags & 1) {  // non-finite: stop this instance, remaining frames NaN
-        const int64_t nfr = target / stride;  // frames of this launch only
-        for (int64_t f = step / stride + 1; f <= nfr; ++f) {
-#pragma unroll
-          for (int l = 0; l < DQ; ++l) {
-            a.qout[out_off + f * DQ + l] = __builtin_nan("");
-            if constexpr (KIND != kUserOde) a.pout[out_off + f * DQ + l] = __builtin_nan("");
+    if constexpr (INDEP) {
+      // One fixed-point iteration for every live lane; a lane whose instance
+      // has converged finishes its step in the same pass, so no lane waits
+      // for a slower one (but every pass carries the end-of-step work of the
+      // lanes that finished).
+      if (live) {
+        ++k;
+        bool ok, bad;
+        iterate(ok, bad);
+        if (ok || bad || k >= a.max_iter) release |= end_step(k, bad ? 1 : (!ok ? 2 : 0));
+      }
+    } else {
+      // One step, all live lanes in lockstep: converged lanes wait for the
+      // slowest lane of the wavefront, then all finish the step together.
+      bool conv = !live;
+      int kl = 0, flags = 0;
+      while (__ballot(!conv) != 0) {
+        ++k;
+        if (!conv) {
+          bool ok, bad;
+          iterate(ok, bad);
+          if (ok || bad || k >= a.max_iter) {
+            conv = true;
+            kl = k;
+            flags = bad ? 1 : (!ok ? 2 : 0);
           }
-        }
-        if (iters_off >= 0) a.step_iters[iters_off + step] = (uint8_t)kl;
-        InstStat st;
-        st.steps_done = step;
-        st.iterations = it_sum;
-        st.nonconv = nonconv;
-        st.max_k = maxk;
-        st.status = kNonFinite;
-        a.stat[inst] = st;
-        release = true;
-      } else {
-        const ConstTab r = row_tab(T);
-#pragma unroll
-        for (int l = 0; l < DQ; ++l) form_update<KIND, EXACT>(r, R[l], h, qh[l], ql[l], vh[l], vl[l]);
-        if (iters_off >= 0) a.step_iters[iters_off + step] = (uint8_t)kl;
-        ++step;
-        it_sum += kl;
-        nonconv += (flags & 2) ? 1 : 0;
-        if (kl > maxk) maxk = kl;
-        if (step % stride == 0) {  // unit masses: p = v; first order: y only
-          const int64_t f = step / stride;
-#pragma unroll
-          for (int l = 0; l < DQ; ++l) {
-            a.qout[out_off + f * DQ + l] = qh[l];
-            if constexpr (KIND != kUserOde) a.pout[out_off + f * DQ + l] = vh[l];
-          }
-        }
-        if (step >= target) {
-          double* St = a.state + state_off;
-#pragma unroll
-          for (int l = 0; l < DQ; ++l) {
-            St[l] = qh[l];
-            St[DQ + l] = ql[l];
-            if constexpr (KIND != kUserOde) {
-              St[2 * DQ + l] = vh[l];
-              St[3 * DQ + l] = vl[l];
-            }
-#pragma unroll
-            for (int s = 0; s < S; ++s) St[4 * DQ + l * S + s] = R[l][s];
-          }
-          InstStat st;
-          st.steps_done = step;
-          st.iterations = it_sum;
-          st.nonconv = nonconv;
-          st.max_k = maxk;
-          st.status = kOk;
-          a.stat[inst] = st;
-          release = true;
-        } else {
-          form_guess<KIND, DQ, EXACT>(T, qh, vh, R, h, Qc);
         }
       }
+      if (live) release |= end_step(kl, flags);
     }
     if (release) inst = -1;
   }

@@ -265,3 +265,28 @@ def test_chunked_and_promoted_runs_are_bit_identical(monkeypatch, flags, promote
     assert np.array_equal(s1["step_iters"], s8["step_iters"])
     assert np.array_equal(s1["inst_iterations"], s8["inst_iterations"])
     assert np.array_equal(s1["inst_status"], s8["inst_status"])
+
+
+def test_nonfinite_instance_frames_across_chunks(monkeypatch):
+    """A call long enough to run in chunks: the instance that is non-finite
+    from its first step has NaN in every later frame (the frames of chunks it
+    no longer runs in included), and its neighbour is bit-identical to a run
+    in one launch."""
+    m = np.array([1.0, 1.0])
+    prob = dict(kind=K.IRKGL16_GRAVITY, n=2, d=3, mass=m, G=1.0, eps=0.0)
+    q0 = np.concatenate([np.zeros(6), [1.0, 0, 0, -1.0, 0, 0]])
+    p0 = np.concatenate([np.zeros(6), [0, 0.5, 0, 0, -0.5, 0]])
+    out = {}
+    for chunks in ("0", "1"):
+        monkeypatch.setenv("IRKGL16_CHUNKS", chunks)
+        integ = K.Integrator([prob, prob])
+        out[chunks] = integ.integrate(q0, p0, 0.05, 1000, 10)
+        integ.close()
+    q, p, st, rc = out["0"]  # automatic: 15 chunks
+    assert rc == K.IRKGL16_ENONFINITE and st["inst_status"][0] == K.IRKGL16_ENONFINITE
+    nfr = 1000 // 10 + 1
+    qa = q[:6 * nfr].reshape(nfr, 6)
+    assert np.all(np.isfinite(qa[0])) and np.all(np.isnan(qa[1:]))
+    assert np.all(np.isnan(p[6:6 * nfr]))
+    assert np.array_equal(q[6 * nfr:], out["1"][0][6 * nfr:])
+    assert np.array_equal(p[6 * nfr:], out["1"][1][6 * nfr:])
