@@ -241,14 +241,17 @@ def test_iteration_cap_reports_noconv():
 
 @pytest.mark.parametrize("flags", [0, K.IRKGL16_REPRODUCIBLE])
 @pytest.mark.parametrize("promote_k", ["0", "2.0", "2.2"])
-def test_chunked_and_promoted_runs_are_bit_identical(monkeypatch, flags, promote_k):
+@pytest.mark.parametrize("bodies", [3, 6, 8])
+def test_chunked_and_promoted_runs_are_bit_identical(monkeypatch, flags, promote_k, bodies):
     """A call run in chunks, with slow instances moved to the stage-parallel
     kernel between chunks (threshold 2.0: nearly all of them; 2.2: a mix;
     0: none), gives bit-identical frames and iteration counts to one launch
-    per class."""
+    per class.  3 bodies: one leftover component spread over the slot by
+    stage; 6: two; 8: three full rounds of components."""
     n, steps, stride = 256, 512, 64
-    mass, q0, p0 = W.planetary_arrays(n, 6, seed=77)
-    probs = [dict(kind=K.IRKGL16_GRAVITY, n=6, d=3, G=1.0, eps=0.0, mass=mass[i]) for i in range(n)]
+    mass, q0, p0 = W.planetary_arrays(n, bodies, seed=77)
+    probs = [dict(kind=K.IRKGL16_GRAVITY, n=bodies, d=3, G=1.0, eps=0.0, mass=mass[i])
+             for i in range(n)]
 
     def run(chunks, pk):
         monkeypatch.setenv("IRKGL16_CHUNKS", chunks)
