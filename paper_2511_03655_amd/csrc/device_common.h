@@ -132,7 +132,28 @@ struct LaunchArgs {
   // If set, the queue length in device memory (written by an earlier kernel
   // of the same call); replaces queue_len for launches with a queue counter.
   const int32_t* queue_len_dev = nullptr;
+  // If > 0: no instance goes past this step count in this launch (a chunk
+  // boundary; instances behind it catch up).
+  int64_t step_limit = 0;
+  // Small-system kernel, if > 0: an instance whose recent iterations per step
+  // (an exponential average over about 8 steps) reach evict_k stops at the
+  // end of that step, with `evicted` set, for the next launch to move it to
+  // the stage-parallel kernel.
+  double evict_k = 0.0;
+  uint8_t* evicted = nullptr;
 };
+
+// Step count an instance may reach in a launch: its own, cut by the launch's
+// step budget (relative) and step limit (absolute); its current count if it
+// has stopped or is already past the limit.
+__device__ __forceinline__ int64_t launch_target(const LaunchArgs& a, int64_t steps_done,
+                                                 int64_t nsteps, int32_t status) {
+  int64_t t = nsteps;
+  if (a.step_budget > 0 && steps_done + a.step_budget < t) t = steps_done + a.step_budget;
+  if (a.step_limit > 0 && a.step_limit < t) t = a.step_limit;
+  if (status != kOk || t < steps_done) t = steps_done;
+  return t;
+}
 
 // Length of a launch's class queue.
 __device__ __forceinline__ int32_t queue_length(const LaunchArgs& a) {

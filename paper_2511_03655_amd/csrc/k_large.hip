@@ -276,9 +276,7 @@ __global__ __launch_bounds__(64 * NCH) void large_kernel(LargeArgs L) {
   const double eps2 = dsc.eps * dsc.eps;
   const InstStat st0 = a.stat[L.inst];
   int64_t step = st0.steps_done;
-  int64_t target = dsc.nsteps;
-  if (a.step_budget > 0 && step + a.step_budget < dsc.nsteps) target = step + a.step_budget;
-  if (st0.status != kOk) target = step;
+  const int64_t target = launch_target(a, step, dsc.nsteps, st0.status);
   int64_t it_sum = st0.iterations, nonconv = st0.nonconv;
   int32_t maxk = st0.max_k;
   // barrier generation: continue from the release word left by the previous

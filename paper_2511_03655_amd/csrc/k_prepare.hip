@@ -21,7 +21,8 @@ __global__ __launch_bounds__(64) void prepare_kernel(const InstDesc* __restrict_
                                                      uint8_t* __restrict__ step_iters,
                                                      int32_t* __restrict__ heads, int n_heads,
                                                      const int32_t* __restrict__ ids,
-                                                     int64_t* __restrict__ prev) {
+                                                     int64_t* __restrict__ prev,
+                                                     uint8_t* __restrict__ evicted) {
   const int i = ids ? ids[blockIdx.x] : (int)blockIdx.x;
   if (blockIdx.x == 0) {
     for (int t = threadIdx.x; t < n_heads; t += blockDim.x) heads[t] = 0;
@@ -53,16 +54,18 @@ __global__ __launch_bounds__(64) void prepare_kernel(const InstDesc* __restrict_
     st.status = kOk;
     stat[i] = st;
     if (prev) prev[2 * i] = prev[2 * i + 1] = 0;
+    if (evicted) evicted[i] = 0;
   }
 }
 
 hipError_t launch_prepare(const InstDesc* desc, InstStat* stat, double* state,
                           const double* params, const double* q0, const double* p0, double* qout,
                           double* pout, uint8_t* step_iters, int32_t* heads, int n_heads,
-                          int n_inst, hipStream_t st, const int32_t* ids, int64_t* prev) {
+                          int n_inst, hipStream_t st, const int32_t* ids, int64_t* prev,
+                          uint8_t* evicted) {
   if (n_inst <= 0) return hipSuccess;
   hipLaunchKernelGGL(prepare_kernel, dim3(n_inst), dim3(64), 0, st, desc, stat, state, params, q0,
-                     p0, qout, pout, step_iters, heads, n_heads, ids, prev);
+                     p0, qout, pout, step_iters, heads, n_heads, ids, prev, evicted);
   return hipGetLastError();
 }
 
@@ -74,7 +77,8 @@ hipError_t launch_prepare(const InstDesc* desc, InstStat* stat, double* state,
 // an octave.  Instances with nothing left go last.  The order inside a
 // bucket is arbitrary: it decides only when an instance runs, never its
 // arithmetic.  With promote_k > 0, instances that needed at least promote_k
-// iterations per step go to a second queue instead (served by a kernel with
+// iterations per step, or that the small-system kernel evicted (evicted[id],
+// cleared here), go to a second queue instead (served by a kernel with
 // more lanes per instance and a shorter iteration; both kernels compute the
 // same arithmetic).  counts[0], counts[1]: lengths of the two queues.
 // Records each instance's counters for the next chunk and resets both queue
@@ -90,7 +94,8 @@ __global__ __launch_bounds__(1024) void order_kernel(const int32_t* __restrict__
                                                      int32_t* __restrict__ qprom,
                                                      int32_t* __restrict__ counts,
                                                      int32_t* __restrict__ head_prom,
-                                                     double promote_k) {
+                                                     double promote_k,
+                                                     uint8_t* __restrict__ evicted) {
   __shared__ int32_t hist[kOrderBuckets];
   __shared__ int32_t base[kOrderBuckets];
   __shared__ int32_t nprom;
@@ -104,6 +109,7 @@ __global__ __launch_bounds__(1024) void order_kernel(const int32_t* __restrict__
     const int64_t rem = (s.status == kOk) ? desc[id].nsteps - s.steps_done : 0;
     if (rem <= 0) return kOrderBuckets - 1;
     const int64_t it = s.iterations - prev[2 * id], st = s.steps_done - prev[2 * id + 1];
+    if (promote_k > 0.0 && evicted[id]) return -1;
     if (promote_k > 0.0 && st > 0 && (double)it >= promote_k * (double)st) return -1;
     const double kbar = st > 0 ? (double)it / (double)st : 2.0;
     int b = (int)(2.0 * log2((double)rem * (kbar > 1.0 ? kbar : 1.0)));
@@ -135,6 +141,7 @@ __global__ __launch_bounds__(1024) void order_kernel(const int32_t* __restrict__
       qprom[atomicAdd(&nprom, 1)] = id;
     prev[2 * id] = stat[id].iterations;
     prev[2 * id + 1] = stat[id].steps_done;
+    evicted[id] = 0;
   }
   __syncthreads();
   if (tid == 0) {
@@ -146,9 +153,10 @@ __global__ __launch_bounds__(1024) void order_kernel(const int32_t* __restrict__
 
 hipError_t launch_order(const int32_t* qin, int32_t* qout, int32_t count, const InstDesc* desc,
                         const InstStat* stat, int64_t* prev, int32_t* head, int32_t* qprom,
-                        int32_t* counts, int32_t* head_prom, double promote_k, hipStream_t st) {
+                        int32_t* counts, int32_t* head_prom, double promote_k,
+                        uint8_t* evicted, hipStream_t st) {
   hipLaunchKernelGGL(order_kernel, dim3(1), dim3(1024), 0, st, qin, qout, count, desc, stat, prev,
-                     head, qprom, counts, head_prom, promote_k);
+                     head, qprom, counts, head_prom, promote_k, evicted);
   return hipGetLastError();
 }
 

@@ -149,9 +149,7 @@ __global__ __launch_bounds__(8 * NPMAX) void stage_kernel(LaunchArgs a, int np) 
     const double eps2 = dsc.eps * dsc.eps;
     const int64_t stride = dsc.stride, out_off = dsc.out_off, iters_off = dsc.iters_off;
     int64_t step = st0.steps_done;
-    int64_t target = dsc.nsteps;
-    if (a.step_budget > 0 && step + a.step_budget < dsc.nsteps) target = step + a.step_budget;
-    if (st0.status != kOk) target = step;
+    const int64_t target = launch_target(a, step, dsc.nsteps, st0.status);
     int64_t it_sum = st0.iterations, nonconv = st0.nonconv;
     int32_t maxk = st0.max_k;
     int32_t status = st0.status;

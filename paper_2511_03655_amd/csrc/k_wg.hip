@@ -166,11 +166,7 @@ __global__ __launch_bounds__(MAXT) void wg_kernel(LaunchArgs a, int S) {
       M.it_sum = st.iterations;
       M.nonconv = st.nonconv;
       M.maxk = st.max_k;
-      int64_t target = dsc.nsteps;
-      if (a.step_budget > 0 && st.steps_done + a.step_budget < dsc.nsteps)
-        target = st.steps_done + a.step_budget;
-      if (st.status != kOk) target = st.steps_done;
-      M.target = target;
+      M.target = launch_target(a, st.steps_done, dsc.nsteps, st.status);
     }
     __syncthreads();
     const int n = (cur >= 0) ? M.n : 0;

@@ -205,9 +205,7 @@ __global__ __launch_bounds__(64) void lane_kernel(LaunchArgs a) {
       it_sum = st.iterations;
       nonconv = st.nonconv;
       maxk = st.max_k;
-      target = dsc.nsteps;
-      if (a.step_budget > 0 && step + a.step_budget < dsc.nsteps) target = step + a.step_budget;
-      if (st.status != kOk) target = step;
+      target = launch_target(a, step, dsc.nsteps, st.status);
       const double* St = a.state + state_off;
 #pragma unroll
       for (int l = 0; l < DQ; ++l) {

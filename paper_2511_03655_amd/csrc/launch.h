@@ -27,12 +27,13 @@ hipError_t launch_prepare(const InstDesc* desc, InstStat* stat, double* state,
                           const double* params, const double* q0, const double* p0, double* qout,
                           double* pout, uint8_t* step_iters, int32_t* heads, int n_heads,
                           int n_inst, hipStream_t st, const int32_t* ids = nullptr,
-                          int64_t* prev = nullptr);
+                          int64_t* prev = nullptr, uint8_t* evicted = nullptr);
 hipError_t launch_nan_fill(const InstDesc* desc, const InstStat* stat, double* qout, double* pout,
                            int n_inst, hipStream_t st);
 hipError_t launch_order(const int32_t* qin, int32_t* qout, int32_t count, const InstDesc* desc,
                         const InstStat* stat, int64_t* prev, int32_t* head, int32_t* qprom,
-                        int32_t* counts, int32_t* head_prom, double promote_k, hipStream_t st);
+                        int32_t* counts, int32_t* head_prom, double promote_k,
+                        uint8_t* evicted, hipStream_t st);
 hipError_t launch_small_class(int kind, int nb, int d, const LaunchArgs& a, int n_items,
                               int num_cus, hipStream_t st);
 bool small_class_supported(int kind, int nb, int d);

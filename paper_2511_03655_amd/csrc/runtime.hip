@@ -110,8 +110,10 @@ struct irkgl16_ctx {
   DevBuf d_tab, d_desc, d_stat, d_state, d_params, d_queue, d_heads, d_plainq;
   DevBuf d_queue2, d_prev;  // chunked calls: reordered queues, per-instance counters
   DevBuf d_qprom, d_counts, d_heads_prom;  // promoted queues, queue lengths, their heads
+  DevBuf d_evicted;                         // per instance: evicted by the small-system kernel
   int chunks = 0;            // chunks per call (0: automatic)
   double promote_k = 5.0;    // promotion threshold, iterations per step (0: never)
+  double evict_k = 12.0;     // mid-chunk eviction threshold, recent iterations per step (0: never)
   DevBuf d_q0, d_p0, d_qout, d_pout, d_iters, d_large;
   int large_nmax = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -326,6 +328,9 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
   // Iterations per step from which a small-system instance moves to the
   // stage-parallel kernel for the next chunk (0: never).
   if (const char* pk = std::getenv("IRKGL16_PROMOTE_K")) c->promote_k = std::max(0.0, std::atof(pk));
+  // Recent iterations per step from which the small-system kernel stops an
+  // instance mid-chunk for promotion at the next chunk (0: never).
+  if (const char* ek = std::getenv("IRKGL16_EVICT_K")) c->evict_k = std::max(0.0, std::atof(ek));
   for (auto& kc : c->classes)
     if (kc.cls == irk::kClassWg)
       kc.tune.wg_block = c->tune.get(irk::wg_tune_key(kc.kind, kc.d, kc.size), 0);
@@ -363,6 +368,7 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
       (rc = alloc_try(c->d_qprom, sizeof(int32_t) * std::max<size_t>(queue_len, 1))) ||
       (rc = alloc_try(c->d_counts, sizeof(int32_t) * 2 * std::max<size_t>(c->classes.size(), 1))) ||
       (rc = alloc_try(c->d_heads_prom, sizeof(int32_t) * std::max<size_t>(c->classes.size(), 1))) ||
+      (rc = alloc_try(c->d_evicted, (size_t)std::max(n_inst, 1))) ||
       (rc = alloc_try(c->d_plainq, sizeof(int32_t) * std::max<size_t>(plainq.size(), 1))) ||
       (rc = alloc_try(c->d_heads, sizeof(int32_t) * std::max<size_t>(c->classes.size(), 1))))
     return fail(rc);
@@ -602,7 +608,8 @@ static int integrate_impl(irkgl16_ctx* c, const double* q0, const double* p0, co
   HIP_TRY(irk::launch_prepare(c->d_desc.as<irk::InstDesc>(), c->d_stat.as<irk::InstStat>(),
                               c->d_state.as<double>(), c->d_params.as<double>(), dq0, dp0, dqo,
                               dpo, c->record ? c->d_iters.as<uint8_t>() : nullptr,
-                              c->d_heads.as<int32_t>(), (int)c->classes.size(), n, c->stream, nullptr, c->d_prev.as<int64_t>()));
+                              c->d_heads.as<int32_t>(), (int)c->classes.size(), n, c->stream, nullptr,
+                              c->d_prev.as<int64_t>(), c->d_evicted.as<uint8_t>()));
   irk::LaunchArgs a = base_args(c, dqo, dpo);
   if ((c->flags & IRKGL16_PLAIN) && (c->flags & IRKGL16_GRAPH)) {
     // Plain form with the step loop in a graph: one step's launches (one per
@@ -680,7 +687,13 @@ static int integrate_impl(irkgl16_ctx* c, const double* q0, const double* p0, co
         ca.queue = (ch == 0 ? members : qnorm) + kc.queue_off;
         ca.queue_len = (int32_t)kc.ids.size();
         ca.queue_head = c->d_heads.as<int32_t>() + pl.k;
-        ca.step_budget = pl.budget;
+        // chunk boundary: instances behind it (evicted ones) catch up; the
+        // last chunk runs every instance to its end
+        ca.step_limit = (pl.nch > 1 && ch + 1 < pl.nch) ? (ch + 1) * pl.budget : 0;
+        if (pl.jp >= 0 && ch + 1 < pl.nch) {
+          ca.evict_k = c->evict_k;
+          ca.evicted = c->d_evicted.as<uint8_t>();
+        }
         if (ch > 0) ca.queue_len_dev = counts + 2 * pl.k;  // set by the order kernel
         HIP_TRY(fork(pl.j));
         if (pl.nch > 1) step_used[pl.j] = 1;
@@ -690,6 +703,7 @@ static int integrate_impl(irkgl16_ctx* c, const double* q0, const double* p0, co
           ks.cls = irk::kClassStage;
           ks.size = irk::stage_np(kc.size);
           irk::LaunchArgs pa = ca;
+          pa.evict_k = 0.0;
           pa.queue = c->d_qprom.as<int32_t>() + kc.queue_off;
           pa.queue_len_dev = counts + 2 * pl.k + 1;
           pa.queue_head = c->d_heads_prom.as<int32_t>() + pl.k;
@@ -715,7 +729,8 @@ static int integrate_impl(irkgl16_ctx* c, const double* q0, const double* p0, co
                                   c->d_heads.as<int32_t>() + pl.k,
                                   c->d_qprom.as<int32_t>() + kc.queue_off, counts + 2 * pl.k,
                                   c->d_heads_prom.as<int32_t>() + pl.k,
-                                  pl.jp >= 0 ? c->promote_k : 0.0, c->stream));
+                                  pl.jp >= 0 ? c->promote_k : 0.0,
+                                  c->d_evicted.as<uint8_t>(), c->stream));
       }
     }
     for (int j = 0; j < naux; ++j) {

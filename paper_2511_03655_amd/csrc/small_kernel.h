@@ -152,6 +152,7 @@ struct SlotMeta {
   double h, G, eps2;
   double m[NB];
   int64_t prm_off;                   // user-force parameters in the params arena, or -1
+  double kema;                       // recent iterations per step (eviction, LaunchArgs.evict_k)
   int32_t inst, maxk;
 };
 
@@ -260,11 +261,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
       M.it_sum = st.iterations;
       M.nonconv = st.nonconv;
       M.maxk = st.max_k;
-      int64_t target = dsc.nsteps;
-      if (a.step_budget > 0 && st.steps_done + a.step_budget < dsc.nsteps)
-        target = st.steps_done + a.step_budget;
-      if (st.status != kOk) target = st.steps_done;
-      M.target = target;
+      M.target = launch_target(a, st.steps_done, dsc.nsteps, st.status);
+      M.kema = 2.0;
 #pragma unroll
       for (int b = 0; b < NB; ++b) M.m[b] = (dsc.mass_off >= 0) ? a.params[dsc.mass_off + b] : 1.0;
     }
@@ -419,6 +417,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
         const int64_t step = step0 + 1;
         const bool frame = (step % stride) == 0;
         const bool last = step >= M.target;
+        // An instance whose recent steps needed many iterations stops here,
+        // for the next launch to move it to the stage-parallel kernel.
+        const double kema = 0.875 * M.kema + 0.125 * (double)kslot;
+        const bool evict = !last && a.evict_k > 0.0 && kema >= a.evict_k;
+        const bool stop = last || evict;
         double* St = a.state + M.state_off;
         double R[CPL][S];
         const ConstTab r = row_tab(T);
@@ -434,7 +437,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
               a.qout[out_off + f * DQ + c] = qh[cc];
               if constexpr (KIND != kUserOde) a.pout[out_off + f * DQ + c] = M.m[c / D] * vh[cc];
             }
-            if (last) {
+            if (stop) {
               St[c] = qh[cc];
               St[DQ + c] = ql[cc];
               St[2 * DQ + c] = vh[cc];
@@ -444,7 +447,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
             }
           }
         }
-        if (!last) {
+        if (!stop) {
           form_guess<KIND, CPL, EXACT>(T, qh, vh, R, h, Qc);
           begin_step(step);
         }
@@ -459,7 +462,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
               a.qout[out_off + f * DQ + tcomp] = tqh;
               if constexpr (KIND != kUserOde) a.pout[out_off + f * DQ + tcomp] = M.m[tcomp / D] * tvh;
             }
-            if (last) {
+            if (stop) {
               St[tcomp] = tqh;
               St[DQ + tcomp] = tql;
               St[2 * DQ + tcomp] = tvh;
@@ -468,7 +471,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
               for (int s = 0; s < S; ++s) St[4 * DQ + tcomp * S + s] = tR[s];
             }
           }
-          if (!last) {
+          if (!stop) {
 #pragma unroll
             for (int u = 0; u < TSL; ++u)
               tQ[u] = guess_stage<KIND, EXACT>(TabL, tst0 + u, tqh, tvh, tR, h);
@@ -479,8 +482,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
           M.step = step;
           M.it_sum += kslot;
           M.nonconv += slot_ok ? 0 : 1;
+          M.kema = kema;
           if (kslot > M.maxk) M.maxk = kslot;
-          if (last) {
+          if (evict) a.evicted[inst] = 1;
+          if (stop) {
             InstStat st;
             st.steps_done = step;
             st.iterations = M.it_sum;
@@ -490,7 +495,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
             a.stat[inst] = st;
           }
         }
-        release = last;
+        release = stop;
       }
     }
     __syncthreads();

@@ -52,9 +52,7 @@ __global__ __launch_bounds__(64) void split_kernel(LaunchArgs a) {
       iters_off = dsc.iters_off;
       state_off = dsc.state_off;
       step = st0.steps_done;
-      target = dsc.nsteps;
-      if (a.step_budget > 0 && step + a.step_budget < dsc.nsteps) target = step + a.step_budget;
-      if (st0.status != kOk) target = step;
+      target = launch_target(a, step, dsc.nsteps, st0.status);
       const double* St = a.state + state_off;
 #pragma unroll
       for (int l = 0; l < DQ; ++l) {

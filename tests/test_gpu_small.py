@@ -240,14 +240,18 @@ def test_iteration_cap_reports_noconv():
 
 
 @pytest.mark.parametrize("flags", [0, K.IRKGL16_REPRODUCIBLE])
-@pytest.mark.parametrize("promote_k", ["0", "2.0", "2.2"])
+@pytest.mark.parametrize("promote_k,evict_k", [("0", "0"), ("2.0", "8"), ("2.2", "8"),
+                                               ("2.2", "2.3")])
 @pytest.mark.parametrize("bodies", [3, 6, 8])
-def test_chunked_and_promoted_runs_are_bit_identical(monkeypatch, flags, promote_k, bodies):
+def test_chunked_and_promoted_runs_are_bit_identical(monkeypatch, flags, promote_k, evict_k,
+                                                     bodies):
     """A call run in chunks, with slow instances moved to the stage-parallel
     kernel between chunks (threshold 2.0: nearly all of them; 2.2: a mix;
-    0: none), gives bit-identical frames and iteration counts to one launch
-    per class.  3 bodies: one leftover component spread over the slot by
-    stage; 6: two; 8: three full rounds of components."""
+    0: none) and, with eviction threshold 2.3, many instances stopped
+    mid-chunk to catch up on the stage-parallel kernel in the next one,
+    gives bit-identical frames and iteration counts to one launch per
+    class.  3 bodies: one leftover component spread over the slot by stage;
+    6: two; 8: three full rounds of components."""
     n, steps, stride = 256, 512, 64
     mass, q0, p0 = W.planetary_arrays(n, bodies, seed=77)
     probs = [dict(kind=K.IRKGL16_GRAVITY, n=bodies, d=3, G=1.0, eps=0.0, mass=mass[i])
@@ -256,6 +260,7 @@ def test_chunked_and_promoted_runs_are_bit_identical(monkeypatch, flags, promote
     def run(chunks, pk):
         monkeypatch.setenv("IRKGL16_CHUNKS", chunks)
         monkeypatch.setenv("IRKGL16_PROMOTE_K", pk)
+        monkeypatch.setenv("IRKGL16_EVICT_K", evict_k)
         integ = K.Integrator(probs, flags=flags, record_iters=True)
         out = integ.integrate(q0.ravel(), p0.ravel(), 1.0, steps, stride)
         integ.close()
