@@ -141,6 +141,9 @@ struct LaunchArgs {
   // the stage-parallel kernel.
   double evict_k = 0.0;
   uint8_t* evicted = nullptr;
+  // Stage-parallel kernel: the launch serves promoted instances, the slowest
+  // work of the call, whose wavefronts then take the highest issue priority.
+  int32_t promoted = 0;
 };
 
 // Step count an instance may reach in a launch: its own, cut by the launch's

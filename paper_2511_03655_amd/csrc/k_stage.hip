@@ -121,6 +121,9 @@ __global__ __launch_bounds__(8 * NPMAX) void stage_kernel(LaunchArgs a, int np) 
   const double cs = a.tab[kTabC + s];
   const double bs = a.tab[kTabB + s];
 
+  // Promoted instances bound the length of their chunk: their wavefronts
+  // take issue priority over the few-body kernel's on the same SIMDs.
+  if (a.promoted) __builtin_amdgcn_s_setprio(3);
   if (tid < 7) ctl[tid] = 0;
   int64_t gk = 0;  // iteration counter over the whole launch (flag rotation)
 

@@ -704,6 +704,7 @@ static int integrate_impl(irkgl16_ctx* c, const double* q0, const double* p0, co
           ks.size = irk::stage_np(kc.size);
           irk::LaunchArgs pa = ca;
           pa.evict_k = 0.0;
+          pa.promoted = 1;
           pa.queue = c->d_qprom.as<int32_t>() + kc.queue_off;
           pa.queue_len_dev = counts + 2 * pl.k + 1;
           pa.queue_head = c->d_heads_prom.as<int32_t>() + pl.k;
