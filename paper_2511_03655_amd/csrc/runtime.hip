@@ -632,10 +632,13 @@ static int integrate_impl(irkgl16_ctx* c, const double* q0, const double* p0, co
     // stream after the others; the batched classes run concurrently, one
     // auxiliary stream per class (round robin), joined back into the stream.
     // A class that can promote instances (or every batched class when a chunk
-    // count is given) runs in chunks of a step budget; between chunks the
-    // order kernel, on the main stream, sorts its queue by estimated remaining
-    // work and picks the instances for the stage-parallel kernel, whose chunk
-    // runs concurrently on an auxiliary stream that no class uses.  Each chunk
+    // count is given) runs in chunks ending at multiples of a step count (the
+    // few-body kernel stops an instance early once its iterations per step
+    // grow large; it catches up in the next chunk); between chunks the order
+    // kernel, on the main stream, sorts its queue by estimated remaining work
+    // and picks the instances for the stage-parallel kernel (evicted ones and
+    // slow ones), whose chunk runs concurrently, at the highest wave priority,
+    // on an auxiliary stream that no class uses.  Each chunk
     // forks the class's stream and its promotion stream from one event, so the
     // promoted chunk is placed on the GPU as early as the class's own (a
     // promoted chunk queued behind a full grid of the class's workgroups would
