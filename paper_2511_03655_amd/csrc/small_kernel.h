@@ -206,6 +206,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
   // per step).
   int k = 0;
   double hb_sub = 0.0, t_sub = 0.0;
+  // A converged slot waits (its increments stay in its LDS tile) until its
+  // step end runs together with other slots' (see the flush rule below):
+  // kw, wok, wbad are the iteration count and outcome it converged with.
+  bool waiting = false, wok = true, wbad = false;
+  int waited = 0, kw = 0;
   const int sub_s = sub < S ? sub : S - 1;
   auto begin_step = [&](int64_t step) {
     k = 0;
@@ -302,8 +307,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
     // only its own slot's throughput).
     const bool live = (inst >= 0) && (M.step < M.target);
     const double h = M.h;
-    if (fresh) begin_step(M.step);
-    if (live) {
+    if (fresh) {
+      begin_step(M.step);
+      waiting = false;
+    }
+    const bool active = live && !waiting;  // iterates in this pass
+    if (active) {
       ++k;
 #pragma unroll
       for (int cc = 0; cc < CPL; ++cc) {
@@ -318,13 +327,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
       }
     }
     __syncthreads();
-    if (live && sub < S)  // lanes past the stage count idle in this role
+    if (active && sub < S)  // lanes past the stage count idle in this role
       stage_increment<KIND, NB, D, EXACT, S>(Xs, sub, M.m, M.eps2, hb_sub, M.G,
                                              M.prm_off >= 0 ? a.params + M.prm_off : nullptr,
                                              t_sub);
     __syncthreads();
     bool ok = true, bad = false;
-    if (live) {
+    if (active) {
       double R[CPL][S], dmax[CPL], nf[CPL];
 #pragma unroll
       for (int cc = 0; cc < CPL; ++cc) {
@@ -370,13 +379,30 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
     const uint64_t badm = __ballot(bad);
     const bool slot_ok = (okm & smask) == smask;
     const bool slot_bad = (badm & smask) != 0;
-    const bool done = live && (slot_ok || slot_bad || k >= a.max_iter);
+    if (active && (slot_ok || slot_bad || k >= a.max_iter)) {
+      waiting = true;
+      waited = 0;
+      kw = k;
+      wok = slot_ok;
+      wbad = slot_bad;
+    }
+    // Flush rule: the waiting slots finish their steps together once at
+    // least half the slots wait, once one has waited two passes, or once no
+    // slot is iterating.  The step end then runs about once per step for the
+    // whole wavefront instead of in nearly every pass, while a slot that
+    // needs many iterations never holds the others back for long.
+    const int nwait = __popcll(__ballot(waiting && sub == 0));
+    const int nact = __popcll(__ballot(live && !waiting && sub == 0));
+    const bool flush =
+        nwait >= kSlot / 2 || __ballot(waiting && waited >= 2) != 0 || (nwait > 0 && nact == 0);
+    const bool done = waiting && flush;
+    if (waiting && !flush) ++waited;
     // A wavefront holding an instance deep in its fixed-point iteration
     // (k >= 4 this step; typical steps take 2 or 3) takes issue priority on
     // its SIMD: the long sequential integrations, which bound the batch's
     // completion time, then run near their uncontended speed while the
     // other wavefronts fill the remaining issue slots.
-    if (__ballot(live && k >= 4) != 0)
+    if (__ballot(active && k >= 4) != 0)
       __builtin_amdgcn_s_setprio(2);
     else
       __builtin_amdgcn_s_setprio(0);
@@ -385,9 +411,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
     // output, next initial guess
     bool release = (inst >= 0) && !live;
     if (done) {
-      const int kslot = k;
+      waiting = false;
+      const int kslot = kw;
       const int64_t step0 = M.step, stride = M.stride, out_off = M.out_off;
-      if (slot_bad) {  // non-finite: stop this instance, remaining frames NaN
+      if (wbad) {  // non-finite: stop this instance, remaining frames NaN
         const int64_t nf = M.target / stride;  // frames of this launch only
         for (int64_t f = step0 / stride + 1; f <= nf; ++f) {
 #pragma unroll
@@ -481,7 +508,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
           if (M.iters_off >= 0) a.step_iters[M.iters_off + step0] = (uint8_t)kslot;
           M.step = step;
           M.it_sum += kslot;
-          M.nonconv += slot_ok ? 0 : 1;
+          M.nonconv += wok ? 0 : 1;
           M.kema = kema;
           if (kslot > M.maxk) M.maxk = kslot;
           if (evict) a.evicted[inst] = 1;
