@@ -91,12 +91,25 @@ CSRC = os.path.join(ROOT, "paper_2511_03655_amd", "csrc")
 
 
 def source_digest(files):
-    """sha256 over kernel source files (the ones a traffic measurement covers)."""
+    """sha256 over kernel source files (the ones a traffic measurement covers).
+    C/C++ sources are hashed without comments and with whitespace runs
+    collapsed, so that an edited comment does not retire a measurement of
+    unchanged code; other files are hashed as they are."""
     import hashlib
+    import re
+    token = re.compile(r'"(?:\\.|[^"\\])*"|\'(?:\\.|[^\'\\])*\'|//[^\n]*|/\*.*?\*/', re.S)
+
+    def code_only(text):
+        text = token.sub(lambda m: "" if m.group(0).startswith("/") else m.group(0), text)
+        return re.sub(r"\s+", " ", text).strip()
+
     h = hashlib.sha256()
     for f in files:
         with open(os.path.join(CSRC, f), "rb") as fh:
-            h.update(fh.read())
+            data = fh.read()
+        if f.endswith((".h", ".hip", ".cpp")):
+            data = code_only(data.decode()).encode()
+        h.update(data)
     return h.hexdigest()
 
 

@@ -10,15 +10,22 @@
 //    Q_i = q + h (c_i v + sum_j eta_ij R_j) (eq. IRK_FP2), the per-component
 //    max-norm increment and stopping rule (eqs. Delta_n, stopping), the
 //    compensated update (eq. qnvn2) and the extrapolated initial guess
-//    (eq. IRK_init2) without any cross-lane traffic.
+//    (eq. IRK_init2) without any cross-lane traffic (when Dq = 8m + 1, 2 or
+//    4, the leftover components are spread over the slot by stage instead,
+//    with a DPP group maximum for their increment norms).
 //
 // The two roles exchange stage positions and increments R_i = h b_i g(Q_i)
-// through one LDS tile per slot laid out [component][stage].  Slots iterate
-// in lockstep; a slot whose instance has converged is masked until the slowest
-// slot of the wave converges, then all slots finish the step together.  When
-// an instance finishes (or exhausts the per-launch step budget) its lanes write
-// the resumable state back and pull the next instance from the class queue.
-// Each instance's arithmetic is independent of which slot or wave runs it.
+// through one LDS tile per slot laid out [component][stage].  Each pass of
+// the wavefront is one fixed-point iteration of every slot that is still
+// iterating; a slot whose instance has converged waits (its increments stay
+// in its tile) and the waiting slots finish their steps together once half
+// the slots wait, one has waited two passes, or none iterates -- so a slow
+// instance holds the others back by at most two passes.  When an instance
+// finishes, reaches the launch's step budget or limit, or (LaunchArgs.evict_k)
+// has needed many iterations per step lately, its lanes write the resumable
+// state back and pull the next instance from the class queue.  Each
+// instance's arithmetic is independent of which slot or wave runs it, and of
+// where its steps are split between launches.
 //
 // KIND == kUserOde runs the first-order form (section 2.4, eqs. Yi2 / yn2;
 // section 2.5, eqs. IRK_init / IRK_FP) with the same two roles: stage lanes
