@@ -205,7 +205,7 @@ int irkgl16_ode_compile_check(const char *rhs_src, int32_t D, char *log, int64_t
  * with IRKGL16_DEVICE_PTRS it returns after enqueueing (stats, if given, force a
  * stream synchronization).  Returns the worst status over instances.
  * Scheduling (never changes results): the batched kernels run in chunks up to
- * step boundaries j ceil(max nsteps / c), c = min(16, max nsteps / 64) (at
+ * step boundaries j ceil(max nsteps / c), c = min(8, max nsteps / 64) (at
  * least 1);
  * between chunks a device kernel orders each class's work queue by estimated
  * remaining work (steps left times the iterations per step of the last chunk)
