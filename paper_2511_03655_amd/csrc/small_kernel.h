@@ -44,10 +44,24 @@ namespace irk {
 
 constexpr int kSlot = 8;  // lanes per slot (one instance per slot)
 
-// Reads the stage positions from column `sub` of the slot tile and overwrites
-// the same column with the increments R_sub = h b_sub g(Q_sub): a lane only
-// touches its own column, so no barrier is needed between the read and the
-// write.  Ms: the slot's masses (LDS); coef = (h b_sub) and G; prm: the
+// LDS tile of one slot: one row of kRow doubles per component, the stage
+// values in columns 0..S-1.  The row is padded to an odd length: in the
+// component-lane role the 8 lanes of a slot read rows sub, sub + 8, ... at a
+// stride of kRow doubles, and an even stride would put several of them on the
+// same LDS banks.  Slot tiles start 8 doubles (16 four-byte banks) apart
+// modulo 16 doubles, so the two slots that one 16-lane pass of a 64-bit LDS
+// access serves use disjoint banks in both roles.
+template <int DQ, int S = kS>
+struct SmallTile {
+  static constexpr int kRow = (S % 2 == 0) ? S + 1 : S;
+  static constexpr int kTile = DQ * kRow;
+  static constexpr int kStride = kTile + ((8 - kTile % 16) + 16) % 16;
+};
+
+// Reads the stage positions from column `sub` of the slot tile (rows of
+// SmallTile::kRow doubles) and overwrites the same column with the increments
+// R_sub = h b_sub g(Q_sub): a lane only touches its own column, so no barrier
+// is needed between the read and the write.  Ms: the slot's masses (LDS); coef = (h b_sub) and G; prm: the
 // instance's parameters of a user force; t: the stage time (user force only).
 template <int KIND, int NB, int D, bool EXACT, int S = kS>
 __device__ __forceinline__ void stage_increment(double* __restrict__ Xs, int sub,
@@ -55,14 +69,15 @@ __device__ __forceinline__ void stage_increment(double* __restrict__ Xs, int sub
                                                 double hb, double G, const double* prm,
                                                 double t) {
   constexpr int DQ = NB * D;
+  constexpr int RS = SmallTile<DQ, S>::kRow;
 #ifdef IRKGL16_USER_FORCE
   if constexpr (KIND == kUser) {  // R = h b_sub g(Q_sub, t_sub), g from the caller's source
     double q[DQ], r[DQ];
 #pragma unroll
-    for (int l = 0; l < DQ; ++l) q[l] = Xs[l * S + sub];
+    for (int l = 0; l < DQ; ++l) q[l] = Xs[l * RS + sub];
     user_increment<DQ>(q, hb, prm, t, r);
 #pragma unroll
-    for (int l = 0; l < DQ; ++l) Xs[l * S + sub] = r[l];
+    for (int l = 0; l < DQ; ++l) Xs[l * RS + sub] = r[l];
     return;
   }
 #endif
@@ -70,10 +85,10 @@ __device__ __forceinline__ void stage_increment(double* __restrict__ Xs, int sub
   if constexpr (KIND == kUserOde) {  // L = h b_sub f(t_sub, Y_sub), first-order form
     double y[DQ], r[DQ];
 #pragma unroll
-    for (int l = 0; l < DQ; ++l) y[l] = Xs[l * S + sub];
+    for (int l = 0; l < DQ; ++l) y[l] = Xs[l * RS + sub];
     ode_increment<DQ>(y, hb, prm, t, r);
 #pragma unroll
-    for (int l = 0; l < DQ; ++l) Xs[l * S + sub] = r[l];
+    for (int l = 0; l < DQ; ++l) Xs[l * RS + sub] = r[l];
     return;
   }
 #endif
@@ -82,10 +97,10 @@ __device__ __forceinline__ void stage_increment(double* __restrict__ Xs, int sub
   if constexpr (KIND == kKepler) {
     double q[DQ], r[DQ];
 #pragma unroll
-    for (int l = 0; l < DQ; ++l) q[l] = Xs[l * S + sub];
+    for (int l = 0; l < DQ; ++l) q[l] = Xs[l * RS + sub];
     kepler_increment<DQ, EXACT>(q, hb, G, r);
 #pragma unroll
-    for (int l = 0; l < DQ; ++l) Xs[l * S + sub] = r[l];
+    for (int l = 0; l < DQ; ++l) Xs[l * RS + sub] = r[l];
   } else if constexpr (EXACT) {
     // Ordered pairs, b ascending for every a, as in the force's definition.
     double out[DQ];
@@ -100,7 +115,7 @@ __device__ __forceinline__ void stage_increment(double* __restrict__ Xs, int sub
         double dx[D], r2 = 0.0;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-          dx[k] = Xs[(b * D + k) * S + sub] - Xs[(a * D + k) * S + sub];
+          dx[k] = Xs[(b * D + k) * RS + sub] - Xs[(a * D + k) * RS + sub];
           r2 = r2 + dx[k] * dx[k];
         }
         r2 = r2 + eps2;
@@ -112,7 +127,7 @@ __device__ __forceinline__ void stage_increment(double* __restrict__ Xs, int sub
       for (int k = 0; k < D; ++k) out[a * D + k] = hb * (G * acc[k]);
     }
 #pragma unroll
-    for (int l = 0; l < DQ; ++l) Xs[l * S + sub] = out[l];
+    for (int l = 0; l < DQ; ++l) Xs[l * RS + sub] = out[l];
   } else {
     double m[NB];
 #pragma unroll
@@ -127,7 +142,7 @@ __device__ __forceinline__ void stage_increment(double* __restrict__ Xs, int sub
       for (int b = a + 1; b < NB; ++b) {
         double dx[D];
 #pragma unroll
-        for (int k = 0; k < D; ++k) dx[k] = Xs[(b * D + k) * S + sub] - Xs[(a * D + k) * S + sub];
+        for (int k = 0; k < D; ++k) dx[k] = Xs[(b * D + k) * RS + sub] - Xs[(a * D + k) * RS + sub];
         double r2 = fma(dx[0], dx[0], eps2);
 #pragma unroll
         for (int k = 1; k < D; ++k) r2 = fma(dx[k], dx[k], r2);
@@ -142,15 +157,9 @@ __device__ __forceinline__ void stage_increment(double* __restrict__ Xs, int sub
     }
     const double coef = hb * G;
 #pragma unroll
-    for (int l = 0; l < DQ; ++l) Xs[l * S + sub] = coef * acc[l];
+    for (int l = 0; l < DQ; ++l) Xs[l * RS + sub] = coef * acc[l];
   }
 }
-
-template <int DQ, int S = kS>
-struct SmallTile {
-  // Slot tiles padded so that consecutive slots start on different LDS banks.
-  static constexpr int kStride = ((DQ * S * 2) % 32 == 0) ? DQ * S + 8 : DQ * S;
-};
 
 // Per-slot bookkeeping, kept in LDS rather than replicated in 8 lanes' VGPRs.
 template <int NB>
@@ -178,6 +187,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
   constexpr int TG = SPLIT ? kSlot / TAIL : 1;  // lanes per tail component
   constexpr int TSL = SPLIT ? TAIL : 1;         // tail stages per lane
   constexpr int TS = SmallTile<DQ, S>::kStride;
+  constexpr int RS = SmallTile<DQ, S>::kRow;
   __shared__ double X[8 * TS];
   // Coefficient table for rows picked by a lane-dependent stage (tail split).
   __shared__ double TabL[SPLIT ? Tab<S>::Size : 1];
@@ -325,12 +335,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
       for (int cc = 0; cc < CPL; ++cc) {
         if (owns(cc)) {
 #pragma unroll
-          for (int s = 0; s < S; ++s) Xs[comp(cc) * S + s] = Qc[cc][s];
+          for (int s = 0; s < S; ++s) Xs[comp(cc) * RS + s] = Qc[cc][s];
         }
       }
       if constexpr (SPLIT) {
 #pragma unroll
-        for (int u = 0; u < TSL; ++u) Xs[tcomp * S + tst0 + u] = tQ[u];
+        for (int u = 0; u < TSL; ++u) Xs[tcomp * RS + tst0 + u] = tQ[u];
       }
     }
     __syncthreads();
@@ -347,7 +357,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
         dmax[cc] = 0.0;
         nf[cc] = 0.0;
 #pragma unroll
-        for (int s = 0; s < S; ++s) R[cc][s] = Xs[cidx(cc) * S + s];
+        for (int s = 0; s < S; ++s) R[cc][s] = Xs[cidx(cc) * RS + s];
       }
 #pragma unroll
       for (int s = 0; s < S; ++s) {
@@ -369,7 +379,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
       if constexpr (SPLIT) {  // this lane's stages of its tail component
         double tR[S];
 #pragma unroll
-        for (int s = 0; s < S; ++s) tR[s] = Xs[tcomp * S + s];
+        for (int s = 0; s < S; ++s) tR[s] = Xs[tcomp * RS + s];
         double tdmax = 0.0, tnf = 0.0;
 #pragma unroll
         for (int u = 0; u < TSL; ++u) {
@@ -462,7 +472,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
 #pragma unroll
         for (int cc = 0; cc < CPL; ++cc) {
 #pragma unroll
-          for (int s = 0; s < S; ++s) R[cc][s] = Xs[cidx(cc) * S + s];
+          for (int s = 0; s < S; ++s) R[cc][s] = Xs[cidx(cc) * RS + s];
           form_update<KIND, EXACT>(r, R[cc], h, qh[cc], ql[cc], vh[cc], vl[cc]);
           if (owns(cc)) {
             const int c = comp(cc);
@@ -488,7 +498,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
         if constexpr (SPLIT) {  // tail component: update (replicated), outputs, guess
           double tR[S];
 #pragma unroll
-          for (int s = 0; s < S; ++s) tR[s] = Xs[tcomp * S + s];
+          for (int s = 0; s < S; ++s) tR[s] = Xs[tcomp * RS + s];
           form_update<KIND, EXACT>(r, tR, h, tqh, tql, tvh, tvl);
           if (tlead) {
             if (frame) {
