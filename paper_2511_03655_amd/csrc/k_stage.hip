@@ -29,10 +29,14 @@ namespace irk {
 
 constexpr int kStageMaxBodies = 128;
 
-// Component stride of a body's stage position in the LDS tiles.
+// Component stride of a body's stage position in the LDS tiles: odd (D, or
+// D + 1 for even D), so that the 8 stage addresses of one source in the force
+// loop, the per-lane writes of R and Q, and the two bodies' broadcast reads of
+// R that one 16-lane pass of a 64-bit LDS access serves all fall on distinct
+// four-byte banks.
 template <int D>
 constexpr int stage_pad() {
-  return D == 3 ? 4 : D;
+  return (D % 2 == 1) ? D : D + 1;
 }
 
 // LDS doubles: Qt [2][np][8][P], Rt [np][8][P], masses [np]; then 8 int32.
@@ -42,13 +46,15 @@ size_t stage_lds_doubles(int np) {
   return (size_t)3 * np * kS * P + np;
 }
 
-// Maximum over the 8 stage lanes of a body (lanes 8u .. 8u+7); a non-finite
-// operand is detected by the caller (finite() of its own increment), since
-// fmax drops NaN.
+// Maximum over the 8 stage lanes of a body (lanes 8u .. 8u+7, all active or
+// all inactive together) by DPP: swap neighbours, swap pairs, then mirror
+// within the 8 lanes, which pairs each quad with the other.  The maximum is
+// exact in any order.  A non-finite operand is detected by the caller
+// (finite() of its own increment), since fmax drops NaN.
 __device__ __forceinline__ double stage_group_max(double x) {
-#pragma unroll
-  for (int m = 1; m < kS; m <<= 1) x = fmax(x, __shfl_xor(x, m, kS));
-  return x;
+  x = fmax(x, dpp_double<0xB1>(x));
+  x = fmax(x, dpp_double<0x4E>(x));
+  return fmax(x, dpp_double<0x141>(x));
 }
 
 // Orders this lane's LDS writes before the reads that follow (in-wavefront
