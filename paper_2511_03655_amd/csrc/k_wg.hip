@@ -9,9 +9,10 @@
 // (eq. qnvn2) and the extrapolated initial guess (eq. IRK_init2) are all
 // lane-local.  The force needs the other bodies' (or the neighbours') stage
 // positions: each iteration the lanes publish their 8 x d stage positions to an
-// LDS tile laid out [unit][stage][component], and every lane reads the source
-// units it needs from there (gravity: all bodies of its system, summed in
-// ascending order; chain: the two neighbours).
+// LDS tile laid out [unit][stage][component] (units an odd number of doubles
+// apart), and every lane reads the source units it needs from there (gravity:
+// all bodies of its system, summed in ascending order; chain: the two
+// neighbours).
 //
 // A workgroup of T lanes is split into T / S slots of S lanes (S >= n, one
 // system per slot); slots iterate in lockstep, converged slots are masked, and
@@ -20,6 +21,16 @@
 #include "device_common.h"
 
 namespace irk {
+
+// Doubles per unit in the stage tile: the unit's 8 x D stage positions plus
+// one pad, so that consecutive lanes' units start an odd number of doubles
+// apart.  A stride of 8 D doubles (a multiple of 16 four-byte banks) would put
+// the 16 lanes of one 64-bit LDS pass on two banks when each lane reads or
+// writes its own unit, or a neighbour's.
+template <int D>
+constexpr int wg_unit_stride() {
+  return kS * D + 1;
+}
 
 struct WgMeta {
   int64_t nsteps, stride, out_off, iters_off, state_off, step, target, it_sum, nonconv;
@@ -34,7 +45,8 @@ __device__ __forceinline__ void unit_increments(const double* __restrict__ Qs,
                                                 ConstTab T, double h, double (&R)[D][kS]) {
   // The lane's own stage positions are read back from the tile (it published
   // them there), so they need not stay in registers across the force loop.
-  const double* qa = Qs + (size_t)(base + u) * kS * D;
+  constexpr int US = wg_unit_stride<D>();
+  const double* qa = Qs + (size_t)(base + u) * US;
   if constexpr (KIND == kGravity) {
     // Sources b ascending; the 8 stages of a source are 8 independent chains
     // (instruction-level parallelism); each stage's sum keeps the b order.
@@ -42,7 +54,7 @@ __device__ __forceinline__ void unit_increments(const double* __restrict__ Qs,
     double acc[D][kS] = {};
     for (int b = 0; b < n; ++b) {
       if (b == u) continue;
-      const double* qb = Qs + (size_t)(base + b) * kS * D;
+      const double* qb = Qs + (size_t)(base + b) * US;
       const double mb = Ms[base + b];
 #pragma unroll
       for (int s = 0; s < kS; ++s) {
@@ -83,8 +95,8 @@ __device__ __forceinline__ void unit_increments(const double* __restrict__ Qs,
     const double m_site = Ms[base + u];
 #pragma unroll
     for (int s = 0; s < kS; ++s) {
-      const double ql = (u > 0) ? Qs[(size_t)(base + u - 1) * kS + s] : 0.0;
-      const double qr = (u < n - 1) ? Qs[(size_t)(base + u + 1) * kS + s] : 0.0;
+      const double ql = (u > 0) ? Qs[(size_t)(base + u - 1) * US + s] : 0.0;
+      const double qr = (u < n - 1) ? Qs[(size_t)(base + u + 1) * US + s] : 0.0;
       const double sr = qr - qa[s];
       const double sl = qa[s] - ql;
       double F;
@@ -105,8 +117,9 @@ __global__ __launch_bounds__(MAXT) void wg_kernel(LaunchArgs a, int S) {
   extern __shared__ double lds[];
   const int TT = blockDim.x;
   const int nslots = TT / S;
-  double* Qs = lds;                                  // [TT][8][D]
-  double* Ms = Qs + (size_t)TT * kS * D;             // [TT] masses of the units
+  double* Qs = lds;                                  // [TT][8 D + 1]
+  constexpr int US = wg_unit_stride<D>();
+  double* Ms = Qs + (size_t)TT * US;                 // [TT] masses of the units
   WgMeta* meta = reinterpret_cast<WgMeta*>(Ms + TT);  // [nslots]
   int32_t* slot_inst = reinterpret_cast<int32_t*>(meta + nslots);
   int32_t* qdone = slot_inst + nslots;
@@ -211,7 +224,7 @@ __global__ __launch_bounds__(MAXT) void wg_kernel(LaunchArgs a, int S) {
 #pragma unroll
       for (int s = 0; s < kS; ++s)
 #pragma unroll
-        for (int d = 0; d < D; ++d) Qs[(size_t)(base + u) * kS * D + s * D + d] = Q[d][s];
+        for (int d = 0; d < D; ++d) Qs[(size_t)(base + u) * US + s * D + d] = Q[d][s];
     }
     int k = 0;
     while (__syncthreads_or(!conv)) {
@@ -224,7 +237,7 @@ __global__ __launch_bounds__(MAXT) void wg_kernel(LaunchArgs a, int S) {
       double Qn[D][kS] = {};
       if (!conv && mine) {
         unit_increments<KIND, D, EXACT>(Qs, Ms, base, u, n, M, kl, kr, T, h, R);
-        const double* qa = Qs + (size_t)(base + u) * kS * D;
+        const double* qa = Qs + (size_t)(base + u) * US;
         bool ok = true, bad = false;
         double dmax[D], nf[D];
 #pragma unroll
@@ -260,7 +273,7 @@ __global__ __launch_bounds__(MAXT) void wg_kernel(LaunchArgs a, int S) {
 #pragma unroll
           for (int s = 0; s < kS; ++s)
 #pragma unroll
-            for (int d = 0; d < D; ++d) Qs[(size_t)(base + u) * kS * D + s * D + d] = Qn[d][s];
+            for (int d = 0; d < D; ++d) Qs[(size_t)(base + u) * US + s * D + d] = Qn[d][s];
         }
       }
     }
@@ -372,7 +385,8 @@ int wg_block_size(int S) { return S <= 256 ? 256 : (S <= 512 ? 512 : 1024); }
 
 size_t wg_lds_bytes(int TT, int S, int D) {
   const int nslots = TT / S;
-  return sizeof(double) * ((size_t)TT * kS * D + TT) + sizeof(WgMeta) * nslots +
+  const int us = kS * D + 1;  // wg_unit_stride<D>()
+  return sizeof(double) * ((size_t)TT * us + TT) + sizeof(WgMeta) * nslots +
          sizeof(int32_t) * (nslots + 1);
 }
 
