@@ -36,6 +36,7 @@ constexpr int kStageMaxBodies = 128;
 // four-byte banks.
 template <int D>
 constexpr int stage_pad() {
+  static_assert(D >= 1 && D <= 3, "d = 1, 2 or 3");
   return (D % 2 == 1) ? D : D + 1;
 }
 

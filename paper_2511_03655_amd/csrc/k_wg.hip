@@ -29,6 +29,7 @@ namespace irk {
 // writes its own unit, or a neighbour's.
 template <int D>
 constexpr int wg_unit_stride() {
+  static_assert((kS * D + 1) % 2 == 1, "odd unit stride");
   return kS * D + 1;
 }
 

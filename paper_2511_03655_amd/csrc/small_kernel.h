@@ -56,6 +56,7 @@ struct SmallTile {
   static constexpr int kRow = (S % 2 == 0) ? S + 1 : S;
   static constexpr int kTile = DQ * kRow;
   static constexpr int kStride = kTile + ((8 - kTile % 16) + 16) % 16;
+  static_assert(kRow % 2 == 1 && kStride % 16 == 8, "conflict-free slot tile layout");
 };
 
 // Reads the stage positions from column `sub` of the slot tile (rows of
