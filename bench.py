@@ -402,6 +402,8 @@ def run_c1(args):
     t = time.perf_counter()
     plain.integrate(c1["q"], c1["p"], c1["h"], 2000, 2000)
     dtp = (time.perf_counter() - t) / 2000
+    integ.close()
+    plain.close()
     sp = orc.Spec(orc.KEPLER, 1, 2, G=1.0)
     t = time.perf_counter()
     r = orc.integrate(sp, c1["q"], c1["p"], c1["h"], n, 1)
@@ -437,6 +439,8 @@ def run_c3(args):
     t = time.perf_counter()
     plain.integrate(inst["q"], inst["p"], inst["h"], 50, 50)
     dtp = (time.perf_counter() - t) / 50
+    integ.close()
+    plain.close()
     sp = orc.Spec(orc.GRAVITY, 2048, 3, mass=inst["mass"], eps=inst["eps"])
     t = time.perf_counter()
     orc.integrate(sp, inst["q"], inst["p"], inst["h"], 10, 10)
@@ -499,6 +503,9 @@ def run_c4(args):
     t = time.perf_counter()
     bat.integrate(pq, pv, h[sample], 100, 100)
     dtb = time.perf_counter() - t
+    integ.close()
+    plain.close()
+    bat.close()
     specs = [orc.Spec(mix[i]["kind"], mix[i]["n"], mix[i]["d"], mass=mix[i].get("mass"),
                       G=mix[i].get("G", 1.0), beta=mix[i].get("beta", 0.0)) for i in sample]
     t = time.perf_counter()
@@ -576,6 +583,8 @@ def run_henon(args):
     t = time.perf_counter()
     plain.integrate(q0[:2 * n_p], p0[:2 * n_p], h, s_p, s_p)
     dtp = time.perf_counter() - t
+    integ.close()
+    plain.close()
     cpu = None
     if not args.no_cpu:
         n_c, s_c = 65536, 8000
@@ -655,6 +664,8 @@ def run_sbh(args):
     t = time.perf_counter()
     plain.integrate(y0[:4 * n_p], None, h, s_p, s_p)
     dtp = time.perf_counter() - t
+    integ.close()
+    plain.close()
     cpu = None
     if not args.no_cpu:
         n_c, s_c = 65536, 5000

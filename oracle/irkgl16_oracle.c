@@ -39,6 +39,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #include "tableau.h"
 
@@ -82,6 +85,33 @@ typedef struct {
 
 /* ---------------- forces g(Q) ---------------- */
 
+/* Gravitational systems of at least this many bodies spread their targets
+ * over threads when the caller is not already parallel (one large system).
+ * Each target's sum still runs over b in ascending order on one thread, so
+ * the result is the same for any thread count. */
+#define ORC_PAR_MIN_BODIES 256
+
+static int orc_serial_caller(void) {
+#ifdef _OPENMP
+  return !omp_in_parallel();
+#else
+  return 0;
+#endif
+}
+
+/* Thread count of the oracle's parallel loops for the calling thread (n <= 0:
+ * back to the count in effect before the first call, i.e. OMP_NUM_THREADS or
+ * the OpenMP default). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  static int initial = 0;
+  if (initial == 0) initial = omp_get_max_threads();
+  omp_set_num_threads(n > 0 ? n : initial);
+#else
+  (void)n;
+#endif
+}
+
 static double mass_of(const orc_problem *p, int body) {
   if (p->kind == ORC_GRAVITY) return p->mass[body];
   if (p->kind == ORC_CHAIN) return p->mass ? p->mass[body] : 1.0;
@@ -103,6 +133,8 @@ void orc_force_t(const orc_problem *p, const double *Q, double *G, double t) {
   }
   case ORC_GRAVITY: {
     double eps2 = p->eps * p->eps;
+    const int par = n >= ORC_PAR_MIN_BODIES && orc_serial_caller();
+#pragma omp parallel for schedule(static) if (par)
     for (int a = 0; a < n; ++a) {
       double acc[3] = {0.0, 0.0, 0.0};
       for (int b = 0; b < n; ++b) {

@@ -88,6 +88,8 @@ def lib():
         L.orc_dw_add.restype = None
         L.orc_stop_component.argtypes = [C.c_double, dp, dp]
         L.orc_stop_component.restype = C.c_int
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads.restype = None
         L.orc_tableau.argtypes = [dp] * 5
         L.orc_tableau.restype = None
         L.ddo_integrate.argtypes = [C.POINTER(Problem), dp, dp, C.c_double, C.c_int64, C.c_int64,
@@ -125,6 +127,11 @@ def lib():
         L.orc_split_integrate_batch.restype = C.c_int
         _lib = L
     return _lib
+
+
+def set_threads(n):
+    """Thread count of the oracle's parallel loops (n <= 0: the OpenMP default)."""
+    lib().orc_set_threads(int(n))
 
 
 def _dp(a):

@@ -22,6 +22,12 @@ typedef unsigned long long uint64_t;
 typedef unsigned char uint8_t;
 #endif
 
+}  // namespace irk
+
+#include "store_index.h"
+
+namespace irk {
+
 constexpr int kS = 8;  // stages
 
 // Force kinds (same numbering as the C ABI).
@@ -151,11 +157,7 @@ struct LaunchArgs {
 // has stopped or is already past the limit.
 __device__ __forceinline__ int64_t launch_target(const LaunchArgs& a, int64_t steps_done,
                                                  int64_t nsteps, int32_t status) {
-  int64_t t = nsteps;
-  if (a.step_budget > 0 && steps_done + a.step_budget < t) t = steps_done + a.step_budget;
-  if (a.step_limit > 0 && a.step_limit < t) t = a.step_limit;
-  if (status != kOk || t < steps_done) t = steps_done;
-  return t;
+  return launch_target_of(steps_done, nsteps, status == kOk, a.step_budget, a.step_limit);
 }
 
 // Length of a launch's class queue.

@@ -172,9 +172,10 @@ __global__ __launch_bounds__(64) void nan_fill_kernel(const InstDesc* __restrict
   if (st.status != kNonFinite) return;
   const InstDesc d = desc[i];
   const int dq = d.n * d.d;
-  const int64_t f0 = st.steps_done / d.stride + 1, f1 = d.nsteps / d.stride;
+  const int64_t f0 = first_nan_frame(st.steps_done, d.stride);
+  const int64_t f1 = last_frame_of_launch(d.nsteps, d.stride);
   for (int64_t e = threadIdx.x; e < (f1 - f0 + 1) * dq; e += blockDim.x) {
-    const int64_t o = d.out_off + f0 * dq + e;
+    const int64_t o = frame_index(d.out_off, f0, dq, 0) + e;
     qout[o] = __builtin_nan("");
     if (pout) pout[o] = __builtin_nan("");
   }

@@ -618,6 +618,10 @@ static int integrate_impl(irkgl16_ctx* c, const double* q0, const double* p0, co
     // Plain form with the step loop in a graph: one step's launches (one per
     // instance, single-step budget) captured once, replayed max(nsteps) times.
     HIP_TRY(plain_graph_steps(c, a, nsteps));
+    // An instance that stopped at a non-finite value wrote NaN frames only up
+    // to the end of its one-step launch; the rest are filled here.
+    HIP_TRY(irk::launch_nan_fill(c->d_desc.as<irk::InstDesc>(), c->d_stat.as<irk::InstStat>(),
+                                 dqo, dpo, n, c->stream));
   } else if (c->flags & IRKGL16_PLAIN) {
     // Plain form: one launch per step per instance, instances in turn.
     for (const auto& kc : c->classes) {
@@ -630,6 +634,8 @@ static int integrate_impl(irkgl16_ctx* c, const double* q0, const double* p0, co
         for (int64_t s = 0; s < nsteps[id]; ++s) HIP_TRY(launch_class(c, kc, pa, 1, c->stream));
       }
     }
+    HIP_TRY(irk::launch_nan_fill(c->d_desc.as<irk::InstDesc>(), c->d_stat.as<irk::InstStat>(),
+                                 dqo, dpo, n, c->stream));
   } else {
     // The whole-GPU class (cooperative launches) runs alone on the main
     // stream after the others; the batched classes run concurrently, one

@@ -433,22 +433,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
       const int kslot = kw;
       const int64_t step0 = M.step, stride = M.stride, out_off = M.out_off;
       if (wbad) {  // non-finite: stop this instance, remaining frames NaN
-        const int64_t nf = M.target / stride;  // frames of this launch only
-        for (int64_t f = step0 / stride + 1; f <= nf; ++f) {
+        const int64_t nf = last_frame_of_launch(M.target, stride);  // frames of this launch only
+        for (int64_t f = first_nan_frame(step0, stride); f <= nf; ++f) {
 #pragma unroll
           for (int cc = 0; cc < CPL; ++cc) {
             if (owns(cc)) {
-              a.qout[out_off + f * DQ + comp(cc)] = __builtin_nan("");
-              if constexpr (KIND != kUserOde) a.pout[out_off + f * DQ + comp(cc)] = __builtin_nan("");
+              a.qout[frame_index(out_off, f, DQ, comp(cc))] = __builtin_nan("");
+              if constexpr (KIND != kUserOde)
+                a.pout[frame_index(out_off, f, DQ, comp(cc))] = __builtin_nan("");
             }
           }
           if (SPLIT && tlead) {
-            a.qout[out_off + f * DQ + tcomp] = __builtin_nan("");
-            if constexpr (KIND != kUserOde) a.pout[out_off + f * DQ + tcomp] = __builtin_nan("");
+            a.qout[frame_index(out_off, f, DQ, tcomp)] = __builtin_nan("");
+            if constexpr (KIND != kUserOde) a.pout[frame_index(out_off, f, DQ, tcomp)] = __builtin_nan("");
           }
         }
         if (sub == 0) {
-          if (M.iters_off >= 0) a.step_iters[M.iters_off + step0] = (uint8_t)kslot;
+          if (M.iters_off >= 0) a.step_iters[iters_index(M.iters_off, step0)] = (uint8_t)kslot;
           InstStat st;
           st.steps_done = step0;
           st.iterations = M.it_sum;
@@ -467,7 +468,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
         const double kema = 0.875 * M.kema + 0.125 * (double)kslot;
         const bool evict = !last && a.evict_k > 0.0 && kema >= a.evict_k;
         const bool stop = last || evict;
-        double* St = a.state + M.state_off;
         double R[CPL][S];
         const ConstTab r = row_tab(T);
 #pragma unroll
@@ -479,16 +479,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
             const int c = comp(cc);
             if (frame) {
               const int64_t f = step / stride;
-              a.qout[out_off + f * DQ + c] = qh[cc];
-              if constexpr (KIND != kUserOde) a.pout[out_off + f * DQ + c] = M.m[c / D] * vh[cc];
+              a.qout[frame_index(out_off, f, DQ, c)] = qh[cc];
+              if constexpr (KIND != kUserOde)
+                a.pout[frame_index(out_off, f, DQ, c)] = M.m[c / D] * vh[cc];
             }
             if (stop) {
-              St[c] = qh[cc];
-              St[DQ + c] = ql[cc];
-              St[2 * DQ + c] = vh[cc];
-              St[3 * DQ + c] = vl[cc];
+              a.state[state_index(M.state_off, DQ, 0, c)] = qh[cc];
+              a.state[state_index(M.state_off, DQ, 1, c)] = ql[cc];
+              a.state[state_index(M.state_off, DQ, 2, c)] = vh[cc];
+              a.state[state_index(M.state_off, DQ, 3, c)] = vl[cc];
 #pragma unroll
-              for (int s = 0; s < S; ++s) St[4 * DQ + c * S + s] = R[cc][s];
+              for (int s = 0; s < S; ++s) a.state[rprev_index(M.state_off, DQ, c, s, S)] = R[cc][s];
             }
           }
         }
@@ -504,16 +505,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
           if (tlead) {
             if (frame) {
               const int64_t f = step / stride;
-              a.qout[out_off + f * DQ + tcomp] = tqh;
-              if constexpr (KIND != kUserOde) a.pout[out_off + f * DQ + tcomp] = M.m[tcomp / D] * tvh;
+              a.qout[frame_index(out_off, f, DQ, tcomp)] = tqh;
+              if constexpr (KIND != kUserOde)
+                a.pout[frame_index(out_off, f, DQ, tcomp)] = M.m[tcomp / D] * tvh;
             }
             if (stop) {
-              St[tcomp] = tqh;
-              St[DQ + tcomp] = tql;
-              St[2 * DQ + tcomp] = tvh;
-              St[3 * DQ + tcomp] = tvl;
+              a.state[state_index(M.state_off, DQ, 0, tcomp)] = tqh;
+              a.state[state_index(M.state_off, DQ, 1, tcomp)] = tql;
+              a.state[state_index(M.state_off, DQ, 2, tcomp)] = tvh;
+              a.state[state_index(M.state_off, DQ, 3, tcomp)] = tvl;
 #pragma unroll
-              for (int s = 0; s < S; ++s) St[4 * DQ + tcomp * S + s] = tR[s];
+              for (int s = 0; s < S; ++s) a.state[rprev_index(M.state_off, DQ, tcomp, s, S)] = tR[s];
             }
           }
           if (!stop) {
@@ -523,7 +525,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) void sm
           }
         }
         if (sub == 0) {
-          if (M.iters_off >= 0) a.step_iters[M.iters_off + step0] = (uint8_t)kslot;
+          if (M.iters_off >= 0) a.step_iters[iters_index(M.iters_off, step0)] = (uint8_t)kslot;
           M.step = step;
           M.it_sum += kslot;
           M.nonconv += wok ? 0 : 1;

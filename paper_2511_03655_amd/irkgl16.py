@@ -283,12 +283,25 @@ class Integrator:
         return self
 
     def close(self):
+        """Release the context (synchronizes its stream, frees its device memory)."""
         ctx = getattr(self, "ctx", None)
         if ctx and _lib is not None:
             self.ctx = None
             _lib.irkgl16_destroy(ctx)
 
-    __del__ = close
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        # During interpreter shutdown the HIP runtime, a caller-owned stream or
+        # an attached profiler may already be gone: destroying the context then
+        # (a stream synchronization and hipFree) is not safe, and the process is
+        # about to release the device anyway.  Close contexts explicitly.
+        if not sys.is_finalizing():
+            self.close()
 
     def frames(self, nsteps, stride):
         return np.asarray(nsteps, np.int64) // np.asarray(stride, np.int64) + 1
@@ -444,9 +457,18 @@ class Server:
         return q, p, info, rc
 
     def close(self):
-        if self.srv:
+        """Stop the serving thread after the pending requests and release the server."""
+        if getattr(self, "srv", None):
             irkgl16_server_destroy(self.srv)
             self.srv = None
 
-    __del__ = close
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        if not sys.is_finalizing():  # as Integrator.__del__
+            self.close()
 

@@ -201,14 +201,16 @@ MIX_CLASSES = [("gravity", 3), ("gravity", 6), ("gravity", 16), ("gravity", 64),
                ("chain", 32), ("chain", 256), ("chain", 1024)]
 
 
-def uneven_mix(n_inst=4096, seed=BASE_SEED + 4, steps_range=(1e3, 1e5), classes=None):
+def uneven_mix(n_inst=4096, seed=BASE_SEED + 4, steps_range=(1e3, 1e5), classes=None,
+               step_multiple=100):
     """The uneven batch: classes uniform over MIX_CLASSES, per-instance h and steps.
 
     Gravity systems are generated as planetary_systems with the class's body
     count; their step is h = U(0.05, 1) x 0.5 / w_max with w_max the fastest
     pairwise frequency max_{a<b} sqrt(G (m_a + m_b) / r_ab^3) of the initial
     configuration (star-planet and planet-planet pairs alike).  Steps are
-    log-uniform in steps_range.
+    log-uniform in steps_range, rounded to a multiple of step_multiple (so an
+    output frame can fall on step 1000 of every instance).
     """
     classes = classes or MIX_CLASSES
     out = []
@@ -220,8 +222,8 @@ def uneven_mix(n_inst=4096, seed=BASE_SEED + 4, steps_range=(1e3, 1e5), classes=
             inst["h"] = float(g.uniform(0.05, 1.0) * 0.5 / _max_pair_frequency(inst))
         else:
             inst = fpu_chain(size, seed=sub)
-        inst["nsteps"] = int(round(math.exp(g.uniform(math.log(steps_range[0]),
-                                                      math.log(steps_range[1])))))
+        steps = math.exp(g.uniform(math.log(steps_range[0]), math.log(steps_range[1])))
+        inst["nsteps"] = max(step_multiple, int(round(steps / step_multiple)) * step_multiple)
         inst["cls"] = f"{kind}{size}"
         out.append(inst)
     return out

@@ -298,3 +298,26 @@ def test_nonfinite_instance_frames_across_chunks(monkeypatch):
     assert np.all(np.isnan(p[6:6 * nfr]))
     assert np.array_equal(q[6 * nfr:], out["1"][0][6 * nfr:])
     assert np.array_equal(p[6 * nfr:], out["1"][1][6 * nfr:])
+
+
+@pytest.mark.parametrize("flags", [K.IRKGL16_PLAIN, K.IRKGL16_PLAIN | K.IRKGL16_GRAPH])
+def test_plain_form_fills_frames_after_a_nonfinite_step(flags):
+    """The plain form (one launch per step) stops an instance at its first
+    non-finite step; every later frame is NaN even though the launches after
+    it do no work for that instance.  The context's output buffer first holds
+    finite frames of an ordinary call, so frames left unwritten would show."""
+    m = np.array([1.0, 1.0])
+    prob = dict(kind=K.IRKGL16_GRAVITY, n=2, d=3, mass=m, G=1.0, eps=0.0)
+    good_q = np.array([1.0, 0, 0, -1.0, 0, 0])
+    good_p = np.array([0, 0.5, 0, 0, -0.5, 0])
+    integ = K.Integrator([prob, prob], flags=flags)
+    q, p, st, rc = integ.integrate(np.tile(good_q, 2), np.tile(good_p, 2), 0.05, 12, 2)
+    assert rc == 0 and np.all(np.isfinite(q))
+    bad_q, bad_p = np.zeros(6), np.zeros(6)  # coincident bodies at rest, no softening
+    q, p, st, rc = integ.integrate(np.concatenate([bad_q, good_q]),
+                                   np.concatenate([bad_p, good_p]), 0.05, 12, 2)
+    integ.close()
+    assert rc == K.IRKGL16_ENONFINITE and st["inst_status"][0] == K.IRKGL16_ENONFINITE
+    q, p = q.reshape(2, 7, 6), p.reshape(2, 7, 6)
+    assert np.all(np.isnan(q[0, 1:])) and np.all(np.isnan(p[0, 1:]))
+    assert np.all(np.isfinite(q[1])) and np.all(np.isfinite(p[1]))

@@ -240,6 +240,31 @@ def test_gravity_force_brute_force_and_momentum(orc):
         assert np.max(np.abs(mom)) < 1e-13
 
 
+def test_fpu_beta_force_and_energy_by_hand(orc):
+    """The FPU-beta chain written out by hand, independently of the oracle's
+    own energy: V(s) = s^2/2 + beta s^4/4 per bond, V'(s) = s + beta s^3, fixed
+    ends q_0 = q_{n+1} = 0.
+    One site between the ends: both bonds pull it back, g = -2 (q + beta q^3).
+    Two sites with bond stiffnesses (1, 3, 1/2), masses (2, 4), beta = 2 at
+    q = (1/2, -1/4): bond stretches s = (1/2, -3/4, 1/4), V'(s) = (3/4, -51/32,
+    9/32), so g_1 = (3 (-51/32) - 3/4) / 2 = -177/64 and g_2 = ((1/2)(9/32) -
+    3 (-51/32)) / 4 = 315/256; U = 1/8 + 1/32 + 3 (9/32 + 81/512) + (1/2)(1/32 +
+    1/512) = 1527/1024.  Every value is a dyadic rational, exact in binary64."""
+    for beta in (0.0, 0.5, 1.0, 3.0):
+        sp = orc.Spec(orc.CHAIN, 1, 1, beta=beta)
+        for q in (0.1, -0.37, 1.25):
+            with mpmath.workdps(40):
+                want = -2 * (mpmath.mpf(q) + mpmath.mpf(beta) * mpmath.mpf(q) ** 3)
+            got = orc.force(sp, np.array([q]))[0]
+            assert abs(got - want) <= 2e-16 * abs(want), (beta, q)
+    sp = orc.Spec(orc.CHAIN, 2, 1, mass=np.array([2.0, 4.0]),
+                  coupling=np.array([1.0, 3.0, 0.5]), beta=2.0)
+    q = np.array([0.5, -0.25])
+    assert np.array_equal(orc.force(sp, q), [-177 / 64, 315 / 256])
+    assert orc.energy(sp, q, np.zeros(2)) == 1527 / 1024
+    assert orc.energy(sp, q, np.array([1.0, 2.0])) == 1527 / 1024 + 1 / 4 + 1 / 2
+
+
 def test_forces_are_minus_gradient(orc):
     rng = np.random.default_rng(4)
     cases = [
