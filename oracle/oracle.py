@@ -23,7 +23,10 @@ import subprocess
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liborc.so")
+# IRKGL16_ORACLE_LIB names a prebuilt copy to load instead (the CPU tests'
+# sanitizer build); it is loaded as given, never rebuilt.
+LIB_OVERRIDE = os.environ.get("IRKGL16_ORACLE_LIB")
+LIB_PATH = LIB_OVERRIDE or os.path.join(HERE, "liborc.so")
 SOURCES = ["irkgl16_oracle.c", "irkgl16_dd.c", "irkgl16_ode.c", "irkgl16_split.c"]
 
 KEPLER, GRAVITY, CHAIN, HARMONIC, CONST, HENON = 0, 1, 2, 10, 11, 12
@@ -36,17 +39,20 @@ FLAG_NO_COMPENSATION, FLAG_NAIVE_ETA, FLAG_NO_EXTRAPOLATION = 1, 2, 4
 OK, EINVAL, ENOMEM, ENONFINITE, ENOCONV = 0, -1, -2, -4, 1
 
 
-def build(force=True):
-    """Compile the oracle shared library (gcc, strict IEEE binary64)."""
-    if not force and os.path.exists(LIB_PATH):
-        return LIB_PATH
+def build(force=True, out=None, extra_flags=()):
+    """Compile the oracle shared library (gcc, strict IEEE binary64).
+    extra_flags: added options (the sanitizer build of the CPU tests)."""
+    out = out or os.path.join(HERE, "liborc.so")
+    if not force and os.path.exists(out):
+        return out
     srcs = [os.path.join(HERE, s) for s in SOURCES]
-    tmp = LIB_PATH + ".tmp"
+    tmp = out + ".tmp"
     cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
-           "-shared", "-fPIC", "-Wall", "-Wno-unknown-pragmas", "-o", tmp] + srcs + ["-lm"]
+           "-shared", "-fPIC", "-Wall", "-Wno-unknown-pragmas", *extra_flags, "-o", tmp] + srcs + \
+          ["-lm"]
     subprocess.check_call(cmd, cwd=HERE)
-    os.replace(tmp, LIB_PATH)
-    return LIB_PATH
+    os.replace(tmp, out)
+    return out
 
 
 class Problem(C.Structure):
@@ -67,8 +73,8 @@ def lib():
     global _lib
     if _lib is None:
         srcs = [os.path.join(HERE, s) for s in SOURCES] + [os.path.join(HERE, "tableau.h")]
-        if not os.path.exists(LIB_PATH) or any(
-                os.path.getmtime(s) > os.path.getmtime(LIB_PATH) for s in srcs):
+        if not LIB_OVERRIDE and (not os.path.exists(LIB_PATH) or any(
+                os.path.getmtime(s) > os.path.getmtime(LIB_PATH) for s in srcs)):
             build()
         L = C.CDLL(LIB_PATH)
         dp, i64p, i32p = C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int32)

@@ -21,6 +21,7 @@
 
 #include "../../include/irkgl16.h"
 #include "device_common.h"
+#include "host_common.h"
 #include "launch.h"
 
 
@@ -63,9 +64,12 @@ struct DevBuf {
   }
 };
 
-bool finite(double x) { return std::isfinite(x); }
+}  // namespace
+
+namespace irk {
 
 int validate_problem(const irkgl16_problem& p) {
+  auto finite = [](double x) { return std::isfinite(x); };
   if (p.n < 1 || p.d < 1 || p.d > 3) return IRKGL16_EINVAL;
   switch (p.kind) {
     case IRKGL16_KEPLER:
@@ -90,7 +94,37 @@ int validate_problem(const irkgl16_problem& p) {
   }
 }
 
-}  // namespace
+int summarize_stats(const InstStat* h_stat, int32_t n, irkgl16_stats* stats) {
+  int worst = IRKGL16_OK;
+  int64_t steps = 0, iters = 0, nonconv = 0;
+  int32_t maxk = 0, nnf = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const InstStat& s = h_stat[i];
+    steps += s.steps_done;
+    iters += s.iterations;
+    nonconv += s.nonconv;
+    maxk = std::max(maxk, s.max_k);
+    int st = s.status;
+    if (st == kOk && s.nonconv > 0) st = IRKGL16_ENOCONV;
+    if (s.status == kNonFinite) ++nnf;
+    if (st < 0 && (worst >= 0 || st < worst)) worst = st;
+    if (st > 0 && worst == IRKGL16_OK) worst = st;
+    if (stats) {
+      if (stats->inst_iterations) stats->inst_iterations[i] = s.iterations;
+      if (stats->inst_status) stats->inst_status[i] = st;
+    }
+  }
+  if (stats) {
+    stats->steps = steps;
+    stats->iterations = iters;
+    stats->nonconverged_steps = nonconv;
+    stats->max_k = maxk;
+    stats->n_nonfinite = nnf;
+  }
+  return worst;
+}
+
+}  // namespace irk
 
 struct irkgl16_ctx {
   int device = 0;
@@ -214,7 +248,7 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
       if (!std::isfinite(user->params[k])) return IRKGL16_EINVAL;
   } else {
     for (int32_t i = 0; i < n_inst; ++i) {
-      int rc = validate_problem(probs[i]);
+      int rc = irk::validate_problem(probs[i]);
       if (rc != IRKGL16_OK) return rc;
     }
   }
@@ -890,31 +924,8 @@ int irkgl16_last_stats(irkgl16_ctx* c, irkgl16_stats* stats) {
         c->last_ms = 0.f;
       c->last_synced = true;
     }
-    int worst = IRKGL16_OK;
-    int64_t steps = 0, iters = 0, nonconv = 0;
-    int32_t maxk = 0, nnf = 0;
-    for (int32_t i = 0; i < c->n_inst; ++i) {
-      const irk::InstStat& s = c->h_stat[i];
-      steps += s.steps_done;
-      iters += s.iterations;
-      nonconv += s.nonconv;
-      maxk = std::max(maxk, s.max_k);
-      int st = s.status;
-      if (st == irk::kOk && s.nonconv > 0) st = IRKGL16_ENOCONV;
-      if (s.status == irk::kNonFinite) ++nnf;
-      if (st < 0 && (worst >= 0 || st < worst)) worst = st;
-      if (st > 0 && worst == IRKGL16_OK) worst = st;
-      if (stats) {
-        if (stats->inst_iterations) stats->inst_iterations[i] = s.iterations;
-        if (stats->inst_status) stats->inst_status[i] = st;
-      }
-    }
+    const int worst = irk::summarize_stats(c->h_stat.data(), c->n_inst, stats);
     if (stats) {
-      stats->steps = steps;
-      stats->iterations = iters;
-      stats->nonconverged_steps = nonconv;
-      stats->max_k = maxk;
-      stats->n_nonfinite = nnf;
       stats->device_ms = (double)c->last_ms;
       if (stats->step_iters && c->record && c->last_iters_total > 0)
         HIP_TRY(hipMemcpy(stats->step_iters, c->d_iters.p, (size_t)c->last_iters_total,

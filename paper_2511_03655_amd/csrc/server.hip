@@ -31,6 +31,7 @@
 
 #include "../../include/irkgl16.h"
 #include "device_common.h"
+#include "host_common.h"
 #include "launch.h"
 
 namespace {
@@ -174,24 +175,9 @@ struct irkgl16_server {
 };
 
 static int validate(const irkgl16_problem& p) {
-  if (p.n < 1 || p.d < 1 || p.d > 3) return IRKGL16_EINVAL;
   int S = 0;
-  if (irk::kernel_class(p.kind, p.n, p.d, &S) < 0) return IRKGL16_EINVAL;
-  if (p.kind == IRKGL16_GRAVITY) {
-    if (!p.mass || !std::isfinite(p.G) || !std::isfinite(p.eps) || p.eps < 0) return IRKGL16_EINVAL;
-    for (int a = 0; a < p.n; ++a)
-      if (!(p.mass[a] > 0) || !std::isfinite(p.mass[a])) return IRKGL16_EINVAL;
-  } else if (p.kind == IRKGL16_KEPLER) {
-    if (!std::isfinite(p.G)) return IRKGL16_EINVAL;
-  } else if (p.kind == IRKGL16_CHAIN) {
-    if (!std::isfinite(p.beta)) return IRKGL16_EINVAL;
-    if (p.mass)
-      for (int a = 0; a < p.n; ++a)
-        if (!(p.mass[a] > 0) || !std::isfinite(p.mass[a])) return IRKGL16_EINVAL;
-    if (p.coupling)
-      for (int a = 0; a <= p.n; ++a)
-        if (!std::isfinite(p.coupling[a])) return IRKGL16_EINVAL;
-  }
+  if (irk::validate_problem(p) != IRKGL16_OK || irk::kernel_class(p.kind, p.n, p.d, &S) < 0)
+    return IRKGL16_EINVAL;
   return IRKGL16_OK;
 }
 

@@ -20,7 +20,9 @@ import sys
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libirkgl16.so")
+# IRKGL16_LIB names another build of the same library (the CPU tests' sanitizer
+# build); there is no other implementation to fall back to.
+LIB_PATH = os.environ.get("IRKGL16_LIB") or os.path.join(HERE, "libirkgl16.so")
 
 IRKGL16_OK, IRKGL16_EINVAL, IRKGL16_ENOMEM, IRKGL16_EDEVICE = 0, -1, -2, -3
 IRKGL16_ENONFINITE, IRKGL16_ENOCONV = -4, 1
