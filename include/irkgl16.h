@@ -31,6 +31,8 @@ extern "C" {
 #define IRKGL16_ENOMEM (-2)     /* host or device allocation failed              */
 #define IRKGL16_EDEVICE (-3)    /* no usable GPU, or a HIP runtime error         */
 #define IRKGL16_ENONFINITE (-4) /* an instance produced NaN/Inf (others written) */
+#define IRKGL16_ESCRATCH (-5)   /* irkgl16_integrate_static: the call needs more  */
+                                /* than the fixed scratch (size limits below)     */
 #define IRKGL16_ENOCONV 1       /* warning: some steps stopped at max_iter       */
 
 /* ---- force kinds -------------------------------------------------------- */
@@ -233,6 +235,52 @@ void irkgl16_destroy(irkgl16_ctx *ctx);
 
 /* Static description of a status code. */
 const char *irkgl16_strerror(int status);
+
+/* ---- allocation-free integration ----------------------------------------
+ * For callers that cannot allocate device memory while they integrate: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  One call does what irkgl16_create + irkgl16_integrate (with
+ * IRKGL16_DEVICE_PTRS) + irkgl16_destroy do, with the same kernels and the
+ * same results bit for bit, but calls no device or host allocator: the
+ * per-call device data (coefficient table, instance descriptors, masses and
+ * couplings, class work queues and their counters, per-instance statistics,
+ * the resumable state records, iteration counts) lives in one fixed device
+ * array of IRKGL16_STATIC_SCRATCH_BYTES per GPU, which exists from the
+ * library's loading on that GPU until the process ends, and the host side
+ * stages through fixed arrays.  The first call on a GPU looks up that array's
+ * device address and creates three HIP events (kept until the process ends).
+ *
+ * probs, h, nsteps, out_stride: host memory, as irkgl16_create and
+ *   irkgl16_integrate (read during the call).
+ * q0, p0, q_out, p_out: DEVICE memory, layouts as irkgl16_integrate.
+ * opt: nullable; flags may hold IRKGL16_REPRODUCIBLE (IRKGL16_DEVICE_PTRS is
+ *   implied); stages 0 or 8, method 0; max_iter and record_iters as in
+ *   irkgl16_options.
+ * hip_stream: the hipStream_t the work is enqueued on (NULL: the null stream).
+ * stats: nullable; when given, the call synchronizes the stream and fills it
+ *   (step_iters only with record_iters); otherwise it returns after enqueueing
+ *   and the caller synchronizes.
+ * Scope: instances of the batched kernel classes -- Kepler, gravity up to 512
+ *   bodies, FPU-beta chains up to 1024 sites; one launch per class, in turn on
+ *   the one stream (no chunks, no promotion: those change only the schedule).
+ *   A gravitational system of more than 512 bodies (whole-GPU kernel) is
+ *   IRKGL16_EINVAL, as are the flags, stages or methods not listed above.
+ * Limits: at most IRKGL16_STATIC_MAX_INST instances, and the call's scratch
+ *   ((4 + 8) Dq doubles = 96 Dq bytes of state per instance, plus descriptors,
+ *   statistics, masses, queues and, with record_iters, one byte per step)
+ *   must fit IRKGL16_STATIC_SCRATCH_BYTES; otherwise IRKGL16_ESCRATCH, before
+ *   any device work.
+ * Concurrency: every call on a GPU reuses that GPU's array and keeps nothing
+ *   from earlier calls (the setup kernel rewrites what must start at zero).
+ *   Calls are serialized on the host; calls enqueued on different streams of
+ *   one GPU without synchronization between them race on the array. */
+#define IRKGL16_STATIC_SCRATCH_BYTES (32ll << 20)
+#define IRKGL16_STATIC_MAX_INST 16384
+int irkgl16_integrate_static(const irkgl16_problem *probs, int32_t n_inst,
+                             const irkgl16_options *opt, void *hip_stream, const double *q0,
+                             const double *p0, const double *h, const int64_t *nsteps,
+                             const int64_t *out_stride, double *q_out, double *p_out,
+                             irkgl16_stats *stats);
 
 /* ---- serving ------------------------------------------------------------
  * A server integrates requests that arrive over time with continuous batching:

@@ -951,6 +951,8 @@ const char* irkgl16_strerror(int status) {
     case IRKGL16_EDEVICE: return "no usable gfx950 GPU or HIP runtime error";
     case IRKGL16_ENONFINITE: return "an instance produced a non-finite value";
     case IRKGL16_ENOCONV: return "some steps stopped at the iteration cap";
+    case IRKGL16_ESCRATCH:
+      return "the call does not fit the fixed scratch of irkgl16_integrate_static";
     default: return "unknown status";
   }
 }

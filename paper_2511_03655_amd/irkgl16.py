@@ -25,7 +25,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("IRKGL16_LIB") or os.path.join(HERE, "libirkgl16.so")
 
 IRKGL16_OK, IRKGL16_EINVAL, IRKGL16_ENOMEM, IRKGL16_EDEVICE = 0, -1, -2, -3
-IRKGL16_ENONFINITE, IRKGL16_ENOCONV = -4, 1
+IRKGL16_ENONFINITE, IRKGL16_ENOCONV, IRKGL16_ESCRATCH = -4, 1, -5
+IRKGL16_STATIC_SCRATCH_BYTES, IRKGL16_STATIC_MAX_INST = 32 << 20, 16384
 IRKGL16_KEPLER, IRKGL16_GRAVITY, IRKGL16_CHAIN = 0, 1, 2
 IRKGL16_DEVICE_PTRS, IRKGL16_PLAIN, IRKGL16_REPRODUCIBLE, IRKGL16_GRAPH = 1, 2, 4, 8
 IRKGL16_STRANG, IRKGL16_SUZ90 = 1, 2  # irkgl16_options.method: explicit baselines
@@ -33,7 +34,8 @@ IRKGL16_STRANG, IRKGL16_SUZ90 = 1, 2  # irkgl16_options.method: explicit baselin
 EXPORTED = ["irkgl16_create", "irkgl16_integrate", "irkgl16_last_stats", "irkgl16_destroy",
             "irkgl16_strerror", "irkgl16_server_create", "irkgl16_submit", "irkgl16_poll",
             "irkgl16_wait", "irkgl16_server_destroy", "irkgl16_create_user",
-            "irkgl16_user_compile_check", "irkgl16_create_ode", "irkgl16_ode_compile_check"]
+            "irkgl16_user_compile_check", "irkgl16_create_ode", "irkgl16_ode_compile_check",
+            "irkgl16_integrate_static"]
 
 
 class irkgl16_problem(C.Structure):
@@ -122,6 +124,11 @@ def lib():
         L.irkgl16_create_ode.restype = C.c_int
         L.irkgl16_ode_compile_check.argtypes = [C.c_char_p, C.c_int32, C.c_char_p, C.c_int64]
         L.irkgl16_ode_compile_check.restype = C.c_int
+        L.irkgl16_integrate_static.argtypes = [C.POINTER(irkgl16_problem), C.c_int32,
+                                               C.POINTER(irkgl16_options), C.c_void_p,
+                                               C.c_void_p, C.c_void_p, dp, i64p, i64p,
+                                               C.c_void_p, C.c_void_p, C.POINTER(irkgl16_stats)]
+        L.irkgl16_integrate_static.restype = C.c_int
         _lib = L
     return _lib
 
@@ -233,6 +240,35 @@ def irkgl16_integrate(ctx, q0, p0, h, nsteps, out_stride, q_out, p_out, stats=No
                                    ns.ctypes.data_as(C.POINTER(C.c_int64)),
                                    sd.ctypes.data_as(C.POINTER(C.c_int64)), _ptr(q_out),
                                    _ptr(p_out), C.byref(stats) if stats is not None else None)
+
+
+def irkgl16_integrate_static(problems, q0, p0, h, nsteps, out_stride, q_out, p_out,
+                             max_iter=0, record_iters=False, flags=0, stream=None, stats=None):
+    """Allocation-free integration (create + integrate + destroy in one call,
+    scratch in the library's fixed device array).  q0, p0, q_out, p_out: torch
+    CUDA tensors (float64) or raw device addresses; h, nsteps, out_stride: one
+    value per instance (host).  stats: an irkgl16_stats or None.  Returns the
+    status code."""
+    keep = []
+    n = len(problems)
+    arr = (irkgl16_problem * max(n, 1))()
+    for i, p in enumerate(problems):
+        arr[i] = _problem_struct(p, keep)
+    opt = irkgl16_options(int(max_iter), int(bool(record_iters)), int(flags))
+    if stream is not None and hasattr(stream, "cuda_stream"):
+        stream = stream.cuda_stream
+    h = np.ascontiguousarray(np.broadcast_to(np.asarray(h, np.float64), (n,)))
+    ns = np.ascontiguousarray(np.broadcast_to(np.asarray(nsteps, np.int64), (n,)))
+    sd = np.ascontiguousarray(np.broadcast_to(np.asarray(out_stride, np.int64), (n,)))
+
+    def addr(x):
+        return C.c_void_p(int(x)) if isinstance(x, int) else _ptr(x)
+
+    return lib().irkgl16_integrate_static(
+        arr, n, C.byref(opt), C.c_void_p(stream) if stream else None, addr(q0), addr(p0),
+        h.ctypes.data_as(C.POINTER(C.c_double)), ns.ctypes.data_as(C.POINTER(C.c_int64)),
+        sd.ctypes.data_as(C.POINTER(C.c_int64)), addr(q_out), addr(p_out),
+        C.byref(stats) if stats is not None else None)
 
 
 def irkgl16_last_stats(ctx, stats):

@@ -28,7 +28,7 @@ def test_header_symbols_are_exported():
 
 
 def test_strerror_covers_codes():
-    for code in (0, -1, -2, -3, -4, 1):
+    for code in (0, -1, -2, -3, -4, -5, 1):
         assert K.irkgl16_strerror(code) != "unknown status"
     assert K.irkgl16_strerror(12345) == "unknown status"
 
@@ -270,3 +270,41 @@ def test_one_hip_runtime_with_torch():
     import ast
     paths = ast.literal_eval(out.stdout.strip().splitlines()[-1])
     assert len(paths) == 1, paths
+
+
+# ---- allocation-free entry point: argument and size checks come before any
+# device call, so they hold without a GPU
+
+def _static(problems, flags=0, h=0.1, nsteps=10, stride=10):
+    return K.irkgl16_integrate_static(problems, 8, 8, h, nsteps, stride, 8, 8, flags=flags)
+
+
+def test_static_entry_point_rejects_beyond_its_scratch():
+    kep = dict(kind=K.IRKGL16_KEPLER, n=1, d=2, G=1.0)
+    assert _static([kep] * (K.IRKGL16_STATIC_MAX_INST + 1)) == K.IRKGL16_ESCRATCH
+    chain = dict(kind=K.IRKGL16_CHAIN, n=1024, d=1, beta=1.0)
+    # 96 Dq bytes of state per chain: 400 chains of 1024 sites need 39 MB
+    assert _static([chain] * 400) == K.IRKGL16_ESCRATCH
+
+
+@pytest.mark.parametrize("case", ["plain", "graph", "large", "stride", "h"])
+def test_static_entry_point_rejects_what_it_does_not_serve(case):
+    kep = dict(kind=K.IRKGL16_KEPLER, n=1, d=2, G=1.0)
+    if case == "plain":
+        assert _static([kep], flags=K.IRKGL16_PLAIN) == K.IRKGL16_EINVAL
+    elif case == "graph":
+        assert _static([kep], flags=K.IRKGL16_PLAIN | K.IRKGL16_GRAPH) == K.IRKGL16_EINVAL
+    elif case == "large":  # a system for the whole-GPU kernel
+        big = dict(kind=K.IRKGL16_GRAVITY, n=600, d=3, mass=np.full(600, 1 / 600), G=1.0)
+        assert _static([big]) == K.IRKGL16_EINVAL
+    elif case == "stride":
+        assert _static([kep], nsteps=10, stride=3) == K.IRKGL16_EINVAL
+    else:
+        assert _static([kep], h=float("nan")) == K.IRKGL16_EINVAL
+
+
+@pytest.mark.skipif(_has_gpu(), reason="checks the no-device path")
+def test_static_entry_point_without_gpu_reports_edevice():
+    kep = dict(kind=K.IRKGL16_KEPLER, n=1, d=2, G=1.0)
+    assert _static([kep]) == K.IRKGL16_EDEVICE
+    assert _static([]) == K.IRKGL16_OK  # nothing to do: no device needed
