@@ -35,6 +35,15 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+# The kernel classes of one integration call run concurrently on auxiliary
+# streams, but HIP runs the kernels of streams that share a hardware queue one
+# after another, and a process gets GPU_MAX_HW_QUEUES queues (4 by default,
+# two of them taken by the default and the caller's streams).  With 8 the seven
+# classes of the uneven mix overlap: 8.9-10.0 s per call instead of 10.1-11.0 s;
+# the ensemble call gains about 1 %.  Read when HIP initialises, so set here,
+# before anything imports torch.
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+
 METRIC = "FP64 IRKGL16 steps/s, batched vs plain, at rel err<=1e-12; p50/p99 solve latency"
 N_INST, N_BODIES, D, NSTEPS, H = 65536, 6, 3, 10_000, 1.0
 FP64_PEAK_TFLOPS = 78.6
@@ -146,6 +155,98 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 3}))
 
 
+def accuracy_sample(probs, mass, q0, p0, dq, nsteps, stream, K, n_glob=4096, n_loc=256,
+                    loc_steps=1000):
+    """Energy-error statistics on a sample of the same workload (eqs. DHglobmax and
+    DHlocmax) and the fixed-point iteration histogram, outside the timed region.
+    Global: the first n_glob systems over the full run, every 100 steps, with the
+    iteration count of every step recorded.  Local: the first n_loc systems, every
+    step of the first loc_steps."""
+    import torch
+    dev = torch.device("cuda:0")
+    out = {}
+    stride = 100
+    nf = nsteps // stride + 1
+    with K.Integrator(probs[:n_glob], record_iters=True) as it:
+        qg, pg, st, rc = it.integrate(q0[:n_glob * dq], p0[:n_glob * dq], H, nsteps, stride)
+    m = mass[:n_glob]
+    Q, P = qg.reshape(n_glob, nf, dq), pg.reshape(n_glob, nf, dq)
+    E = np.stack([gravity_energy(m, Q[:, f], P[:, f]) for f in range(nf)], 1)
+    dglob = np.max(np.abs(E / E[:, :1] - 1), 1)
+    k = st["step_iters"].astype(np.int64)
+    hist = np.bincount(k, minlength=int(k.max()) + 1)
+    out["DHglob_max"] = {"definition": "max over frames (every 100 steps) of |H_n - H_0|/|H_0| "
+                                       "(eq. DHglobmax) per system",
+                         "sample": f"first {n_glob} systems, full run",
+                         "pass_frac_1e-12": float(np.mean(dglob <= 1e-12)),
+                         "median": float(np.median(dglob)), "p90": float(np.percentile(dglob, 90)),
+                         "max": float(dglob.max())}
+    out["iterations_per_step_histogram"] = {
+        "sample": f"first {n_glob} systems, every step of the full run",
+        "counts_by_k": {str(i): int(c) for i, c in enumerate(hist) if c},
+        "mean": float(k.mean())}
+    with K.Integrator(probs[:n_loc]) as it:
+        ql, pl, _, _ = it.integrate(q0[:n_loc * dq], p0[:n_loc * dq], H, loc_steps, 1)
+    Q, P = ql.reshape(n_loc, loc_steps + 1, dq), pl.reshape(n_loc, loc_steps + 1, dq)
+    m = mass[:n_loc]
+    E = np.stack([gravity_energy(m, Q[:, f], P[:, f]) for f in range(loc_steps + 1)], 1)
+    dloc = np.max(np.abs((E[:, 1:] - E[:, :-1]) / E[:, :-1]), 1)
+    out["DHloc_max"] = {"definition": "max over steps of |H_n - H_{n-1}|/|H_{n-1}| "
+                                      "(eq. DHlocmax) per system",
+                        "sample": f"first {n_loc} systems, every step of the first "
+                                  f"{loc_steps}",
+                        "median": float(np.median(dloc)), "p90": float(np.percentile(dloc, 90)),
+                        "max": float(dloc.max())}
+    return out
+
+
+def bulk_and_critical_path(probs, q0, p0, dq, nsteps, inst_it, stream, K, flops_fn):
+    """The same call without the 1 % of systems that needed the most fixed-point
+    iterations (close encounters), and the single most-iterating system alone:
+    the bulk rate and the serial critical path of the call."""
+    import torch
+    dev = torch.device("cuda:0")
+    n = len(probs)
+    order = np.argsort(inst_it)
+    keep = np.sort(order[: n - n // 100])
+    pk = [probs[i] for i in keep]
+    qk = np.concatenate([q0[i * dq:(i + 1) * dq] for i in keep])
+    pkv = np.concatenate([p0[i * dq:(i + 1) * dq] for i in keep])
+    res = {}
+    with K.Integrator(pk, flags=K.IRKGL16_DEVICE_PTRS, stream=stream) as it:
+        qd = torch.from_numpy(qk).to(dev)
+        pd = torch.from_numpy(pkv).to(dev)
+        qo = torch.empty(len(keep) * dq * 2, dtype=torch.float64, device=dev)
+        po = torch.empty_like(qo)
+        times = []
+        for _ in range(2):
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            K.irkgl16_integrate(it.ctx, qd, pd, np.full(len(keep), H),
+                                np.full(len(keep), nsteps, np.int64),
+                                np.full(len(keep), nsteps, np.int64), qo, po)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1) / 1e3)
+        st, _ = it.last_stats()
+    dt = min(times)
+    res["bulk"] = {"sample": f"the call without the {n - len(keep)} systems (1 %) with the "
+                             "most fixed-point iterations",
+                   "value": len(keep) * nsteps / dt, "unit": "instance-steps/s",
+                   "seconds": dt, "mean_iterations_per_step": st["iterations"] / (len(keep) * nsteps),
+                   "roofline_frac": flops_fn(st["iterations"], len(keep) * nsteps) / dt / 1e12
+                   / FP64_PEAK_TFLOPS}
+    j = int(order[-1])
+    with K.Integrator([probs[j]]) as it:
+        _, _, st1, _ = it.integrate(q0[j * dq:(j + 1) * dq], p0[j * dq:(j + 1) * dq], H, nsteps,
+                                    nsteps)
+    res["critical_path"] = {"sample": f"system {j} (most fixed-point iterations) alone",
+                            "seconds": st1["device_ms"] / 1e3,
+                            "mean_iterations_per_step": st1["iterations"] / nsteps}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,9 +322,18 @@ def main():
     inst_steps = n_inst * nsteps
     value = args.steps * inst_steps / elapsed
     iters = int(stats["iterations"])
-    flops = iters * flops_per_iteration(N_BODIES, dq) + inst_steps * flops_per_step_fixed(dq)
+
+    def call_flops(iterations, instance_steps):
+        return iterations * flops_per_iteration(N_BODIES, dq) + \
+            instance_steps * flops_per_step_fixed(dq)
+
+    flops = call_flops(iters, inst_steps)
     avg_s = float(np.mean(kernel_ms)) / 1e3
     achieved = flops / avg_s / 1e12
+    tail = None
+    if not args.no_plain:
+        tail = bulk_and_critical_path(probs, q0, p0, dq, nsteps, stats["inst_iterations"],
+                                      stream, K, call_flops)
 
     # accuracy gate on the last call's output frames (first and last)
     qo = q_out.cpu().numpy().reshape(n_inst, 2, dq)
@@ -232,10 +342,18 @@ def main():
     E1 = gravity_energy(mass, qo[:, 1], po[:, 1])
     dE = np.abs(E1 / E0 - 1)
     gate = float(np.mean(dE <= 1e-12))
+    inst_it = stats["inst_iterations"]
+    accuracy = {"gate": "relative energy error first->last frame <= 1e-12 (every instance)",
+                "pass_frac": gate, "median_dE": float(np.median(dE)),
+                "steps_at_max_iter": int(stats["nonconverged_steps"]),
+                "instances_with_capped_steps": int(np.sum(stats["inst_status"] ==
+                                                          K.IRKGL16_ENOCONV))}
+    if not args.no_plain:
+        accuracy.update(accuracy_sample(probs, mass, q0, p0, dq, nsteps, stream, K))
 
     plain = None
     if not args.no_plain:
-        n_p, s_p = 64, 200
+        n_p, s_p = 1024, 1000
         pi = K.Integrator(probs[:n_p], flags=K.IRKGL16_PLAIN)
         pi.integrate(q0[:n_p * dq], p0[:n_p * dq], H, 20, 20)  # warm-up
         t = time.perf_counter()
@@ -322,8 +440,8 @@ def main():
                                "chunks, stage_kernel for promoted instances, queue-order kernels",
                      "kernel_ms": float(np.mean(kernel_ms)),
                      "algorithmic_flops_per_launch": flops},
-        "accuracy": {"gate": "relative energy error first->last frame <= 1e-12",
-                     "pass_frac": gate, "median_dE": float(np.median(dE))},
+        "accuracy": accuracy,
+        "stragglers": tail,
         "plain": plain,
         "reproducible": repro,
         "served": served,
@@ -506,6 +624,20 @@ def run_c4(args):
     integ.close()
     plain.close()
     bat.close()
+    # serial critical path: the call cannot end before its slowest instance,
+    # and one instance runs on one CU (or one slot); the three instances with
+    # the most work (iterations x per-iteration cost) timed alone
+    cost = np.array([it * (m["n"] ** 2 if m["kind"] == 1 else m["n"]) for m, it in zip(mix, its)])
+    crit = []
+    for i in np.argsort(cost)[-3:][::-1]:
+        m = mix[int(i)]
+        with K.Integrator([probs[int(i)]]) as one:
+            _, _, s1, _ = one.integrate(m["q"], m["p"], m["h"], m["nsteps"], m["nsteps"])
+        crit.append({"instance": int(i), "class": m["cls"], "steps": int(m["nsteps"]),
+                     "mean_iterations_per_step": s1["iterations"] / m["nsteps"],
+                     "seconds_alone": s1["device_ms"] / 1e3})
+    print(f"c4: critical path {max(c['seconds_alone'] for c in crit):.2f} s", file=sys.stderr,
+          flush=True)
     specs = [orc.Spec(mix[i]["kind"], mix[i]["n"], mix[i]["d"], mass=mix[i].get("mass"),
                       G=mix[i].get("G", 1.0), beta=mix[i].get("beta", 0.0)) for i in sample]
     t = time.perf_counter()
@@ -518,6 +650,9 @@ def run_c4(args):
                     "roofline": {"bound": "alu", "achieved": flops / dt / 1e12,
                                  "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                                  "frac": flops / dt / 1e12 / FP64_PEAK_TFLOPS, "traffic": None},
+                    "critical_path": {"instances_alone": crit,
+                                      "call_over_longest_alone":
+                                          dt / max(c["seconds_alone"] for c in crit)},
                     "plain": {"value": len(sample) * 100 / dtp, "unit": "instance-steps/s",
                               "batched_same_sample": len(sample) * 100 / dtb,
                               "sample": f"{len(sample)} instances (2 per class) x 100 steps"},

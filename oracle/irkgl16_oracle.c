@@ -120,6 +120,26 @@ static double mass_of(const orc_problem *p, int body) {
 
 static double dV(double s, double beta) { return s + beta * (s * s * s); }
 
+/* Softened Newtonian acceleration of body a (eq. Ham2): sources b != a in
+ * ascending order. */
+static void gravity_target(const orc_problem *p, const double *Q, double *G, int a) {
+  const int n = p->n, d = p->d;
+  const double eps2 = p->eps * p->eps;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int b = 0; b < n; ++b) {
+    if (b == a) continue;
+    double dx[3], r2 = 0.0;
+    for (int k = 0; k < d; ++k) {
+      dx[k] = Q[b * d + k] - Q[a * d + k];
+      r2 += dx[k] * dx[k];
+    }
+    r2 += eps2;
+    double w = p->mass[b] / (r2 * sqrt(r2));
+    for (int k = 0; k < d; ++k) acc[k] += w * dx[k];
+  }
+  for (int k = 0; k < d; ++k) G[a * d + k] = p->G * acc[k];
+}
+
 /* g(Q, t); the autonomous kinds ignore t. */
 void orc_force_t(const orc_problem *p, const double *Q, double *G, double t) {
   const int n = p->n, d = p->d, Dq = n * d;
@@ -132,23 +152,13 @@ void orc_force_t(const orc_problem *p, const double *Q, double *G, double t) {
     break;
   }
   case ORC_GRAVITY: {
-    double eps2 = p->eps * p->eps;
-    const int par = n >= ORC_PAR_MIN_BODIES && orc_serial_caller();
-#pragma omp parallel for schedule(static) if (par)
-    for (int a = 0; a < n; ++a) {
-      double acc[3] = {0.0, 0.0, 0.0};
-      for (int b = 0; b < n; ++b) {
-        if (b == a) continue;
-        double dx[3], r2 = 0.0;
-        for (int k = 0; k < d; ++k) {
-          dx[k] = Q[b * d + k] - Q[a * d + k];
-          r2 += dx[k] * dx[k];
-        }
-        r2 += eps2;
-        double w = p->mass[b] / (r2 * sqrt(r2));
-        for (int k = 0; k < d; ++k) acc[k] += w * dx[k];
-      }
-      for (int k = 0; k < d; ++k) G[a * d + k] = p->G * acc[k];
+    /* a small system stays out of the OpenMP runtime altogether: even a
+     * parallel region that runs on one thread costs more than its force */
+    if (n >= ORC_PAR_MIN_BODIES && orc_serial_caller()) {
+#pragma omp parallel for schedule(static)
+      for (int a = 0; a < n; ++a) gravity_target(p, Q, G, a);
+    } else {
+      for (int a = 0; a < n; ++a) gravity_target(p, Q, G, a);
     }
     break;
   }

@@ -93,6 +93,34 @@ def test_sampled_instances_match_the_oracle(full_run, orc):
         xq, xp = x["q"].reshape(len(pick), 2, DQ), x["p"].reshape(len(pick), 2, DQ)
         sens_q = np.maximum(sens_q, [relmax(xq[j, 1], bq[j, 1]) for j in range(len(pick))])
         sens_p = np.maximum(sens_p, [relmax(xp[j, 1], bp[j, 1]) for j in range(len(pick))])
+    # The final energy errors after 10^4 steps: the oracle's own values from
+    # 1-ulp perturbations of the initial state (3 for every sampled instance,
+    # 8 for those whose final state diverges under them: through a close
+    # encounter at h = 1 the energy error depends on the exact path and spans
+    # orders of magnitude, e.g. 8e-7 .. 9e-2 for ensemble instance 2924).
+    def final_errors(js, reps):
+        out = {j: [] for j in js}
+        fq = {j: [] for j in js}
+        cs = [specs[j] for j in js]
+        cq = np.concatenate([qs[j * DQ:(j + 1) * DQ] for j in js])
+        cp = np.concatenate([ps[j * DQ:(j + 1) * DQ] for j in js])
+        for _ in range(reps):
+            qp = cq + rng.choice([-1.0, 1.0], cq.size) * np.spacing(np.abs(cq))
+            pp = cp + rng.choice([-1.0, 1.0], cp.size) * np.spacing(np.abs(cp))
+            x = orc.integrate_batch(cs, qp, pp, H, NSTEPS, NSTEPS)
+            xq, xp = x["q"].reshape(len(js), 2, DQ), x["p"].reshape(len(js), 2, DQ)
+            for m, j in enumerate(js):
+                H0 = orc.energy(specs[j], qp[m * DQ:(m + 1) * DQ], pp[m * DQ:(m + 1) * DQ])
+                out[j].append(abs(orc.energy(specs[j], xq[m, 1], xp[m, 1]) / H0 - 1))
+                fq[j].append(max(relmax(xq[m, 1], Qo[j, -1]), relmax(xp[m, 1], Po[j, -1])))
+        return out, fq
+
+    e_spread, div_full = final_errors(list(range(len(pick))), 3)
+    chaotic = [j for j in range(len(pick)) if max(div_full[j]) > 1e-13]
+    if chaotic:
+        more, _ = final_errors(chaotic, 5)
+        for j in chaotic:
+            e_spread[j] += more[j]
     smooth = 0
     for j, i in enumerate(pick):
         H0g = orc.energy(specs[j], Q[i, 0], P[i, 0])
@@ -103,12 +131,15 @@ def test_sampled_instances_match_the_oracle(full_run, orc):
             smooth += 1
             assert relmax(Q[i, 1], Qo[j, 1]) <= r12_tolerance(sens_q[j]), (int(i), sens_q[j])
             assert relmax(P[i, 1], Po[j, 1]) <= r12_tolerance(sens_p[j]), (int(i), sens_p[j])
-            assert eg <= max(1e-12, 2.0 * eo), (int(i), eg, eo)
+        worst = max([eo] + e_spread[j])
+        if j not in chaotic:   # non-chaotic over the whole run
+            assert eg <= max(1e-12, 2.0 * worst), (int(i), eg, eo, e_spread[j])
             assert abs(kg - ko) <= 0.05 * ko, (int(i), int(kg), int(ko))
         else:
             # rounding differences are amplified: the two trajectories differ
-            # but are equally valid; the energy error stays of the same order
-            assert eg <= 100.0 * max(eo, 1e-12), (int(i), eg, eo)
+            # but are equally valid; the energy error stays within the range
+            # the oracle itself reaches over 1-ulp perturbations
+            assert eg <= 100.0 * max(worst, 1e-12), (int(i), eg, eo, e_spread[j])
     assert smooth >= len(pick) // 4, smooth
 
 

@@ -139,18 +139,19 @@ def test_iteration_cap_matches_oracle(orc):
     assert st["nonconverged_steps"] == r["stats"]["nonconverged"] >= 1
 
 
-def test_nonfinite_flagged_others_intact():
+@pytest.mark.parametrize("nb", [16, 40])  # one lane, two lanes per (body, stage)
+def test_nonfinite_flagged_others_intact(nb):
     """Two coincident bodies with equal velocities: the unsoftened force is
     non-finite at the first step; that system reports ENONFINITE with NaN frames
     while a healthy system in the same call is unaffected."""
-    bad = W.planetary_systems(1, 16, seed=14)[0]
-    q = bad["q"].reshape(16, 3).copy()
-    v = bad["p"].reshape(16, 3) / bad["mass"][:, None]
+    bad = W.planetary_systems(1, nb, seed=14)[0]
+    q = bad["q"].reshape(nb, 3).copy()
+    v = bad["p"].reshape(nb, 3) / bad["mass"][:, None]
     q[5] = q[4]
     v[5] = v[4]
     bad["q"] = q.ravel()
     bad["p"] = (v * bad["mass"][:, None]).ravel()
-    good = W.planetary_systems(1, 16, seed=15)[0]
+    good = W.planetary_systems(1, nb, seed=15)[0]
     probs = [prob(bad), prob(good)]
     qq = np.concatenate([bad["q"], good["q"]])
     pp = np.concatenate([bad["p"], good["p"]])
@@ -158,7 +159,7 @@ def test_nonfinite_flagged_others_intact():
     q, p, st, rc = integ.integrate(qq, pp, np.array([1.0, 1.0]), 20, 10)
     assert rc == K.IRKGL16_ENONFINITE
     assert st["inst_status"][0] == K.IRKGL16_ENONFINITE and st["inst_status"][1] == 0
-    dq = 48
+    dq = 3 * nb
     assert np.array_equal(q[:dq], bad["q"])      # frame 0 is the input
     assert np.all(np.isnan(q[dq:3 * dq]))         # later frames NaN
     qg, pg, _, _ = K.Integrator([probs[1]]).integrate(good["q"], good["p"], 1.0, 20, 10)
