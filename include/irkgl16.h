@@ -33,6 +33,7 @@ extern "C" {
 #define IRKGL16_ENONFINITE (-4) /* an instance produced NaN/Inf (others written) */
 #define IRKGL16_ESCRATCH (-5)   /* irkgl16_integrate_static: the call needs more  */
                                 /* than the fixed scratch (size limits below)     */
+#define IRKGL16_ECANCELED (-6)  /* a served request was cancelled                */
 #define IRKGL16_ENOCONV 1       /* warning: some steps stopped at max_iter       */
 
 /* ---- force kinds -------------------------------------------------------- */
@@ -337,6 +338,28 @@ int irkgl16_poll(irkgl16_server *s, int64_t ticket, int32_t *done);
  * release the ticket.  Returns the request's status. */
 int irkgl16_wait(irkgl16_server *s, int64_t ticket, double *q_out, double *p_out,
                  irkgl16_request_info *info);
+
+/* Cancel a request.  A pending one is dropped (its frames after frame 0 are
+ * NaN); a resident one stops when the current time slice ends, keeping the
+ * frames of the steps it completed (later frames NaN).  irkgl16_wait then
+ * returns IRKGL16_ECANCELED with the steps done in info.  A request that has
+ * already finished is left as it is.  EINVAL: unknown ticket. */
+int irkgl16_cancel(irkgl16_server *s, int64_t ticket);
+
+/* Totals of a server since its creation. */
+typedef struct {
+  int64_t slices;             /* time slices run                                  */
+  double slice_wall_s;        /* their summed wall time (set-up, uploads, kernels, */
+                              /* copies of statistics and frames, harvest)        */
+  double slice_device_s;      /* their summed device time, first upload to last   */
+                              /* kernel (HIP events on the slice stream)          */
+  int64_t requests_done;      /* finished requests, cancelled ones included       */
+  int64_t requests_cancelled;
+  int32_t max_resident;       /* most requests resident in one slice              */
+  int32_t resident, pending;  /* now                                              */
+} irkgl16_server_info;
+
+int irkgl16_server_stats(irkgl16_server *s, irkgl16_server_info *out);
 
 /* Stop the serving thread after the resident and pending requests finish, and
  * release everything.  NULL-safe. */

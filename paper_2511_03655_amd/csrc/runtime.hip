@@ -953,6 +953,7 @@ const char* irkgl16_strerror(int status) {
     case IRKGL16_ENOCONV: return "some steps stopped at the iteration cap";
     case IRKGL16_ESCRATCH:
       return "the call does not fit the fixed scratch of irkgl16_integrate_static";
+    case IRKGL16_ECANCELED: return "the request was cancelled";
     default: return "unknown status";
   }
 }

@@ -33,49 +33,9 @@
 #include "device_common.h"
 #include "host_common.h"
 #include "launch.h"
+#include "serve_sched.h"
 
 namespace {
-
-// First-fit allocator over [0, size) (units: doubles) with coalescing.
-class Arena {
- public:
-  explicit Arena(int64_t size) { free_[0] = size; }
-  int64_t alloc(int64_t n) {
-    n = (n + 31) / 32 * 32;  // 256-byte granules
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= n) {
-        const int64_t off = it->first, len = it->second;
-        free_.erase(it);
-        if (len > n) free_[off + n] = len - n;
-        used_[off] = n;
-        return off;
-      }
-    }
-    return -1;
-  }
-  void release(int64_t off) {
-    auto u = used_.find(off);
-    if (u == used_.end()) return;
-    int64_t len = u->second;
-    used_.erase(u);
-    auto next = free_.lower_bound(off);
-    if (next != free_.end() && off + len == next->first) {
-      len += next->second;
-      next = free_.erase(next);
-    }
-    if (next != free_.begin()) {
-      auto prev = std::prev(next);
-      if (prev->first + prev->second == off) {
-        prev->second += len;
-        return;
-      }
-    }
-    free_[off] = len;
-  }
-
- private:
-  std::map<int64_t, int64_t> free_, used_;
-};
 
 struct Request {
   int64_t ticket = 0;
@@ -93,6 +53,7 @@ struct Request {
   double t_submit = 0, t_admit = 0, t_done = 0;
   bool fresh = false, done = false;
   bool finish = false;  // set by the slice (worker only); published as `done` under the lock
+  bool cancel = false;  // set by irkgl16_cancel (under the lock): stop after the current slice
   int64_t stage_base = 0, f0 = 0;  // this slice's frame window
   int64_t budget = 0, old_steps = 0;  // this slice's step budget, steps done before it
 };
@@ -146,7 +107,7 @@ struct irkgl16_server {
   DevBuf d_tab, d_desc, d_stat, d_arena, d_in, d_stage_q, d_stage_p, d_queue, d_heads, d_ids,
       d_large;
   int large_nmax = 0;
-  std::unique_ptr<Arena> arena;
+  std::unique_ptr<irk::Arena> arena;
 
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -155,6 +116,12 @@ struct irkgl16_server {
   std::vector<int> free_slots;
   std::unordered_map<int64_t, std::unique_ptr<Request>> requests;
   int64_t next_ticket = 1;
+  // totals reported by irkgl16_server_stats (under the lock)
+  int64_t n_slices = 0, n_finished = 0, n_cancelled = 0;
+  double slice_wall_s = 0.0, slice_device_s = 0.0;
+  int32_t max_resident_seen = 0;
+  hipEvent_t ev_s0 = nullptr, ev_s1 = nullptr;  // device span of a slice (uploads to results)
+  double last_slice_device_s = 0.0;             // worker only
   bool stopping = false;
   int device_error = 0;
   std::thread worker;
@@ -168,6 +135,8 @@ struct irkgl16_server {
     for (hipEvent_t e : cls_ev) (void)hipEventDestroy(e);
     for (hipStream_t sk : aux) (void)hipStreamDestroy(sk);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_s0) (void)hipEventDestroy(ev_s0);
+    if (ev_s1) (void)hipEventDestroy(ev_s1);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
   }
   void run();
@@ -212,8 +181,7 @@ int irkgl16_server::slice(std::vector<Request*>& live, std::vector<Request*>& fr
     const double us = it != step_us.end() ? it->second
                                           : model_step_us(std::get<0>(key), std::get<1>(key),
                                                           std::get<2>(key));
-    const double fit = opt.slice_ms * 1e3 / std::max(us, 1e-3);
-    budget[key] = std::max<int64_t>(1, std::min<int64_t>(slice_steps, (int64_t)fit));
+    budget[key] = irk::slice_budget(us, opt.slice_ms, slice_steps);
   }
   for (Request* r : live) {
     r->budget = budget[std::make_tuple(r->cls, r->kind, r->S, r->d)];
@@ -222,12 +190,10 @@ int irkgl16_server::slice(std::vector<Request*>& live, std::vector<Request*>& fr
   // frame windows and staging layout
   int64_t stage_total = 0, in_total = 0;
   for (Request* r : live) {
-    const int64_t f0 = r->steps_done / r->stride;
-    const int64_t end = std::min(r->nsteps, r->steps_done + r->budget);
-    const int64_t f1 = end / r->stride;
-    r->f0 = f0;
+    const irk::FrameWindow w = irk::slice_frames(r->steps_done, r->budget, r->nsteps, r->stride);
+    r->f0 = w.f0;
     r->stage_base = stage_total;
-    stage_total += (f1 - f0 + 1) * r->dq;
+    stage_total += (w.f1 - w.f0 + 1) * r->dq;
   }
   std::vector<int64_t> in_off(live.size(), 0);
   for (Request* r : fresh) in_total += r->dq;
@@ -277,6 +243,7 @@ int irkgl16_server::slice(std::vector<Request*>& live, std::vector<Request*>& fr
   do {                                               \
     if ((x) != hipSuccess) return IRKGL16_EDEVICE;   \
   } while (0)
+  SRV_TRY(hipEventRecord(ev_s0, st));
   SRV_TRY(hipMemcpyAsync(d_desc.p, h_desc.data(), sizeof(irk::InstDesc) * max_slot,
                          hipMemcpyHostToDevice, st));
   SRV_TRY(hipMemcpyAsync(d_queue.p, queue.data(), sizeof(int32_t) * queue.size(),
@@ -360,6 +327,7 @@ int irkgl16_server::slice(std::vector<Request*>& live, std::vector<Request*>& fr
     h_stage_q.resize(stage_total);
     h_stage_p.resize(stage_total);
   }
+  SRV_TRY(hipEventRecord(ev_s1, st));
   SRV_TRY(hipMemcpyAsync(h_stat.data(), d_stat.p, sizeof(irk::InstStat) * max_slot,
                          hipMemcpyDeviceToHost, st));
   if (stage_total > 0) {
@@ -369,14 +337,18 @@ int irkgl16_server::slice(std::vector<Request*>& live, std::vector<Request*>& fr
                            hipMemcpyDeviceToHost, st));
   }
   SRV_TRY(hipStreamSynchronize(st));
+  {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ev_s0, ev_s1) == hipSuccess) last_slice_device_s = 1e-3 * ms;
+  }
 #undef SRV_TRY
   // harvest frames and progress
   for (Request* r : live) {
     const irk::InstStat& s = h_stat[r->slot];
-    const int64_t old = r->steps_done;
-    const int64_t fa = r->fresh ? 0 : old / r->stride + 1;
-    const int64_t fb = s.steps_done / r->stride;
-    for (int64_t f = fa; f <= fb; ++f) {
+    const irk::FrameWindow hv = irk::harvested_frames(r->fresh, r->steps_done, s.steps_done,
+                                                      r->stride);
+    const int64_t fb = hv.f1;
+    for (int64_t f = hv.f0; f <= fb; ++f) {
       const int64_t src = r->stage_base + (f - r->f0) * r->dq;
       std::copy(h_stage_q.begin() + src, h_stage_q.begin() + src + r->dq,
                 r->qf.begin() + f * r->dq);
@@ -467,24 +439,43 @@ void irkgl16_server::run() {
         continue;
       }
     }
-    // parameters of fresh requests into the arena
+    // parameters of fresh requests into the arena (the host copies stay alive
+    // until the slice has synchronized its stream)
+    std::vector<std::vector<double>> prm_host;
     for (Request* r : fresh) {
       const int64_t po = r->arena_off + (int64_t)(4 + irk::kS) * r->dq;
       std::vector<double> prm(r->mass);
       prm.insert(prm.end(), r->coupling.begin(), r->coupling.end());
-      if (!prm.empty())
-        (void)hipMemcpyAsync(d_arena.as<double>() + po, prm.data(), sizeof(double) * prm.size(),
-                             hipMemcpyHostToDevice, stream);
+      if (prm.empty()) continue;
+      prm_host.push_back(std::move(prm));
+      (void)hipMemcpyAsync(d_arena.as<double>() + po, prm_host.back().data(),
+                           sizeof(double) * prm_host.back().size(), hipMemcpyHostToDevice, stream);
     }
     live.insert(live.end(), fresh.begin(), fresh.end());
+    const auto ts = std::chrono::steady_clock::now();
+    last_slice_device_s = 0.0;
     const int rc = device_error ? device_error : slice(live, fresh);
+    const double wall = std::chrono::duration<double>(std::chrono::steady_clock::now() - ts).count();
     std::lock_guard<std::mutex> lk(mu);
+    ++n_slices;
+    slice_wall_s += wall;
+    slice_device_s += last_slice_device_s;
+    max_resident_seen = std::max<int32_t>(max_resident_seen, (int32_t)live.size());
     for (Request* r : live) {
       if (rc != IRKGL16_OK && !r->finish) {
         r->status = rc;
         r->finish = true;
       }
+      if (r->cancel && !r->finish) {  // frames after the last completed step stay NaN
+        const int64_t fb = r->steps_done / r->stride;
+        std::fill(r->qf.begin() + (fb + 1) * r->dq, r->qf.end(), std::nan(""));
+        std::fill(r->pf.begin() + (fb + 1) * r->dq, r->pf.end(), std::nan(""));
+        r->status = IRKGL16_ECANCELED;
+        r->finish = true;
+        ++n_cancelled;
+      }
       if (r->finish) {
+        ++n_finished;
         r->done = true;
         r->t_done = now_s(t0);
         arena->release(r->arena_off);
@@ -523,7 +514,7 @@ int irkgl16_server_create(irkgl16_server** out, const irkgl16_server_options* op
     const int64_t cap_doubles = opt->cap_bytes / (int64_t)sizeof(double);
     if (s->d_arena.ensure(sizeof(double) * (size_t)cap_doubles) != hipSuccess)
       return IRKGL16_ENOMEM;
-    s->arena.reset(new Arena(cap_doubles));
+    s->arena.reset(new irk::Arena(cap_doubles));
     const size_t R = (size_t)s->opt.max_resident;
     if (s->d_desc.ensure(sizeof(irk::InstDesc) * R) || s->d_stat.ensure(sizeof(irk::InstStat) * R) ||
         s->d_tab.ensure(sizeof(double) * irk::kTabSize))
@@ -560,7 +551,8 @@ int irkgl16_server_create(irkgl16_server** out, const irkgl16_server_options* op
       if (hipEventCreateWithFlags(&ek, hipEventDisableTiming) != hipSuccess) return IRKGL16_EDEVICE;
       s->aux_done.push_back(ek);
     }
-    if (hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming) != hipSuccess)
+    if (hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreate(&s->ev_s0) != hipSuccess || hipEventCreate(&s->ev_s1) != hipSuccess)
       return IRKGL16_EDEVICE;
     irkgl16_server* raw = s.release();
     raw->worker = std::thread([raw] { raw->run(); });
@@ -650,6 +642,48 @@ int irkgl16_wait(irkgl16_server* s, int64_t ticket, double* q_out, double* p_out
     info->done_s = r->t_done;
   }
   return r->status;
+}
+
+int irkgl16_cancel(irkgl16_server* s, int64_t ticket) {
+  if (!s) return IRKGL16_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->requests.find(ticket);
+  if (it == s->requests.end()) return IRKGL16_EINVAL;
+  Request* r = it->second.get();
+  if (r->done) return IRKGL16_OK;
+  auto pq = std::find(s->pending.begin(), s->pending.end(), r);
+  if (pq != s->pending.end()) {  // never admitted: no frame beyond the initial state
+    s->pending.erase(pq);
+    std::fill(r->qf.begin(), r->qf.end(), std::nan(""));
+    std::fill(r->pf.begin(), r->pf.end(), std::nan(""));
+    std::copy(r->q0.begin(), r->q0.end(), r->qf.begin());
+    std::copy(r->p0.begin(), r->p0.end(), r->pf.begin());
+    r->status = IRKGL16_ECANCELED;
+    r->done = true;
+    r->t_done = now_s(s->t0);
+    ++s->n_finished;
+    ++s->n_cancelled;
+    s->cv_done.notify_all();
+    return IRKGL16_OK;
+  }
+  r->cancel = true;  // resident: stops when the current slice ends
+  return IRKGL16_OK;
+}
+
+int irkgl16_server_stats(irkgl16_server* s, irkgl16_server_info* out) {
+  if (!s || !out) return IRKGL16_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  out->slices = s->n_slices;
+  out->slice_wall_s = s->slice_wall_s;
+  out->slice_device_s = s->slice_device_s;
+  out->requests_done = s->n_finished;
+  out->requests_cancelled = s->n_cancelled;
+  out->max_resident = s->max_resident_seen;
+  int32_t res = 0;
+  for (Request* r : s->resident) res += r ? 1 : 0;
+  out->resident = res;
+  out->pending = (int32_t)s->pending.size();
+  return IRKGL16_OK;
 }
 
 void irkgl16_server_destroy(irkgl16_server* s) {

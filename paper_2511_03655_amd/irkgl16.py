@@ -25,7 +25,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("IRKGL16_LIB") or os.path.join(HERE, "libirkgl16.so")
 
 IRKGL16_OK, IRKGL16_EINVAL, IRKGL16_ENOMEM, IRKGL16_EDEVICE = 0, -1, -2, -3
-IRKGL16_ENONFINITE, IRKGL16_ENOCONV, IRKGL16_ESCRATCH = -4, 1, -5
+IRKGL16_ENONFINITE, IRKGL16_ENOCONV, IRKGL16_ESCRATCH, IRKGL16_ECANCELED = -4, 1, -5, -6
 IRKGL16_STATIC_SCRATCH_BYTES, IRKGL16_STATIC_MAX_INST = 32 << 20, 16384
 IRKGL16_KEPLER, IRKGL16_GRAVITY, IRKGL16_CHAIN = 0, 1, 2
 IRKGL16_DEVICE_PTRS, IRKGL16_PLAIN, IRKGL16_REPRODUCIBLE, IRKGL16_GRAPH = 1, 2, 4, 8
@@ -35,7 +35,7 @@ EXPORTED = ["irkgl16_create", "irkgl16_integrate", "irkgl16_last_stats", "irkgl1
             "irkgl16_strerror", "irkgl16_server_create", "irkgl16_submit", "irkgl16_poll",
             "irkgl16_wait", "irkgl16_server_destroy", "irkgl16_create_user",
             "irkgl16_user_compile_check", "irkgl16_create_ode", "irkgl16_ode_compile_check",
-            "irkgl16_integrate_static"]
+            "irkgl16_integrate_static", "irkgl16_cancel", "irkgl16_server_stats"]
 
 
 class irkgl16_problem(C.Structure):
@@ -65,6 +65,12 @@ class irkgl16_server_options(C.Structure):
 class irkgl16_request_info(C.Structure):
     _fields_ = [("status", C.c_int32), ("steps", C.c_int64), ("iterations", C.c_int64),
                 ("submit_s", C.c_double), ("admit_s", C.c_double), ("done_s", C.c_double)]
+
+
+class irkgl16_server_info(C.Structure):
+    _fields_ = [("slices", C.c_int64), ("slice_wall_s", C.c_double), ("slice_device_s", C.c_double),
+                ("requests_done", C.c_int64), ("requests_cancelled", C.c_int64),
+                ("max_resident", C.c_int32), ("resident", C.c_int32), ("pending", C.c_int32)]
 
 
 class IRKGL16Error(RuntimeError):
@@ -113,6 +119,10 @@ def lib():
         L.irkgl16_poll.restype = C.c_int
         L.irkgl16_wait.argtypes = [C.c_void_p, C.c_int64, dp, dp, C.POINTER(irkgl16_request_info)]
         L.irkgl16_wait.restype = C.c_int
+        L.irkgl16_cancel.argtypes = [C.c_void_p, C.c_int64]
+        L.irkgl16_cancel.restype = C.c_int
+        L.irkgl16_server_stats.argtypes = [C.c_void_p, C.POINTER(irkgl16_server_info)]
+        L.irkgl16_server_stats.restype = C.c_int
         L.irkgl16_server_destroy.argtypes = [C.c_void_p]
         L.irkgl16_server_destroy.restype = None
         L.irkgl16_create_user.argtypes = [C.POINTER(C.c_void_p), C.c_char_p, C.c_int32, C.c_int32,
@@ -465,6 +475,20 @@ def irkgl16_wait(srv, ticket, q_out=None, p_out=None):
                     submit_s=info.submit_s, admit_s=info.admit_s, done_s=info.done_s)
 
 
+def irkgl16_cancel(srv, ticket):
+    rc = lib().irkgl16_cancel(srv, int(ticket))
+    if rc != IRKGL16_OK:
+        raise IRKGL16Error(rc, "irkgl16_cancel")
+
+
+def irkgl16_server_stats(srv):
+    info = irkgl16_server_info()
+    rc = lib().irkgl16_server_stats(srv, C.byref(info))
+    if rc != IRKGL16_OK:
+        raise IRKGL16Error(rc, "irkgl16_server_stats")
+    return {k: getattr(info, k) for k, _ in irkgl16_server_info._fields_}
+
+
 def irkgl16_server_destroy(srv):
     if srv:
         lib().irkgl16_server_destroy(srv)
@@ -493,6 +517,12 @@ class Server:
         p = np.empty(dq * nf) if keep_frames else None
         rc, info = irkgl16_wait(self.srv, ticket, q, p)
         return q, p, info, rc
+
+    def cancel(self, ticket):
+        irkgl16_cancel(self.srv, ticket)
+
+    def stats(self):
+        return irkgl16_server_stats(self.srv)
 
     def close(self):
         """Stop the serving thread after the pending requests and release the server."""

@@ -84,3 +84,51 @@ def test_served_whole_gpu_request_in_slices():
     for (t, r_inst), (q, p, info, rc) in zip(reqs, out["results"]):
         qa, pa, _ = alone(r_inst)
         assert np.array_equal(q, qa) and np.array_equal(p, pa)
+
+
+def test_cancel_resident_and_pending():
+    """A resident request cancelled mid-run keeps the frames of the steps it
+    completed (equal to the same request alone) and NaN after them; a request
+    still waiting for memory is dropped with only its initial frame; the other
+    requests are untouched.  The server's slice totals are consistent."""
+    import time
+    long_inst = W.uneven_mix(1, seed=31, classes=[("gravity", 16)])[0]
+    long_inst.update(nsteps=200000, stride=100)
+    short = W.uneven_mix(1, seed=32, classes=[("gravity", 6)])[0]
+    short.update(nsteps=300, stride=100)
+    waiting = W.uneven_mix(1, seed=33, classes=[("gravity", 6)])[0]
+    waiting.update(nsteps=300, stride=100)
+    need = lambda i: 8 * (i["n"] * i["d"] * 12 + i["n"])
+    # room for the long and the short request, not for the third one as well
+    srv = K.Server(cap_bytes=need(long_inst) + need(short) + 1024, slice_steps=50)
+    try:
+        t_long = srv.submit(prob(long_inst), long_inst["q"], long_inst["p"], long_inst["h"],
+                            long_inst["nsteps"], long_inst["stride"])
+        t_short = srv.submit(prob(short), short["q"], short["p"], short["h"], short["nsteps"],
+                             short["stride"])
+        t_wait = srv.submit(prob(waiting), waiting["q"], waiting["p"], waiting["h"],
+                            waiting["nsteps"], waiting["stride"])
+        qs, ps, info_s, rc_s = srv.wait(t_short)
+        time.sleep(0.05)
+        srv.cancel(t_wait)     # may still be pending, or admitted by now
+        srv.cancel(t_long)     # resident
+        ql, pl, info_l, rc_l = srv.wait(t_long)
+        qw, pw, info_w, rc_w = srv.wait(t_wait)
+        st = srv.stats()
+    finally:
+        srv.close()
+    qa, pa, _ = alone(short)
+    assert rc_s == 0 and np.array_equal(qs, qa) and np.array_equal(ps, pa)
+    assert rc_l == K.IRKGL16_ECANCELED and 0 < info_l["steps"] < long_inst["nsteps"]
+    dq = long_inst["n"] * long_inst["d"]
+    nf = info_l["steps"] // long_inst["stride"] + 1     # frames completed
+    qla, pla, _ = alone(dict(long_inst, nsteps=(nf - 1) * long_inst["stride"]))
+    assert np.array_equal(ql[:nf * dq], qla) and np.array_equal(pl[:nf * dq], pla)
+    assert np.all(np.isnan(ql[nf * dq:])) and np.all(np.isnan(pl[nf * dq:]))
+    assert rc_w in (0, K.IRKGL16_ECANCELED)
+    if rc_w == K.IRKGL16_ECANCELED:
+        dw = waiting["n"] * waiting["d"]
+        nfw = info_w["steps"] // waiting["stride"] + 1
+        assert np.array_equal(qw[:dw], waiting["q"]) and np.all(np.isnan(qw[nfw * dw:]))
+    assert st["requests_done"] == 3 and st["requests_cancelled"] >= 1
+    assert st["slices"] >= 1 and 0 < st["slice_device_s"] <= st["slice_wall_s"]
