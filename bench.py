@@ -39,10 +39,16 @@ sys.path.insert(0, ROOT)
 # streams, but HIP runs the kernels of streams that share a hardware queue one
 # after another, and a process gets GPU_MAX_HW_QUEUES queues (4 by default,
 # two of them taken by the default and the caller's streams).  With 8 the seven
-# classes of the uneven mix overlap: 8.9-10.0 s per call instead of 10.1-11.0 s;
+# classes of the uneven mix overlap (7.3 s per call instead of 10.1-11.0 s);
 # the ensemble call gains about 1 %.  Read when HIP initialises, so set here,
-# before anything imports torch.
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+# before anything imports torch; a larger value already in the environment is
+# kept.
+try:
+    _hwq = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
+except ValueError:
+    _hwq = 4
+if _hwq < 8:
+    os.environ["GPU_MAX_HW_QUEUES"] = "8"
 
 METRIC = "FP64 IRKGL16 steps/s, batched vs plain, at rel err<=1e-12; p50/p99 solve latency"
 N_INST, N_BODIES, D, NSTEPS, H = 65536, 6, 3, 10_000, 1.0
@@ -272,6 +278,8 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "henon", "sbh", "stages",
                              "explicit"])
+    ap.add_argument("--rates", default="",
+                    help="served stream: comma-separated subset of the rates 10,100,1000,10000")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -667,7 +675,11 @@ def run_c4(args):
                    {"seconds": dt, "instance_steps": total_steps,
                     "roofline": {"bound": "alu", "achieved": flops / dt / 1e12,
                                  "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                                 "frac": flops / dt / 1e12 / FP64_PEAK_TFLOPS, "traffic": None},
+                                 "frac": flops / dt / 1e12 / FP64_PEAK_TFLOPS,
+                                 "traffic": traffic_from_profile(
+                                     "uneven_mix_c4_4096",
+                                     ["k_small.hip", "small_kernel.h", "k_stage.hip", "k_wg.hip",
+                                      "k_prepare.hip", "device_common.h", "runtime.hip"])},
                     "critical_path": {"instances_alone": crit,
                                       "call_over_longest_alone":
                                           dt / max(c["seconds_alone"] for c in crit)},
@@ -701,14 +713,18 @@ def run_c5(args):
     from paper_2511_03655_amd import workloads as W
     rows = []
     sat = None
-    for rate, nreq in ((10.0, 60), (100.0, 300), (1000.0, 600), (10000.0, 1000)):
+    sweep = ((10.0, 60), (100.0, 300), (1000.0, 600), (10000.0, 1000))
+    if args.rates:
+        keep = {float(x) for x in args.rates.split(",")}
+        sweep = tuple(r for r in sweep if r[0] in keep)
+    for rate, nreq in sweep:
         reqs = W.poisson_requests(rate, nreq, steps_range=(1e3, 1e5), stride=100,
                                   plummer_sizes=(64, 128, 256))
         so = serve.run_stream(reqs, cap_bytes=64 << 30, slice_steps=1000)
         print(f"c5: rate {rate}/s done in {so['wall_s']:.1f} s", file=sys.stderr, flush=True)
         rows.append(_served_row(rate, nreq, so))
         sat = reqs
-    # the saturated sample (all 1000 requests within 0.1 s) as one batched call
+    # the last (most saturated) sample of the sweep as one batched call
     probs = [_problem(i) for _, i in sat]
     ns = np.array([i["nsteps"] for _, i in sat], np.int64)
     q0 = np.concatenate([i["q"] for _, i in sat])
@@ -719,8 +735,8 @@ def run_c5(args):
         _, _, bst, _ = integ.integrate(q0, p0, h, ns, np.full(len(sat), 100, np.int64))
         dtb = time.perf_counter() - t
     batched = {"value": float(ns.sum()) / dtb, "unit": "instance-steps/s", "seconds": dtb,
-               "sample": "the 1000 requests of the 1e4/s row in one irkgl16_integrate call "
-                         "(host buffers, frames every 100 steps)"}
+               "sample": f"the {len(sat)} requests of the last row in one irkgl16_integrate "
+                         "call (host buffers, frames every 100 steps)"}
     print(f"c5: same requests batched in {dtb:.1f} s", file=sys.stderr, flush=True)
     # the configured distribution at one rate: steps 1e3..1e6, clusters up to
     # 512 bodies, 120 s of arrivals; requests still running then are cancelled

@@ -208,21 +208,23 @@ int irkgl16_ode_compile_check(const char *rhs_src, int32_t D, char *log, int64_t
  * with IRKGL16_DEVICE_PTRS it returns after enqueueing (stats, if given, force a
  * stream synchronization).  Returns the worst status over instances.
  * Scheduling (never changes results): the batched kernels run in chunks up to
- * step boundaries j ceil(max nsteps / c), c = min(8, max nsteps / 64) (at
- * least 1);
- * between chunks a device kernel orders each class's work queue by estimated
- * remaining work (steps left times the iterations per step of the last chunk)
- * and moves gravitational instances of the few-body class that needed at least
- * 5 iterations per step to the stage-parallel kernel for the next chunk (both
- * kernels compute the same arithmetic).  Within a chunk, the few-body kernel
- * stops an instance at the end of a step once its recent iterations per step
- * (an exponential average over about 8 steps) reach 12; it catches up on the
- * stage-parallel kernel in the next chunk.  Only classes that can promote are
- * chunked by default (and only while an auxiliary stream is free for their
- * promoted launches).  Environment, read by irkgl16_create*: IRKGL16_CHUNKS =
- * c (a positive integer; fixed chunk count, every batched class chunked),
- * IRKGL16_PROMOTE_K = the promotion threshold, IRKGL16_EVICT_K = the eviction
- * threshold (0: never, for either). */
+ * step boundaries j ceil(max nsteps / c), c = min(C, max nsteps / 64) (at
+ * least 1); between chunks a device kernel orders each class's work queue by
+ * estimated remaining work (steps left times the iterations per step of the
+ * last chunk) and moves gravitational instances of the few-body class that
+ * needed at least P iterations per step to the stage-parallel kernel for the
+ * next chunk (both kernels compute the same arithmetic).  Within a chunk, the
+ * few-body kernel stops an instance at the end of a step once its recent
+ * iterations per step (an exponential average over about 8 steps) reach E; it
+ * catches up on the stage-parallel kernel in the next chunk.  Only classes
+ * that can promote are chunked by default (and only while an auxiliary stream
+ * is free for their promoted launches).  C = 8, P = 5 and E = 12 unless the
+ * tuning table (tune_cache.json beside the library, or the file
+ * IRKGL16_TUNE_CACHE names; written by the autotuner) sets sched/max_chunks =
+ * C, sched/promote_k10 = 10 P or sched/evict_k10 = 10 E.  Environment, read by
+ * irkgl16_create*, overriding the table: IRKGL16_CHUNKS = c (a positive
+ * integer; fixed chunk count, every batched class chunked), IRKGL16_PROMOTE_K
+ * = P, IRKGL16_EVICT_K = E (0: never, for either). */
 int irkgl16_integrate(irkgl16_ctx *ctx, const double *q0, const double *p0, const double *h,
                       const int64_t *nsteps, const int64_t *out_stride, double *q_out,
                       double *p_out, irkgl16_stats *stats);

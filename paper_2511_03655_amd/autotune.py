@@ -7,7 +7,13 @@ Tunes, on the GPU it runs on, the shapes that do not change results:
   systems in slots of S lanes (systems per workgroup = block / S), timed on a
   batch of such systems;
 * ``large/<n>`` -- sources per LDS tile (128 or 256) of the whole-GPU kernel
-  for one system of up to n bodies.
+  for one system of up to n bodies;
+* ``sched/max_chunks``, ``sched/promote_k10``, ``sched/evict_k10`` -- the
+  schedule of a call with few-body gravitational systems (the classes that can
+  promote run in chunks): the most chunks per call, and ten times the
+  iterations per step from which an instance
+  moves to the stage-parallel kernel between chunks or stops mid-chunk for it
+  (0 = never), tuned one after another on the ensemble workload.
 
 Each candidate is timed by creating a context whose tuning table holds only
 that candidate (IRKGL16_TUNE_CACHE points at a temporary file); the fastest
@@ -80,6 +86,32 @@ def time_batch(insts, nsteps, cache_values):
     return best
 
 
+SCHED_CANDIDATES = [("sched/max_chunks", [4, 6, 8, 12, 16]),
+                    ("sched/promote_k10", [40, 50, 60, 80]),
+                    ("sched/evict_k10", [80, 120, 160, 240])]
+
+
+def tune_schedule(quick, base):
+    """Coordinate descent over the schedule keys on the ensemble workload
+    (6-body planetary systems, h = 1); `base` holds the keys chosen so far."""
+    n_inst, nsteps = (16384, 4000) if quick else (65536, 10_000)
+    sy = W.planetary_systems(n_inst, 6)
+    for s in sy:
+        s["h"] = 1.0
+    chosen, report = {}, {}
+    for key, cands in SCHED_CANDIDATES:
+        times = {}
+        for c in cands:
+            table = dict(base)
+            table.update(chosen)
+            table[key] = c
+            times[c] = time_batch(sy, nsteps, table)
+            print(f"autotune {key} candidate {c}: {times[c] * 1e3:.2f} ms", flush=True)
+        chosen[key] = min(times, key=times.get)
+        report[key] = {str(c): round(t * 1e3, 3) for c, t in times.items()}
+    return chosen, report
+
+
 def cases(quick):
     """(key, candidates, instances, steps) to tune."""
     out = []
@@ -103,6 +135,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--out", default=os.path.join(HERE, "tune_cache.json"))
     ap.add_argument("--quick", action="store_true", help="smaller timing batches")
+    ap.add_argument("--no-schedule", action="store_true", help="launch shapes only")
     args = ap.parse_args()
     result, report = {}, {}
     for key, cands, insts, nsteps in cases(args.quick):
@@ -116,6 +149,10 @@ def main():
         best = min(times, key=times.get)
         result[key] = best
         report[key] = {str(c): round(t * 1e3, 3) for c, t in times.items()}
+    if not args.no_schedule:
+        chosen, rep = tune_schedule(args.quick, result)
+        result.update(chosen)
+        report.update(rep)
     with open(args.out, "w") as f:
         json.dump(result, f, indent=1, sort_keys=True)
     print(json.dumps({"cache": args.out, "chosen": result, "timings_ms": report}))

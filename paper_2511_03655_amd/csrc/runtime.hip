@@ -146,6 +146,7 @@ struct irkgl16_ctx {
   DevBuf d_qprom, d_counts, d_heads_prom;  // promoted queues, queue lengths, their heads
   DevBuf d_evicted;                         // per instance: evicted by the small-system kernel
   int chunks = 0;            // chunks per call (0: automatic)
+  int max_chunks = 8;        // automatic chunk count at most this
   double promote_k = 5.0;    // promotion threshold, iterations per step (0: never)
   double evict_k = 12.0;     // mid-chunk eviction threshold, recent iterations per step (0: never)
   DevBuf d_q0, d_p0, d_qout, d_pout, d_iters, d_large;
@@ -212,16 +213,16 @@ struct UserSpec {
 };
 
 // Chunks per call for a chunked class: `fixed` if positive, else one chunk
-// per 64 steps of its longest integration, at most 8 (with mid-chunk
-// eviction, more chunk boundaries cost more than they catch: 8 chunks ran the
-// 65,536-system ensemble 3-4 % faster than 16, and 4, 6, 10, 12, 24 and 32
-// slower than 8).
-static int chunk_count(int fixed, int64_t max_steps) {
+// per 64 steps of its longest integration, at most max_chunks (8 unless the
+// tuning table says otherwise: with mid-chunk eviction, more chunk boundaries
+// cost more than they catch; 8 chunks ran the 65,536-system ensemble 3-4 %
+// faster than 16, and 4, 6, 10, 12, 24 and 32 slower than 8).
+static int chunk_count(int fixed, int64_t max_steps, int max_chunks) {
   constexpr int64_t kMinChunkSteps = 64;
-  constexpr int kMaxChunks = 8;
   if (max_steps <= 0) return 1;
   if (fixed > 0) return (int)std::min<int64_t>(fixed, max_steps);
-  return (int)std::max<int64_t>(1, std::min<int64_t>(kMaxChunks, max_steps / kMinChunkSteps));
+  return (int)std::max<int64_t>(
+      1, std::min<int64_t>(std::max(1, max_chunks), max_steps / kMinChunkSteps));
 }
 
 // A gravitational few-body instance whose last chunk needed many iterations
@@ -358,8 +359,12 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
     c->ode = user->ode;
     if (rc != 0) return fail(rc == -1 ? IRKGL16_EINVAL : IRKGL16_EDEVICE);
   }
-  // Launch shapes from the tuning table.
+  // Launch shapes and call schedule from the tuning table (the environment
+  // variables below override the schedule keys).
   c->tune = irk::load_tune_table();
+  c->max_chunks = std::max(1, c->tune.get("sched/max_chunks", 8));
+  c->promote_k = std::max(0, c->tune.get("sched/promote_k10", 50)) / 10.0;
+  c->evict_k = std::max(0, c->tune.get("sched/evict_k10", 120)) / 10.0;
   // Chunks per call of the batched classes (0 or unset: automatic).
   if (const char* ch = std::getenv("IRKGL16_CHUNKS")) c->chunks = std::max(0, std::atoi(ch));
   // Iterations per step from which a small-system instance moves to the
@@ -449,6 +454,21 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
     return fail(IRKGL16_EDEVICE);
   *out = c;
   return IRKGL16_OK;
+}
+
+// Estimated duration of a batched class in a call, in arbitrary units: its
+// longest integration, steps times the latency of one step of one instance
+// on that class's kernel (few-body: about constant; stage-parallel: the
+// source loop over the padded body count; workgroup kernel: the source loop
+// over the bodies, or the chain's neighbour terms).  Orders the classes over
+// the auxiliary streams when they outnumber them.
+static double class_estimate(const KernelClass& kc, const int64_t* nsteps) {
+  double lat = 1.0;
+  if (kc.cls == irk::kClassStage) lat = kc.size / 8.0;
+  if (kc.cls == irk::kClassWg) lat = kc.kind == irk::kGravity ? kc.size / 16.0 : 1.0;
+  int64_t m = 0;
+  for (int32_t id : kc.ids) m = std::max(m, nsteps[id]);
+  return lat * (double)m;
 }
 
 static irk::LaunchArgs base_args(irkgl16_ctx* c, double* qout, double* pout) {
@@ -703,17 +723,31 @@ static int integrate_impl(irkgl16_ctx* c, const double* q0, const double* p0, co
       int k, j, jp, nch;  // class, its stream, promotion stream (-1: none), chunks
       int64_t budget;
     };
-    std::vector<Plan> plans;
-    int slot = 0, prom_slot = 0, max_nch = 1;
+    // Classes in order of decreasing estimated duration, each to the stream
+    // with the least estimated work so far (so the longest class starts at
+    // once and on a stream of its own when there are more classes than
+    // streams).
+    std::vector<int> order;
+    std::vector<double> est(c->classes.size(), 0.0);
     for (size_t k = 0; k < c->classes.size(); ++k) {
+      if (c->classes[k].cls == irk::kClassLarge) continue;
+      order.push_back((int)k);
+      est[k] = class_estimate(c->classes[k], nsteps);
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return est[x] > est[y]; });
+    std::vector<double> load(std::max(1, std::min(naux, n_batched)), 0.0);
+    std::vector<Plan> plans;
+    int prom_slot = 0, max_nch = 1;
+    for (int k : order) {
       const auto& kc = c->classes[k];
-      if (kc.cls == irk::kClassLarge) continue;
-      Plan pl{(int)k, slot++ % naux, -1, 1, 0};
+      const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[j] += est[k];
+      Plan pl{k, j, -1, 1, 0};
       const bool prom = promotable(c, kc) && n_batched < naux;
       if (prom) pl.jp = n_batched + prom_slot++ % (naux - n_batched);
       int64_t max_steps = 0;
       for (int32_t id : kc.ids) max_steps = std::max(max_steps, nsteps[id]);
-      pl.nch = (prom || c->chunks > 0) ? chunk_count(c->chunks, max_steps) : 1;
+      pl.nch = (prom || c->chunks > 0) ? chunk_count(c->chunks, max_steps, c->max_chunks) : 1;
       pl.budget = pl.nch > 1 ? (max_steps + pl.nch - 1) / pl.nch : 0;
       max_nch = std::max(max_nch, pl.nch);
       plans.push_back(pl);

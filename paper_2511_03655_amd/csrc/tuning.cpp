@@ -2,8 +2,9 @@
 // by the autotuner (autotune.py next to the library).  Read at context and
 // server creation from the path in IRKGL16_TUNE_CACHE, else from
 // tune_cache.json beside libirkgl16.so; a missing or unreadable file means the
-// built-in defaults.  Only launch shapes are tuned (systems per workgroup,
-// LDS tile sizes): results do not depend on them.
+// built-in defaults.  Only what results do not depend on is tuned: launch
+// shapes (systems per workgroup, LDS tile sizes) and the schedule of a call
+// (chunk count, promotion and eviction thresholds, keys sched/...).
 #include <dlfcn.h>
 
 #include <cctype>

@@ -59,3 +59,19 @@ def test_invalid_table_entries_fall_back_to_defaults(tmp_path):
     ref = run_with(tmp_path, {}, insts, 30, 30)
     out = run_with(tmp_path, {"wg/2/1/32": 96, "large/1024": 7}, insts, 30, 30)  # 96: not a slot multiple of 64
     assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1])
+
+
+def test_schedule_keys_do_not_change_results(tmp_path):
+    """Chunk count and the promotion and eviction thresholds decide only where
+    and when a step runs: every candidate the autotuner may pick gives the
+    same bits (planetary systems with close encounters, so that instances
+    are promoted and evicted)."""
+    insts = W.planetary_systems(600, 6, seed=77)
+    for s in insts:
+        s["h"] = 1.0
+    ref = run_with(tmp_path, {"sched/promote_k10": 0, "sched/evict_k10": 0}, insts, 640, 320)
+    for vals in ({}, {"sched/max_chunks": 4}, {"sched/max_chunks": 16, "sched/promote_k10": 40},
+                 {"sched/max_chunks": 8, "sched/promote_k10": 20, "sched/evict_k10": 30}):
+        out = run_with(tmp_path, vals, insts, 640, 320)
+        assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), vals
+        assert out[2]["iterations"] == ref[2]["iterations"], vals
