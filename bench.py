@@ -455,6 +455,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": prof.get("traffic_bytes_per_launch"),
+                     "traffic_GBps": (prof["traffic_bytes_per_launch"] / avg_s / 1e9
+                                      if "traffic_bytes_per_launch" in prof else None),
                      "issued": ({"flops_per_launch": prof["issued_fp64_flops_per_launch"],
                                  "achieved": prof["issued_fp64_flops_per_launch"] / avg_s / 1e12,
                                  "frac": prof["issued_fp64_flops_per_launch"] / avg_s / 1e12
@@ -585,6 +587,9 @@ def run_c3(args):
     dtp = (time.perf_counter() - t) / 50
     integ.close()
     plain.close()
+    # bytes per 1000-step launch (the call timed here)
+    c3_traffic = traffic_from_profile("large_kernel_c3_plummer2048",
+                                      ["k_large.hip", "device_common.h"])
     sp = orc.Spec(orc.GRAVITY, 2048, 3, mass=inst["mass"], eps=inst["eps"])
     t = time.perf_counter()
     orc.integrate(sp, inst["q"], inst["p"], inst["h"], 10, 10)
@@ -596,9 +601,9 @@ def run_c3(args):
                     "roofline": {"bound": "alu", "achieved": flops / dt / 1e12,
                                  "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                                  "frac": flops / dt / 1e12 / FP64_PEAK_TFLOPS,
-                                 "traffic": traffic_from_profile(
-                                     "large_kernel_c3_plummer2048",
-                                     ["k_large.hip", "device_common.h"]),
+                                 "traffic": c3_traffic,
+                                 "traffic_GBps": (c3_traffic / dt / 1e9
+                                                  if c3_traffic else None),
                                  "kernel": "large_kernel (cooperative, whole GPU)"},
                     "plain": {"value": 1.0 / dtp, "unit": "steps/s",
                               "sample": "50 steps, one launch per step"},
@@ -664,6 +669,9 @@ def run_c4(args):
                      "seconds_alone": s1["device_ms"] / 1e3})
     print(f"c4: critical path {max(c['seconds_alone'] for c in crit):.2f} s", file=sys.stderr,
           flush=True)
+    c4_traffic = traffic_from_profile("uneven_mix_c4_4096",
+                                      ["k_small.hip", "small_kernel.h", "k_stage.hip", "k_wg.hip",
+                                       "k_prepare.hip", "device_common.h", "runtime.hip"])
     specs = [orc.Spec(mix[i]["kind"], mix[i]["n"], mix[i]["d"], mass=mix[i].get("mass"),
                       G=mix[i].get("G", 1.0), beta=mix[i].get("beta", 0.0)) for i in sample]
     t = time.perf_counter()
@@ -676,10 +684,8 @@ def run_c4(args):
                     "roofline": {"bound": "alu", "achieved": flops / dt / 1e12,
                                  "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                                  "frac": flops / dt / 1e12 / FP64_PEAK_TFLOPS,
-                                 "traffic": traffic_from_profile(
-                                     "uneven_mix_c4_4096",
-                                     ["k_small.hip", "small_kernel.h", "k_stage.hip", "k_wg.hip",
-                                      "k_prepare.hip", "device_common.h", "runtime.hip"])},
+                                 "traffic": c4_traffic,
+                                 "traffic_GBps": c4_traffic / dt / 1e9 if c4_traffic else None},
                     "critical_path": {"instances_alone": crit,
                                       "call_over_longest_alone":
                                           dt / max(c["seconds_alone"] for c in crit)},
