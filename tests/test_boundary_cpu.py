@@ -308,3 +308,12 @@ def test_static_entry_point_without_gpu_reports_edevice():
     kep = dict(kind=K.IRKGL16_KEPLER, n=1, d=2, G=1.0)
     assert _static([kep]) == K.IRKGL16_EDEVICE
     assert _static([]) == K.IRKGL16_OK  # nothing to do: no device needed
+
+
+def test_serving_calls_reject_null_handles():
+    """Without a server, every serving call reports EINVAL (no GPU needed)."""
+    L = K.lib()
+    info = K.irkgl16_server_info()
+    assert L.irkgl16_cancel(None, 1) == K.IRKGL16_EINVAL
+    assert L.irkgl16_server_stats(None, C.byref(info)) == K.IRKGL16_EINVAL
+    assert K.irkgl16_strerror(K.IRKGL16_ECANCELED) == "the request was cancelled"
