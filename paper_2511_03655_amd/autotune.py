@@ -6,8 +6,9 @@ Tunes, on the GPU it runs on, the shapes that do not change results:
 * ``wg/<kind>/<d>/<S>`` -- lanes per workgroup of the workgroup kernel for
   systems in slots of S lanes (systems per workgroup = block / S), timed on a
   batch of such systems;
-* ``large/<n>`` -- sources per LDS tile (128 or 256) of the whole-GPU kernel
-  for one system of up to n bodies;
+* ``large/<n>`` -- sources staged per tile (128 or 256, split over the
+  workgroup's 16 wavefronts) of the whole-GPU kernel for one system of up to
+  n bodies;
 * ``sched/max_chunks``, ``sched/promote_k10``, ``sched/evict_k10`` -- the
   schedule of a call with few-body gravitational systems (the classes that can
   promote run in chunks): the most chunks per call, and ten times the

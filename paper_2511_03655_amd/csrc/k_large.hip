@@ -7,22 +7,26 @@
 // (t, s) = 8 t + s stands for target t at stage s.  Per fixed-point iteration:
 //  * force: for each owned group, the NCH wavefronts of the workgroup split the
 //    sources into NCH interleaved chunks (b = c mod NCH, ascending within a
-//    chunk); source stage positions are staged tile by tile in LDS, split into
-//    (x, y) and (z, m) arrays [b][stage] so that the 8 stage entries a
-//    wavefront reads at once are 128 contiguous bytes; chunk partial sums are
-//    reduced in chunk order through LDS;
-//  * update (state wavefront): R_s = h b_s G g_s, stage values
+//    chunk).  Every source is used by one wavefront only, so each wavefront
+//    stages its own sources' stage positions in a region of LDS of its own,
+//    split into (x, y) and (z, m) arrays [b][stage] so that the 8 stage
+//    entries it reads at once are 128 contiguous bytes; the force loop needs
+//    no workgroup barrier.  Chunk partial sums are reduced in chunk order
+//    through LDS;
+//  * update, one component per wavefront (component d of group g by
+//    wavefront 3 g + d): R_s = h b_s G g_s, stage values
 //    Q_s = q + h (c_s v + sum_j eta_sj R_j) (eq. IRK_FP2) with the body's R_j
 //    exchanged inside the wavefront, max-norm increments per component
 //    (eq. Delta_n) by butterfly over the stage lanes, stopping rule
-//    (eq. stopping); "not converged" / "non-finite" are OR-ed into a global
-//    flag word.  The new stage positions go to the next position buffer, and
-//    the next step's initial guess (eq. IRK_init2), formed after a tentative
-//    compensated update (eq. qnvn2), to a third buffer;
-//  * one grid barrier, whose last arriver publishes the flag word with the
-//    release; every workgroup then either iterates again from the new stage
-//    positions or commits the tentative update and starts the next step from
-//    the guess buffer, so a step costs exactly k grid barriers.
+//    (eq. stopping); "not converged" / "non-finite" are OR-ed into the
+//    workgroup's flag word.  The new stage positions go to the next position
+//    buffer, and the next step's initial guess (eq. IRK_init2), formed after
+//    a tentative compensated update (eq. qnvn2), to a third buffer;
+//  * one grid barrier, whose last arriver publishes the OR of the
+//    workgroups' flags with the release; every workgroup then either
+//    iterates again from the new stage positions or commits the tentative
+//    update and starts the next step from the guess buffer, so a step costs
+//    exactly k grid barriers.
 // The per-target state (q, v as two-double values, the stopping-rule history)
 // lives in LDS, so the force loop runs without register spills.  Three
 // position buffers rotate so that no buffer is written while it is read.
@@ -156,10 +160,21 @@ __device__ __forceinline__ double lg_guess(ConstTab T, int s, double q, double v
   return q + row_dot<EXACT>(T, kTabMu + s * kS, L0);
 }
 
-// Weight m (r2 + eps2)^(-3/2) of one source (eps2 already in r2).
+// Weight m (r2 + eps2)^(-3/2) of one source (eps2 already in r2).  Fast form:
+// the hardware reciprocal square root y0 (about 24 correct bits) refined by
+// one Halley step, y = y0 (1 + e/2 + 3 e^2/8) with e = 1 - r2 y0^2 (cubic
+// convergence: within 1 ulp of r2^(-1/2), like two Newton steps, in five
+// operations instead of seven), then cubed.
 template <bool EXACT>
 __device__ __forceinline__ double lg_weight(double r2, double m) {
-  return pair_weight<EXACT>(r2, m);
+  if constexpr (EXACT) {
+    return pair_weight<EXACT>(r2, m);
+  } else {
+    const double y0 = __builtin_amdgcn_rsq(r2);
+    const double e = fma(-r2, y0 * y0, 1.0);
+    const double y = fma(y0, e * fma(e, 0.375, 0.5), y0);
+    return m * ((y * y) * y);
+  }
 }
 
 // Squared distance in the reference order (EXACT) or with fused products.
@@ -190,41 +205,51 @@ __device__ __forceinline__ void lg_acc(double w, double dx, double dy, double dz
   }
 }
 
-// Accumulates the stage-s force on target `tgt` from the sources of one LDS
-// tile that belong to chunk `c` (local indices c, c + NCH, ...), in ascending
-// order.  Two sources are evaluated as independent chains per loop trip (their
-// contributions are still added in source order).  SEL: replace the self
-// distance (unsoftened forces); the self term then contributes w * 0 = 0.
+// Accumulates the stage-s force on target `tgt` from one staged chunk of this
+// wavefront's sources: local entries 0 .. cnt-1 hold global sources b0, b0 +
+// NCH, b0 + 2 NCH, ... (ascending).  Two sources are evaluated as independent
+// chains per loop trip (their contributions are still added in source order).
+// SEL: replace the self distance (unsoftened forces); the self term then
+// contributes w * 0 = 0.
 template <bool EXACT, int NCH, bool SEL>
-__device__ __forceinline__ void lg_force_tile(const double2* __restrict__ sxy,
-                                              const double2* __restrict__ szm, int c, int nb,
-                                              int s, int b0, int tgt, double qx, double qy,
-                                              double qz, double eps2, double& acc0, double& acc1,
-                                              double& acc2) {
-  int bl = c;
-  for (; bl + NCH < nb; bl += 2 * NCH) {
-    const double2 xa = sxy[bl * kS + s], za = szm[bl * kS + s];
-    const double2 xb = sxy[(bl + NCH) * kS + s], zb = szm[(bl + NCH) * kS + s];
+__device__ __forceinline__ void lg_force_chunk(const double2* __restrict__ sxy,
+                                               const double2* __restrict__ szm, int cnt, int s,
+                                               int b0, int tgt, double qx, double qy, double qz,
+                                               double eps2, double& acc0, double& acc1,
+                                               double& acc2) {
+  int i = 0;
+  for (; i + 1 < cnt; i += 2) {
+    const double2 xa = sxy[i * kS + s], za = szm[i * kS + s];
+    const double2 xb = sxy[(i + 1) * kS + s], zb = szm[(i + 1) * kS + s];
     const double dxa = xa.x - qx, dya = xa.y - qy, dza = za.x - qz;
     const double dxb = xb.x - qx, dyb = xb.y - qy, dzb = zb.x - qz;
     double r2a = lg_r2<EXACT>(dxa, dya, dza, eps2);
     double r2b = lg_r2<EXACT>(dxb, dyb, dzb, eps2);
     if constexpr (SEL) {
-      r2a = (b0 + bl == tgt) ? 1.0 : r2a;
-      r2b = (b0 + bl + NCH == tgt) ? 1.0 : r2b;
+      r2a = (b0 + i * NCH == tgt) ? 1.0 : r2a;
+      r2b = (b0 + (i + 1) * NCH == tgt) ? 1.0 : r2b;
     }
     const double wa = lg_weight<EXACT>(r2a, za.y);
     const double wb = lg_weight<EXACT>(r2b, zb.y);
     lg_acc<EXACT>(wa, dxa, dya, dza, acc0, acc1, acc2);
     lg_acc<EXACT>(wb, dxb, dyb, dzb, acc0, acc1, acc2);
   }
-  if (bl < nb) {
-    const double2 xa = sxy[bl * kS + s], za = szm[bl * kS + s];
+  if (i < cnt) {
+    const double2 xa = sxy[i * kS + s], za = szm[i * kS + s];
     const double dxa = xa.x - qx, dya = xa.y - qy, dza = za.x - qz;
     double r2a = lg_r2<EXACT>(dxa, dya, dza, eps2);
-    if constexpr (SEL) r2a = (b0 + bl == tgt) ? 1.0 : r2a;
+    if constexpr (SEL) r2a = (b0 + i * NCH == tgt) ? 1.0 : r2a;
     lg_acc<EXACT>(lg_weight<EXACT>(r2a, za.y), dxa, dya, dza, acc0, acc1, acc2);
   }
+}
+
+// Store into a position buffer that the other workgroups read after the next
+// grid barrier.  A relaxed atomic store at agent scope writes through this
+// XCD's L2, so the L2 holds no dirty position lines when the barrier's release
+// fence writes the L2 back (that write-back, once per workgroup and
+// iteration, otherwise grows with every dirty line of the XCD).
+__device__ __forceinline__ void pos_store(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Per-target state of a group in LDS (identical for the 8 stage lanes of a
@@ -239,9 +264,11 @@ __global__ __launch_bounds__(64 * NCH) void large_kernel(LargeArgs L) {
   constexpr int TB = LargeCfg<NCH, TILE>::kTile;
   constexpr int NT = LargeCfg<NCH, TILE>::kThreads;
   constexpr int GM = LargeCfg<NCH, TILE>::kMaxGroups;
-  constexpr int ENT = (TB * kS + NT - 1) / NT;  // tile entries staged per thread
-  __shared__ double2 sxy[TB * kS];            // [b][s] (x, y)
-  __shared__ double2 szm[TB * kS];            // [b][s] (z, m)
+  constexpr int CB = TB / NCH;       // sources per wavefront chunk
+  constexpr int WENT = CB * kS / 64;  // chunk entries staged per lane
+  static_assert(CB * kS % 64 == 0, "a chunk is a whole number of entries per lane");
+  __shared__ double2 sxy[NCH][CB * kS];       // per wavefront: [source][stage] (x, y)
+  __shared__ double2 szm[NCH][CB * kS];       // per wavefront: [source][stage] (z, m)
   __shared__ double part[NCH][3][64];         // chunk partial sums
   __shared__ double tq[GM][3][64];            // current stage positions of the owned groups
   __shared__ double rt[GM][3][64];            // increments R of the owned groups
@@ -315,12 +342,12 @@ __global__ __launch_bounds__(64 * NCH) void large_kernel(LargeArgs L) {
         for (int j = 0; j < kS; ++j) Rp[j] = Sp[4 * dq + c * kS + j];
         r0 = Rp[s];
         q0 = lg_guess<EXACT>(T, s, qh, vh, Rp, h);
-        pos[((size_t)my_tgt * kS + s) * 4 + d] = q0;
+        pos_store(&pos[((size_t)my_tgt * kS + s) * 4 + d], q0);
       }
       tq[wave][d][lane] = q0;
       rt[wave][d][lane] = r0;
     }
-    if (mine && step < target) pos[((size_t)my_tgt * kS + s) * 4 + 3] = mass[my_tgt];
+    if (mine && step < target) pos_store(&pos[((size_t)my_tgt * kS + s) * 4 + 3], mass[my_tgt]);
   }
   if (tid == 0) blk_flags = 0;
   __threadfence();
@@ -338,69 +365,86 @@ __global__ __launch_bounds__(64 * NCH) void large_kernel(LargeArgs L) {
       const int grp = g0 + g;
       if (grp >= L.ngroups) break;  // uniform over the workgroup
       const int tgt = grp * kLgT + t;
-      // ---- force on the group's targets: this wavefront's source chunk.
-      // The next tile is fetched into registers while the current one is
-      // being used (ENT entries per thread).
+      // ---- force on the group's targets: this wavefront's sources b = wave,
+      // wave + NCH, ... (ascending), staged chunk by chunk in the
+      // wavefront's own LDS region (no other wavefront reads them, so only
+      // wavefront-level ordering is needed).  Lane (t, s) stages stage s of
+      // chunk sources t, t + 8, ...; the next chunk is fetched into registers
+      // while the current one is being used.
       double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
-      double pre[ENT][4];
+      const int nw = n > wave ? (n - wave + NCH - 1) / NCH : 0;  // sources of this wavefront
+      double2* wxy = sxy[wave];
+      double2* wzm = szm[wave];
+      double pre[WENT][4];
 #pragma unroll
-      for (int e = 0; e < ENT; ++e) {
-        const int idx = tid + e * NT;
-        if (idx < min(TB, n) * kS) {
+      for (int r = 0; r < WENT; ++r) {
+        const int i = t + 8 * r;
+        if (i < nw) {
+          const double* src = P + ((size_t)(wave + NCH * i) * kS + s) * 4;
 #pragma unroll
-          for (int c = 0; c < 4; ++c) pre[e][c] = P[(size_t)idx * 4 + c];
+          for (int c = 0; c < 4; ++c) pre[r][c] = src[c];
         }
       }
-      for (int b0 = 0; b0 < n; b0 += TB) {
-        const int nb = min(TB, n - b0);
-        __syncthreads();
+      double qx = 0.0, qy = 0.0, qz = 0.0;
+      if (tgt < n) {
+        qx = tq[g][0][lane];
+        qy = tq[g][1][lane];
+        qz = tq[g][2][lane];
+      }
+      for (int j0 = 0; j0 < nw; j0 += CB) {
+        const int cnt = min(CB, nw - j0);
+        lg_wave_lds_sync();  // the previous chunk's reads are done
 #pragma unroll
-        for (int e = 0; e < ENT; ++e) {
-          const int idx = tid + e * NT;
-          if (idx < nb * kS) {
-            sxy[idx] = make_double2(pre[e][0], pre[e][1]);
-            szm[idx] = make_double2(pre[e][2], pre[e][3]);
+        for (int r = 0; r < WENT; ++r) {
+          const int i = t + 8 * r;
+          if (i < cnt) {
+            wxy[i * kS + s] = make_double2(pre[r][0], pre[r][1]);
+            wzm[i * kS + s] = make_double2(pre[r][2], pre[r][3]);
           }
         }
-        __syncthreads();
-        const int b1 = b0 + TB;
-        if (b1 < n) {
-          const int nb1 = min(TB, n - b1);
+        lg_wave_lds_sync();
+        const int j1 = j0 + CB;
+        if (j1 < nw) {
 #pragma unroll
-          for (int e = 0; e < ENT; ++e) {
-            const int idx = tid + e * NT;
-            if (idx < nb1 * kS) {
+          for (int r = 0; r < WENT; ++r) {
+            const int i = j1 + t + 8 * r;
+            if (i < nw) {
+              const double* src = P + ((size_t)(wave + NCH * i) * kS + s) * 4;
 #pragma unroll
-              for (int c = 0; c < 4; ++c) pre[e][c] = P[((size_t)b1 * kS + idx) * 4 + c];
+              for (int c = 0; c < 4; ++c) pre[r][c] = src[c];
             }
           }
         }
         if (tgt < n) {
-          const double qx = tq[g][0][lane], qy = tq[g][1][lane], qz = tq[g][2][lane];
           // with softening the self term needs no special case (w finite,
           // displacement 0); without it the self distance is replaced
+          const int b0 = wave + NCH * j0;
           if (eps2 > 0.0)
-            lg_force_tile<EXACT, NCH, false>(sxy, szm, wave, nb, s, b0, tgt, qx, qy, qz, eps2,
-                                             acc0, acc1, acc2);
+            lg_force_chunk<EXACT, NCH, false>(wxy, wzm, cnt, s, b0, tgt, qx, qy, qz, eps2, acc0,
+                                              acc1, acc2);
           else
-            lg_force_tile<EXACT, NCH, true>(sxy, szm, wave, nb, s, b0, tgt, qx, qy, qz, eps2,
-                                            acc0, acc1, acc2);
+            lg_force_chunk<EXACT, NCH, true>(wxy, wzm, cnt, s, b0, tgt, qx, qy, qz, eps2, acc0,
+                                             acc1, acc2);
         }
       }
       if constexpr (NCH > 1) {
+        // the state wavefront of the previous group has read its partial sums
+        if (g > 0) __syncthreads();
         part[wave][0][lane] = acc0;
         part[wave][1][lane] = acc1;
         part[wave][2][lane] = acc2;
         __syncthreads();
       }
-      if (wave == g && tgt < n) {
-        // ---- update of group g by its state wavefront, one component at a time
+      if (tgt < n) {
+        // ---- update of group g: component d by wavefront (3 g + d) mod NCH
         const double hb = h * coef[s][kS + 1];
         const double cs = coef[s][kS];
         LgTargetState& S = ts[g];
-        bool ok = true, bad = false;
+        bool ok = true, bad = false, any = false;
 #pragma unroll 1
         for (int d = 0; d < 3; ++d) {
+          if ((3 * g + d) % NCH != wave) continue;  // uniform over the wavefront
+          any = true;
           double gsum;
           if constexpr (NCH > 1) {
             gsum = part[0][d][lane];
@@ -415,10 +459,7 @@ __global__ __launch_bounds__(64 * NCH) void large_kernel(LargeArgs L) {
           else
             Rn = (hb * G) * gsum;
           rt[g][d][lane] = Rn;
-        }
-        lg_wave_lds_sync();
-#pragma unroll 1
-        for (int d = 0; d < 3; ++d) {
+          lg_wave_lds_sync();
           double Rj[kS];
 #pragma unroll
           for (int j = 0; j < kS; ++j) Rj[j] = rt[g][d][t * kS + j];
@@ -452,15 +493,19 @@ __global__ __launch_bounds__(64 * NCH) void large_kernel(LargeArgs L) {
           S.prv[t][d] = prv;
           tq[g][d][lane] = qn;
           gq[g][d][lane] = qg;
-          pos[((size_t)wb * bufsz + (size_t)tgt * kS + s) * 4 + d] = qn;
-          pos[((size_t)gb * bufsz + (size_t)tgt * kS + s) * 4 + d] = qg;
+          pos_store(&pos[((size_t)wb * bufsz + (size_t)tgt * kS + s) * 4 + d], qn);
+          pos_store(&pos[((size_t)gb * bufsz + (size_t)tgt * kS + s) * 4 + d], qg);
+          if (d == 0) {
+            const double m = mass[tgt];
+            pos_store(&pos[((size_t)wb * bufsz + (size_t)tgt * kS + s) * 4 + 3], m);
+            pos_store(&pos[((size_t)gb * bufsz + (size_t)tgt * kS + s) * 4 + 3], m);
+          }
         }
-        const double m = mass[tgt];
-        pos[((size_t)wb * bufsz + (size_t)tgt * kS + s) * 4 + 3] = m;
-        pos[((size_t)gb * bufsz + (size_t)tgt * kS + s) * 4 + 3] = m;
-        const uint64_t notok = __ballot(!ok), badm = __ballot(bad);
-        if (lane == 0 && (notok | badm))  // target 0 of a group always exists
-          atomicOr(&blk_flags, (notok ? 1u : 0u) | (badm ? 2u : 0u));
+        if (any) {
+          const uint64_t notok = __ballot(!ok), badm = __ballot(bad);
+          if (lane == 0 && (notok | badm))  // target 0 of a group always exists
+            atomicOr(&blk_flags, (notok ? 1u : 0u) | (badm ? 2u : 0u));
+        }
       }
     }
     const unsigned bits = grid_barrier(L.ctl, gen, nblocks, &blk_flags, &bar_res);
@@ -483,34 +528,35 @@ __global__ __launch_bounds__(64 * NCH) void large_kernel(LargeArgs L) {
       a.step_iters[dsc.iters_off + step - 1] = (uint8_t)k;
     k = 0;
     rbuf = gb;
-    if (mine) {
-      LgTargetState& S = ts[wave];
-      const bool frame = s == 0 && step % dsc.stride == 0;
-      const int64_t fo = dsc.out_off + (step / dsc.stride) * dq + my_tgt * 3;
-#pragma unroll 1
-      for (int d = 0; d < 3; ++d) {
-        double Rj[kS];
+    // component d of group g by wavefront 3 g + d (mod NCH), as in the update
+    for (int u = wave; u < 3 * gpw; u += NCH) {
+      const int g = u / 3, d = u % 3;
+      const int tg = (g0 + g) * kLgT + t;
+      if (g0 + g >= L.ngroups || tg >= n) continue;
+      LgTargetState& S = ts[g];
+      double Rj[kS];
 #pragma unroll
-        for (int j = 0; j < kS; ++j) Rj[j] = rt[wave][d][t * kS + j];
-        double sv, sc;
-        step_sums<EXACT>(row_tab(T), Rj, sv, sc);
-        double vh = S.vh[t][d], vl = S.vl[t][d], qh = S.qh[t][d], ql = S.ql[t][d];
-        dw_add(vh, vl, sv);
-        dw_add(qh, ql, h * (vh - sc));
-        // every stage lane of the target computed the same values
-        S.qh[t][d] = qh;
-        S.ql[t][d] = ql;
-        S.vh[t][d] = vh;
-        S.vl[t][d] = vl;
-        S.mind[t][d] = __builtin_inf();
-        S.prv[t][d] = __builtin_inf();
-        tq[wave][d][lane] = gq[wave][d][lane];
-        if (frame) {
-          a.qout[fo + d] = qh;
-          a.pout[fo + d] = mass[my_tgt] * vh;
-        }
+      for (int j = 0; j < kS; ++j) Rj[j] = rt[g][d][t * kS + j];
+      double sv, sc;
+      step_sums<EXACT>(row_tab(T), Rj, sv, sc);
+      double vh = S.vh[t][d], vl = S.vl[t][d], qh = S.qh[t][d], ql = S.ql[t][d];
+      dw_add(vh, vl, sv);
+      dw_add(qh, ql, h * (vh - sc));
+      // every stage lane of the target computed the same values
+      S.qh[t][d] = qh;
+      S.ql[t][d] = ql;
+      S.vh[t][d] = vh;
+      S.vl[t][d] = vl;
+      S.mind[t][d] = __builtin_inf();
+      S.prv[t][d] = __builtin_inf();
+      tq[g][d][lane] = gq[g][d][lane];
+      if (s == 0 && step % dsc.stride == 0) {
+        const int64_t fo = dsc.out_off + (step / dsc.stride) * dq + tg * 3;
+        a.qout[fo + d] = qh;
+        a.pout[fo + d] = mass[tg] * vh;
       }
     }
+    __syncthreads();  // the new step's stage positions (tq) before any wavefront reads them
   }
 
   // ---- end of launch
