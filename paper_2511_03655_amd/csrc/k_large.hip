@@ -46,7 +46,7 @@ struct LargeArgs {
   int32_t n;        // bodies
   int32_t ngroups;  // ceil(n / 8)
   int32_t gpw;      // groups per workgroup
-  double* pos;      // [3][n][8] x (x, y, z, m)
+  double* pos;      // [3 buffers][x, y, z, m][n bodies][8 stages]
   // barrier control words (see grid_barrier); the release word carries the
   // generation << 2 | flags (bit 0 not converged, bit 1 non-finite)
   unsigned* ctl;
@@ -318,7 +318,8 @@ __global__ __launch_bounds__(64 * NCH) void large_kernel(LargeArgs L) {
     coef[tid][kS] = a.tab[kTabC + tid];
     coef[tid][kS + 1] = a.tab[kTabB + tid];
   }
-  const size_t bufsz = (size_t)n * kS;  // entries (4 doubles) per position buffer
+  const size_t n8 = (size_t)n * kS;  // (body, stage) entries per component array
+  const size_t bufsz = 4 * n8;       // doubles per position buffer
   double* pos = L.pos;
   int rbuf = 0;
 
@@ -342,12 +343,15 @@ __global__ __launch_bounds__(64 * NCH) void large_kernel(LargeArgs L) {
         for (int j = 0; j < kS; ++j) Rp[j] = Sp[4 * dq + c * kS + j];
         r0 = Rp[s];
         q0 = lg_guess<EXACT>(T, s, qh, vh, Rp, h);
-        pos_store(&pos[((size_t)my_tgt * kS + s) * 4 + d], q0);
+        pos_store(&pos[d * n8 + (size_t)my_tgt * kS + s], q0);
       }
       tq[wave][d][lane] = q0;
       rt[wave][d][lane] = r0;
     }
-    if (mine && step < target) pos_store(&pos[((size_t)my_tgt * kS + s) * 4 + 3], mass[my_tgt]);
+    // masses never change: written once per launch into all three buffers
+    if (mine && step < target)
+      for (int b = 0; b < 3; ++b)
+        pos_store(&pos[b * bufsz + 3 * n8 + (size_t)my_tgt * kS + s], mass[my_tgt]);
   }
   if (tid == 0) blk_flags = 0;
   __threadfence();
@@ -358,7 +362,7 @@ __global__ __launch_bounds__(64 * NCH) void large_kernel(LargeArgs L) {
   while (step < target) {
     ++k;
     const int wb = (rbuf + 1) % 3, gb = (rbuf + 2) % 3;  // new stage values, next guess
-    const double* P = pos + (size_t)rbuf * bufsz * 4;
+    const double* P = pos + (size_t)rbuf * bufsz;
     if (tid == 0) blk_flags = 0;  // last read by thread 0 inside the previous barrier
 
     for (int g = 0; g < gpw; ++g) {
@@ -380,9 +384,9 @@ __global__ __launch_bounds__(64 * NCH) void large_kernel(LargeArgs L) {
       for (int r = 0; r < WENT; ++r) {
         const int i = t + 8 * r;
         if (i < nw) {
-          const double* src = P + ((size_t)(wave + NCH * i) * kS + s) * 4;
+          const double* src = P + (size_t)(wave + NCH * i) * kS + s;
 #pragma unroll
-          for (int c = 0; c < 4; ++c) pre[r][c] = src[c];
+          for (int c = 0; c < 4; ++c) pre[r][c] = src[c * n8];
         }
       }
       double qx = 0.0, qy = 0.0, qz = 0.0;
@@ -409,9 +413,9 @@ __global__ __launch_bounds__(64 * NCH) void large_kernel(LargeArgs L) {
           for (int r = 0; r < WENT; ++r) {
             const int i = j1 + t + 8 * r;
             if (i < nw) {
-              const double* src = P + ((size_t)(wave + NCH * i) * kS + s) * 4;
+              const double* src = P + (size_t)(wave + NCH * i) * kS + s;
 #pragma unroll
-              for (int c = 0; c < 4; ++c) pre[r][c] = src[c];
+              for (int c = 0; c < 4; ++c) pre[r][c] = src[c * n8];
             }
           }
         }
@@ -493,13 +497,10 @@ __global__ __launch_bounds__(64 * NCH) void large_kernel(LargeArgs L) {
           S.prv[t][d] = prv;
           tq[g][d][lane] = qn;
           gq[g][d][lane] = qg;
-          pos_store(&pos[((size_t)wb * bufsz + (size_t)tgt * kS + s) * 4 + d], qn);
-          pos_store(&pos[((size_t)gb * bufsz + (size_t)tgt * kS + s) * 4 + d], qg);
-          if (d == 0) {
-            const double m = mass[tgt];
-            pos_store(&pos[((size_t)wb * bufsz + (size_t)tgt * kS + s) * 4 + 3], m);
-            pos_store(&pos[((size_t)gb * bufsz + (size_t)tgt * kS + s) * 4 + 3], m);
-          }
+          // lanes (t, s) of the group are 64 consecutive entries of the
+          // component array: one 512-byte store per wavefront
+          pos_store(&pos[wb * bufsz + d * n8 + (size_t)tgt * kS + s], qn);
+          pos_store(&pos[gb * bufsz + d * n8 + (size_t)tgt * kS + s], qg);
         }
         if (any) {
           const uint64_t notok = __ballot(!ok), badm = __ballot(bad);
