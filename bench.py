@@ -587,9 +587,9 @@ def run_c3(args):
     dtp = (time.perf_counter() - t) / 50
     integ.close()
     plain.close()
-    # bytes per 1000-step launch (the call timed here)
-    c3_traffic = traffic_from_profile("large_kernel_c3_plummer2048",
-                                      ["k_large.hip", "device_common.h"])
+    # bytes and issued FP64 flops per 1000-step launch (the call timed here)
+    prof = profile_record("large_kernel_c3_plummer2048", ["k_large.hip", "device_common.h"])
+    c3_traffic = prof.get("traffic_bytes_per_launch")
     sp = orc.Spec(orc.GRAVITY, 2048, 3, mass=inst["mass"], eps=inst["eps"])
     t = time.perf_counter()
     orc.integrate(sp, inst["q"], inst["p"], inst["h"], 10, 10)
@@ -604,6 +604,16 @@ def run_c3(args):
                                  "traffic": c3_traffic,
                                  "traffic_GBps": (c3_traffic / dt / 1e9
                                                   if c3_traffic else None),
+                                 "issued": ({"flops_per_launch":
+                                                 prof["issued_fp64_flops_per_launch"],
+                                             "achieved": prof["issued_fp64_flops_per_launch"]
+                                                 / dt / 1e12,
+                                             "frac": prof["issued_fp64_flops_per_launch"]
+                                                 / dt / 1e12 / FP64_PEAK_TFLOPS,
+                                             "source": "rocprofv3 SQ_INSTS_VALU_FLOPS_FP64 x 64 "
+                                                       "lanes, profiles/large_kernel_c3_"
+                                                       "plummer2048.md"}
+                                            if "issued_fp64_flops_per_launch" in prof else None),
                                  "kernel": "large_kernel (cooperative, whole GPU)"},
                     "plain": {"value": 1.0 / dtp, "unit": "steps/s",
                               "sample": "50 steps, one launch per step"},
