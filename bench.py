@@ -588,7 +588,8 @@ def run_c3(args):
     integ.close()
     plain.close()
     # bytes and issued FP64 flops per 1000-step launch (the call timed here)
-    prof = profile_record("large_kernel_c3_plummer2048", ["k_large.hip", "device_common.h"])
+    prof = profile_record("large_kernel_c3_plummer2048",
+                          ["k_large.hip", "device_common.h", "pair_weight.h"])
     c3_traffic = prof.get("traffic_bytes_per_launch")
     sp = orc.Spec(orc.GRAVITY, 2048, 3, mass=inst["mass"], eps=inst["eps"])
     t = time.perf_counter()
@@ -681,7 +682,8 @@ def run_c4(args):
           flush=True)
     c4_traffic = traffic_from_profile("uneven_mix_c4_4096",
                                       ["k_small.hip", "small_kernel.h", "k_stage.hip", "k_wg.hip",
-                                       "k_prepare.hip", "device_common.h", "runtime.hip"])
+                                       "k_prepare.hip", "device_common.h", "runtime.hip",
+                                       "pair_weight.h"])
     specs = [orc.Spec(mix[i]["kind"], mix[i]["n"], mix[i]["d"], mass=mix[i].get("mass"),
                       G=mix[i].get("G", 1.0), beta=mix[i].get("beta", 0.0)) for i in sample]
     t = time.perf_counter()

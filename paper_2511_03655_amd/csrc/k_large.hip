@@ -33,6 +33,7 @@
 // With EXACT (reproducible mode) a single chunk is used and every sum runs in
 // the reference order.
 #include "device_common.h"
+#include "pair_weight.h"
 
 namespace irk {
 
@@ -160,21 +161,14 @@ __device__ __forceinline__ double lg_guess(ConstTab T, int s, double q, double v
   return q + row_dot<EXACT>(T, kTabMu + s * kS, L0);
 }
 
-// Weight m (r2 + eps2)^(-3/2) of one source (eps2 already in r2).  Fast form:
-// the hardware reciprocal square root y0 (about 24 correct bits) refined by
-// one Halley step, y = y0 (1 + e/2 + 3 e^2/8) with e = 1 - r2 y0^2 (cubic
-// convergence: within 1 ulp of r2^(-1/2), like two Newton steps, in five
-// operations instead of seven), then cubed.
+// Weight m (r2 + eps2)^(-3/2) of one source (eps2 already in r2); fast form
+// with one Halley step (mass_rinv3_halley).
 template <bool EXACT>
 __device__ __forceinline__ double lg_weight(double r2, double m) {
-  if constexpr (EXACT) {
+  if constexpr (EXACT)
     return pair_weight<EXACT>(r2, m);
-  } else {
-    const double y0 = __builtin_amdgcn_rsq(r2);
-    const double e = fma(-r2, y0 * y0, 1.0);
-    const double y = fma(y0, e * fma(e, 0.375, 0.5), y0);
-    return m * ((y * y) * y);
-  }
+  else
+    return mass_rinv3_halley(r2, m);
 }
 
 // Squared distance in the reference order (EXACT) or with fused products.

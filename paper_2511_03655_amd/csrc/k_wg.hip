@@ -19,6 +19,7 @@
 // a slot whose system finishes pulls the next one from the class queue.  Per
 // system arithmetic does not depend on the slot or workgroup that runs it.
 #include "device_common.h"
+#include "pair_weight.h"
 
 namespace irk {
 
@@ -74,7 +75,7 @@ __device__ __forceinline__ void unit_increments(const double* __restrict__ Qs,
           double r2 = fma(dx[0], dx[0], eps2);
 #pragma unroll
           for (int d = 1; d < D; ++d) r2 = fma(dx[d], dx[d], r2);
-          const double w = mb * rinv3(r2);
+          const double w = mass_rinv3_halley(r2, mb);
 #pragma unroll
           for (int d = 0; d < D; ++d) acc[d][s] = fma(w, dx[d], acc[d][s]);
         }
