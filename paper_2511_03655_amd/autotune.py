@@ -59,8 +59,9 @@ def problem(inst):
     return p
 
 
-def time_batch(insts, nsteps, cache_values):
-    """Seconds of one integration call of `insts` with the given tuning table."""
+def time_batch(insts, nsteps, cache_values, reps=2):
+    """Seconds of one integration call of `insts` with the given tuning table
+    (the best of `reps` timed calls)."""
     with tempfile.NamedTemporaryFile("w", suffix=".json", delete=False) as f:
         json.dump(cache_values, f)
         path = f.name
@@ -79,7 +80,7 @@ def time_batch(insts, nsteps, cache_values):
     h = np.array([m["h"] for m in insts])
     integ.integrate(q0, p0, h, 2, 2)  # warm-up (code objects, allocations)
     best = float("inf")
-    for _ in range(2):
+    for _ in range(reps):
         t = time.perf_counter()
         integ.integrate(q0, p0, h, nsteps, nsteps)
         best = min(best, time.perf_counter() - t)
@@ -127,8 +128,10 @@ def cases(quick):
         cands = [b for b in (256, 512) if b >= s and b % s == 0]
         insts = [W.plummer(n, seed=200 + i) for i in range(16 if quick else 64)]
         out.append((f"wg/1/3/{s}", cands, insts, 5 if quick else 20))
+    # one call of the whole-GPU kernel lasts ~0.1 ms per step: 10^3 steps so that
+    # launch and copy overheads do not hide a few per cent between tiles
     insts = [W.plummer(2048, seed=300)]
-    out.append(("large/2048", [128, 256], insts, 20 if quick else 100))
+    out.append(("large/2048", [128, 256], insts, 200 if quick else 1000))
     return out
 
 
@@ -145,7 +148,7 @@ def main():
             continue
         times = {}
         for c in cands:
-            times[c] = time_batch(insts, nsteps, {key: c})
+            times[c] = time_batch(insts, nsteps, {key: c}, reps=3)
             print(f"autotune {key} candidate {c}: {times[c] * 1e3:.2f} ms", flush=True)
         best = min(times, key=times.get)
         result[key] = best
@@ -154,6 +157,9 @@ def main():
         chosen, rep = tune_schedule(args.quick, result)
         result.update(chosen)
         report.update(rep)
+    elif os.path.exists(args.out):  # launch shapes only: keep the schedule keys there
+        with open(args.out) as f:
+            result.update({k: v for k, v in json.load(f).items() if k.startswith("sched/")})
     with open(args.out, "w") as f:
         json.dump(result, f, indent=1, sort_keys=True)
     print(json.dumps({"cache": args.out, "chosen": result, "timings_ms": report}))
