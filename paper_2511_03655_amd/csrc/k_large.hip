@@ -5,14 +5,17 @@
 // into groups of 8 targets; workgroup w owns groups w*gpw .. w*gpw+gpw-1 and
 // wavefront g of the workgroup is the state wavefront of group g: lane
 // (t, s) = 8 t + s stands for target t at stage s.  Per fixed-point iteration:
-//  * force: for each owned group, the NCH wavefronts of the workgroup split the
-//    sources into NCH interleaved chunks (b = c mod NCH, ascending within a
-//    chunk).  Every source is used by one wavefront only, so each wavefront
-//    stages its own sources' stage positions in a region of LDS of its own,
-//    split into (x, y) and (z, m) arrays [b][stage] so that the 8 stage
-//    entries it reads at once are 128 contiguous bytes; the force loop needs
-//    no workgroup barrier.  Chunk partial sums are reduced in chunk order
-//    through LDS;
+//  * force: for each owned group, the sources are split into 32 interleaved
+//    chunks (b = c mod 32, ascending within a chunk) that the NCH wavefronts
+//    of the workgroup take in turn from an LDS ticket counter (a fixed share
+//    per wavefront let the oldest wavefront of each SIMD finish first and the
+//    last one finish alone, at half the SIMD's FP64 issue rate).  Every
+//    source is used by one wavefront only, so a wavefront stages its chunk's
+//    stage positions in a region of LDS of its own, split into (x, y) and
+//    (z, m) arrays [b][stage] so that the 8 stage entries it reads at once are
+//    128 contiguous bytes; the force loop needs no workgroup barrier.  Chunk
+//    partial sums go to per-chunk LDS slots and are added in chunk order, so
+//    the result does not depend on which wavefront took which chunk;
 //  * update, one component per wavefront (component d of group g by
 //    wavefront 3 g + d): R_s = h b_s G g_s, stage values
 //    Q_s = q + h (c_s v + sum_j eta_sj R_j) (eq. IRK_FP2) with the body's R_j
@@ -56,6 +59,8 @@ struct LargeArgs {
 template <int NCH, int TILE>
 struct LargeCfg {
   static constexpr int kThreads = 64 * NCH;
+  // source chunks per group and iteration, taken by the wavefronts in turn
+  static constexpr int kChunks = NCH > 1 ? 32 : 1;
   static constexpr int kTile = TILE;                  // sources per LDS tile
   static constexpr int kMaxGroups = NCH > 1 ? 4 : 1;  // groups per workgroup
 };
@@ -263,7 +268,9 @@ __global__ __launch_bounds__(64 * NCH) void large_kernel(LargeArgs L) {
   static_assert(CB * kS % 64 == 0, "a chunk is a whole number of entries per lane");
   __shared__ double2 sxy[NCH][CB * kS];       // per wavefront: [source][stage] (x, y)
   __shared__ double2 szm[NCH][CB * kS];       // per wavefront: [source][stage] (z, m)
-  __shared__ double part[NCH][3][64];         // chunk partial sums
+  constexpr int NCK = LargeCfg<NCH, TILE>::kChunks;
+  __shared__ double part[NCK > 1 ? NCK : 1][3][64];  // chunk partial sums
+  __shared__ unsigned tickets;                        // chunk tickets (never reset)
   __shared__ double tq[GM][3][64];            // current stage positions of the owned groups
   __shared__ double rt[GM][3][64];            // increments R of the owned groups
   __shared__ double gq[GM][3][64];            // tentative next-step initial guess
@@ -347,7 +354,11 @@ __global__ __launch_bounds__(64 * NCH) void large_kernel(LargeArgs L) {
       for (int b = 0; b < 3; ++b)
         pos_store(&pos[b * bufsz + 3 * n8 + (size_t)my_tgt * kS + s], mass[my_tgt]);
   }
-  if (tid == 0) blk_flags = 0;
+  if (tid == 0) {
+    blk_flags = 0;
+    tickets = 0;
+  }
+  unsigned tbase = 0;  // first ticket of the current group's chunks
   __threadfence();
   grid_barrier(L.ctl, gen, nblocks, &blk_flags, &bar_res);
 
@@ -363,74 +374,95 @@ __global__ __launch_bounds__(64 * NCH) void large_kernel(LargeArgs L) {
       const int grp = g0 + g;
       if (grp >= L.ngroups) break;  // uniform over the workgroup
       const int tgt = grp * kLgT + t;
-      // ---- force on the group's targets: this wavefront's sources b = wave,
-      // wave + NCH, ... (ascending), staged chunk by chunk in the
-      // wavefront's own LDS region (no other wavefront reads them, so only
-      // wavefront-level ordering is needed).  Lane (t, s) stages stage s of
-      // chunk sources t, t + 8, ...; the next chunk is fetched into registers
-      // while the current one is being used.
-      double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
-      const int nw = n > wave ? (n - wave + NCH - 1) / NCH : 0;  // sources of this wavefront
-      double2* wxy = sxy[wave];
-      double2* wzm = szm[wave];
-      double pre[WENT][4];
-#pragma unroll
-      for (int r = 0; r < WENT; ++r) {
-        const int i = t + 8 * r;
-        if (i < nw) {
-          const double* src = P + (size_t)(wave + NCH * i) * kS + s;
-#pragma unroll
-          for (int c = 0; c < 4; ++c) pre[r][c] = src[c * n8];
-        }
-      }
+      // ---- force on the group's targets.  The sources are split into NCK
+      // interleaved chunks (b = c mod NCK, ascending within a chunk) that the
+      // wavefronts take in turn from an LDS ticket counter, so the wavefronts
+      // of a SIMD finish together instead of the oldest first; chunk c's
+      // partial sums go to slot c and the update adds the slots in chunk
+      // order, so the result does not depend on which wavefront took which
+      // chunk.  A wavefront stages its chunk's sources in its own LDS region
+      // (no other wavefront reads them: wavefront-level ordering suffices).
+      // Lane (t, s) stages stage s of sources t, t + 8, ... of the chunk; the
+      // next part is fetched into registers while the current one is used.
       double qx = 0.0, qy = 0.0, qz = 0.0;
       if (tgt < n) {
         qx = tq[g][0][lane];
         qy = tq[g][1][lane];
         qz = tq[g][2][lane];
       }
-      for (int j0 = 0; j0 < nw; j0 += CB) {
-        const int cnt = min(CB, nw - j0);
-        lg_wave_lds_sync();  // the previous chunk's reads are done
+      // the update of the previous group has read its partial sums
+      if constexpr (NCK > 1) {
+        if (g > 0) __syncthreads();
+      }
+      double2* wxy = sxy[wave];
+      double2* wzm = szm[wave];
+      double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+      for (int taken = 0;; ++taken) {
+        int c;
+        if constexpr (NCK > 1) {
+          unsigned tk = 0;
+          if (lane == 0) tk = atomicAdd(&tickets, 1u);
+          c = (int)(__builtin_amdgcn_readfirstlane(tk) - tbase);
+        } else {
+          c = taken;  // a single chunk, all sources in order
+        }
+        if (c >= NCK) break;
+        acc0 = acc1 = acc2 = 0.0;
+        const int nw = n > c ? (n - c + NCK - 1) / NCK : 0;  // sources of this chunk
+        double pre[WENT][4];
 #pragma unroll
         for (int r = 0; r < WENT; ++r) {
           const int i = t + 8 * r;
-          if (i < cnt) {
-            wxy[i * kS + s] = make_double2(pre[r][0], pre[r][1]);
-            wzm[i * kS + s] = make_double2(pre[r][2], pre[r][3]);
+          if (i < nw) {
+            const double* src = P + (size_t)(c + NCK * i) * kS + s;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pre[r][q] = src[q * n8];
           }
         }
-        lg_wave_lds_sync();
-        const int j1 = j0 + CB;
-        if (j1 < nw) {
+        for (int j0 = 0; j0 < nw; j0 += CB) {
+          const int cnt = min(CB, nw - j0);
+          lg_wave_lds_sync();  // the previous part's reads are done
 #pragma unroll
           for (int r = 0; r < WENT; ++r) {
-            const int i = j1 + t + 8 * r;
-            if (i < nw) {
-              const double* src = P + (size_t)(wave + NCH * i) * kS + s;
-#pragma unroll
-              for (int c = 0; c < 4; ++c) pre[r][c] = src[c * n8];
+            const int i = t + 8 * r;
+            if (i < cnt) {
+              wxy[i * kS + s] = make_double2(pre[r][0], pre[r][1]);
+              wzm[i * kS + s] = make_double2(pre[r][2], pre[r][3]);
             }
           }
+          lg_wave_lds_sync();
+          const int j1 = j0 + CB;
+          if (j1 < nw) {
+#pragma unroll
+            for (int r = 0; r < WENT; ++r) {
+              const int i = j1 + t + 8 * r;
+              if (i < nw) {
+                const double* src = P + (size_t)(c + NCK * i) * kS + s;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) pre[r][q] = src[q * n8];
+              }
+            }
+          }
+          if (tgt < n) {
+            // with softening the self term needs no special case (w finite,
+            // displacement 0); without it the self distance is replaced
+            const int b0 = c + NCK * j0;
+            if (eps2 > 0.0)
+              lg_force_chunk<EXACT, NCK, false>(wxy, wzm, cnt, s, b0, tgt, qx, qy, qz, eps2,
+                                                acc0, acc1, acc2);
+            else
+              lg_force_chunk<EXACT, NCK, true>(wxy, wzm, cnt, s, b0, tgt, qx, qy, qz, eps2,
+                                               acc0, acc1, acc2);
+          }
         }
-        if (tgt < n) {
-          // with softening the self term needs no special case (w finite,
-          // displacement 0); without it the self distance is replaced
-          const int b0 = wave + NCH * j0;
-          if (eps2 > 0.0)
-            lg_force_chunk<EXACT, NCH, false>(wxy, wzm, cnt, s, b0, tgt, qx, qy, qz, eps2, acc0,
-                                              acc1, acc2);
-          else
-            lg_force_chunk<EXACT, NCH, true>(wxy, wzm, cnt, s, b0, tgt, qx, qy, qz, eps2, acc0,
-                                             acc1, acc2);
+        if constexpr (NCK > 1) {
+          part[c][0][lane] = acc0;
+          part[c][1][lane] = acc1;
+          part[c][2][lane] = acc2;
         }
       }
-      if constexpr (NCH > 1) {
-        // the state wavefront of the previous group has read its partial sums
-        if (g > 0) __syncthreads();
-        part[wave][0][lane] = acc0;
-        part[wave][1][lane] = acc1;
-        part[wave][2][lane] = acc2;
+      if constexpr (NCK > 1) {
+        tbase += NCK + NCH;  // NCK chunks and one empty ticket per wavefront
         __syncthreads();
       }
       if (tgt < n) {
@@ -447,7 +479,7 @@ __global__ __launch_bounds__(64 * NCH) void large_kernel(LargeArgs L) {
           if constexpr (NCH > 1) {
             gsum = part[0][d][lane];
 #pragma unroll
-            for (int c = 1; c < NCH; ++c) gsum += part[c][d][lane];
+            for (int c = 1; c < NCK; ++c) gsum += part[c][d][lane];
           } else {
             gsum = d == 0 ? acc0 : (d == 1 ? acc1 : acc2);
           }
