@@ -4,8 +4,9 @@
 Tunes, on the GPU it runs on, the shapes that do not change results:
 
 * ``wg/<kind>/<d>/<S>`` -- lanes per workgroup of the workgroup kernel for
-  systems in slots of S lanes (systems per workgroup = block / S), timed on a
-  batch of such systems;
+  systems in slots of S lanes (systems per workgroup = block / S; gravity in
+  the fast mode up to 256 bodies uses slots of 2 S lanes), timed on a batch of
+  such systems;
 * ``large/<n>`` -- sources staged per tile (128 or 256, split over the
   workgroup's 16 wavefronts) of the whole-GPU kernel for one system of up to
   n bodies;
@@ -125,7 +126,10 @@ def cases(quick):
         out.append((f"wg/2/1/{s}", cands, insts, 100 if quick else 300))
     for n in (256,):
         s = slot_width(n)
-        cands = [b for b in (256, 512) if b >= s and b % s == 0]
+        # the fast mode gives gravity systems of up to 256 bodies two lanes per
+        # body: the slot is twice the body slot (one candidate at 256 bodies)
+        lanes = 2 * s if 2 * s <= 512 else s
+        cands = [b for b in (256, 512) if b >= lanes and b % lanes == 0]
         insts = [W.plummer(n, seed=200 + i) for i in range(16 if quick else 64)]
         out.append((f"wg/1/3/{s}", cands, insts, 5 if quick else 20))
     # one call of the whole-GPU kernel lasts ~0.1 ms per step: 10^3 steps so that

@@ -44,7 +44,8 @@ template <int KIND, int D, bool EXACT>
 __device__ __forceinline__ void unit_increments(const double* __restrict__ Qs,
                                                 const double* __restrict__ Ms, int base, int u,
                                                 int n, const WgMeta& M, double kl, double kr,
-                                                ConstTab T, double h, double (&R)[D][kS]) {
+                                                ConstTab T, double h, double (&R)[D][kS],
+                                                int b_lo, int b_hi) {
   // The lane's own stage positions are read back from the tile (it published
   // them there), so they need not stay in registers across the force loop.
   constexpr int US = wg_unit_stride<D>();
@@ -54,7 +55,7 @@ __device__ __forceinline__ void unit_increments(const double* __restrict__ Qs,
     // (instruction-level parallelism); each stage's sum keeps the b order.
     const double eps2 = M.eps2;
     double acc[D][kS] = {};
-    for (int b = 0; b < n; ++b) {
+    for (int b = b_lo; b < b_hi; ++b) {
       if (b == u) continue;
       const double* qb = Qs + (size_t)(base + b) * US;
       const double mb = Ms[base + b];
@@ -114,7 +115,16 @@ __device__ __forceinline__ void unit_increments(const double* __restrict__ Qs,
   }
 }
 
-template <int KIND, int D, bool EXACT, int MAXT>
+// SPLIT (gravity, fast mode, systems of up to 256 bodies): a slot of S lanes
+// holds one system on S / 2 body lanes; lane u >= S / 2 helps body u - S / 2 by
+// summing the upper half of the sources (b >= ceil(n / 2)) while the body lane
+// sums the lower half, and passes its increments through its own row of the
+// stage tile (no body's unit lives there); the body lane's increment is the
+// sum lower + upper.  A lone system of 256 bodies then keeps two wavefronts
+// per SIMD busy instead of one (one wavefront alone issues FP64 work at about
+// half the SIMD's rate).  Arithmetic per system still depends on its size
+// only.
+template <int KIND, int D, bool EXACT, int MAXT, bool SPLIT>
 __global__ __launch_bounds__(MAXT) void wg_kernel(LaunchArgs a, int S) {
   extern __shared__ double lds[];
   const int TT = blockDim.x;
@@ -128,7 +138,10 @@ __global__ __launch_bounds__(MAXT) void wg_kernel(LaunchArgs a, int S) {
 
   const int tid = threadIdx.x;
   const int slot = tid / S;
-  const int u = tid - slot * S;
+  const int us = tid - slot * S;            // lane within the slot
+  const int Sb = SPLIT ? S / 2 : S;         // body lanes of the slot
+  const bool helper = SPLIT && us >= Sb;    // sums the upper half of the sources
+  const int u = helper ? us - Sb : us;      // body of this lane
   const int base = slot * S;
   WgMeta& M = meta[slot];
   const ConstTab T = const_tab(a.tab);
@@ -146,7 +159,7 @@ __global__ __launch_bounds__(MAXT) void wg_kernel(LaunchArgs a, int S) {
   __syncthreads();
 
   for (;;) {
-    if (u == 0 && slot_inst[slot] < 0 && !*qdone) {
+    if (us == 0 && slot_inst[slot] < 0 && !*qdone) {
       if (a.queue_head) {
         const int idx = atomicAdd(a.queue_head, 1);
         if (idx < queue_length(a))
@@ -163,7 +176,7 @@ __global__ __launch_bounds__(MAXT) void wg_kernel(LaunchArgs a, int S) {
     if (__syncthreads_or(cur >= 0) == 0) break;
 
     const bool fresh = cur >= 0 && cur != inst;
-    if (fresh && u == 0) {
+    if (fresh && us == 0) {
       const InstDesc& dsc = a.desc[cur];
       const InstStat st = a.stat[cur];
       M.inst = cur;
@@ -185,7 +198,10 @@ __global__ __launch_bounds__(MAXT) void wg_kernel(LaunchArgs a, int S) {
     }
     __syncthreads();
     const int n = (cur >= 0) ? M.n : 0;
-    const bool mine = u < n;  // this lane owns a unit of the slot's system
+    const bool mine = u < n && !helper;  // this lane owns a unit of the slot's system
+    const bool forces = u < n;           // this lane sums forces on unit u
+    const int nh = SPLIT ? (n + 1) / 2 : n;
+    const int b_lo = helper ? nh : 0, b_hi = (SPLIT && !helper) ? nh : n;
     if (fresh) {
       inst = cur;
       const InstDesc& dsc = a.desc[cur];
@@ -231,14 +247,32 @@ __global__ __launch_bounds__(MAXT) void wg_kernel(LaunchArgs a, int S) {
     int k = 0;
     while (__syncthreads_or(!conv)) {
       ++k;
-      if (!conv && u == 0) {
+      if (!conv && us == 0) {
         M.notok = 0;
         M.bad = 0;
       }
       __syncthreads();
       double Qn[D][kS] = {};
+      if (!conv && forces)
+        unit_increments<KIND, D, EXACT>(Qs, Ms, base, u, n, M, kl, kr, T, h, R, b_lo, b_hi);
+      if constexpr (SPLIT) {
+        // the helper's increments go to its own tile row; the body lane adds them
+        double* row = Qs + (size_t)(base + Sb + u) * US;
+        if (!conv && forces && helper) {
+#pragma unroll
+          for (int s = 0; s < kS; ++s)
+#pragma unroll
+            for (int d = 0; d < D; ++d) row[s * D + d] = R[d][s];
+        }
+        __syncthreads();
+        if (!conv && mine) {
+#pragma unroll
+          for (int s = 0; s < kS; ++s)
+#pragma unroll
+            for (int d = 0; d < D; ++d) R[d][s] = R[d][s] + row[s * D + d];
+        }
+      }
       if (!conv && mine) {
-        unit_increments<KIND, D, EXACT>(Qs, Ms, base, u, n, M, kl, kr, T, h, R);
         const double* qa = Qs + (size_t)(base + u) * US;
         bool ok = true, bad = false;
         double dmax[D], nf[D];
@@ -267,7 +301,7 @@ __global__ __launch_bounds__(MAXT) void wg_kernel(LaunchArgs a, int S) {
         const bool slot_ok = M.notok == 0;
         if (slot_ok || slot_bad || k >= a.max_iter) {
           conv = true;
-          if (u == 0) {
+          if (us == 0) {
             M.kslot = k;
             M.flags = (slot_bad ? 1 : 0) | ((!slot_ok && !slot_bad) ? 2 : 0);
           }
@@ -297,7 +331,7 @@ __global__ __launch_bounds__(MAXT) void wg_kernel(LaunchArgs a, int S) {
               a.pout[out_off + f * dq + u * D + d] = __builtin_nan("");
             }
         }
-        if (u == 0) {
+        if (us == 0) {
           if (M.iters_off >= 0) a.step_iters[M.iters_off + step0] = (uint8_t)kslot;
           InstStat st;
           st.steps_done = step0;
@@ -338,7 +372,7 @@ __global__ __launch_bounds__(MAXT) void wg_kernel(LaunchArgs a, int S) {
           }
           if (!last) initial_guess<D, EXACT>(T, qh, vh, R, h, Q);
         }
-        if (u == 0) {
+        if (us == 0) {
           if (M.iters_off >= 0) a.step_iters[M.iters_off + step0] = (uint8_t)kslot;
           M.step = step;
           M.it_sum += kslot;
@@ -359,7 +393,7 @@ __global__ __launch_bounds__(MAXT) void wg_kernel(LaunchArgs a, int S) {
     }
     __syncthreads();
     if (release) {
-      if (u == 0) slot_inst[slot] = -1;
+      if (us == 0) slot_inst[slot] = -1;
       inst = -1;
     }
     __syncthreads();
@@ -401,14 +435,20 @@ bool wg_class_supported(int kind, int n, int d) {
 template <int KIND, int D>
 hipError_t launch_wg(const LaunchArgs& a, int S, int n_items, int num_cus, hipStream_t st,
                      int block) {
-  // tuned block: a multiple of the slot width and of 64, at least the slot
   constexpr int MAXT = (KIND == kGravity) ? 512 : 1024;
+  // gravity in the fast mode up to 256 bodies: two lanes per body (SPLIT), so
+  // the slot is twice the body slot
+  const bool split = KIND == kGravity && !a.exact && 2 * S <= MAXT;
+  if (split) S *= 2;
+  // tuned block: a multiple of the slot width and of 64, at least the slot
   const int TT = (block >= S && block % S == 0 && block % 64 == 0 && block <= MAXT)
                      ? block
                      : wg_block_size(S);
   const size_t lds = wg_lds_bytes(TT, S, D);
   if (TT > MAXT) return hipErrorInvalidConfiguration;
-  auto kern = a.exact ? wg_kernel<KIND, D, true, MAXT> : wg_kernel<KIND, D, false, MAXT>;
+  auto kern = a.exact ? wg_kernel<KIND, D, true, MAXT, false>
+                      : (split ? wg_kernel<KIND, D, false, MAXT, KIND == kGravity>
+                               : wg_kernel<KIND, D, false, MAXT, false>);
   hipError_t e = hipFuncSetAttribute((const void*)kern,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
