@@ -2,9 +2,9 @@
 // 8192, e.g. a 2048-body Plummer cluster): the whole GPU works on one system.
 //
 // One cooperative persistent launch per integration call.  The bodies are cut
-// into groups of 8 targets; workgroup w owns groups w*gpw .. w*gpw+gpw-1 and
-// wavefront g of the workgroup is the state wavefront of group g: lane
-// (t, s) = 8 t + s stands for target t at stage s.  Per fixed-point iteration:
+// into groups of 8 targets; workgroup w owns groups w*gpw .. w*gpw+gpw-1, and
+// in every wavefront lane (t, s) = 8 t + s stands for target t at stage s of
+// the group at hand.  Per fixed-point iteration:
 //  * force: for each owned group, the sources are split into 32 interleaved
 //    chunks (b = c mod 32, ascending within a chunk) that the NCH wavefronts
 //    of the workgroup take in turn from an LDS ticket counter (a fixed share
