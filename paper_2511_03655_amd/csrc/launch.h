@@ -37,6 +37,11 @@ hipError_t launch_order(const int32_t* qin, int32_t* qout, int32_t count, const 
 hipError_t launch_small_class(int kind, int nb, int d, const LaunchArgs& a, int n_items,
                               int num_cus, hipStream_t st);
 bool small_class_supported(int kind, int nb, int d);
+// Latency kernel for a few Kepler orbits (one 8-lane wavefront per orbit;
+// bit-identical to the small-system kernel): whether a launch qualifies, and
+// the launch.
+bool kepler_lane_supported(int d, int n_items, const LaunchArgs& a);
+hipError_t launch_kepler_lanes(int d, const LaunchArgs& a, int n_items, hipStream_t st);
 hipError_t launch_wg_class(int kind, int d, int S, const LaunchArgs& a, int n_items, int num_cus,
                            hipStream_t st, int block = 0);
 bool wg_class_supported(int kind, int n, int d);
@@ -111,7 +116,12 @@ inline hipError_t launch_batched(int cls, int kind, int size, int d, const Launc
                                  int n_items, int num_cus, hipStream_t st,
                                  const LaunchTune& tune = LaunchTune()) {
   switch (cls) {
-    case kClassSmall: return launch_small_class(kind, size, d, a, n_items, num_cus, st);
+    case kClassSmall:
+      // a few Kepler orbits: one 8-lane wavefront each (the same arithmetic
+      // as the slot kernel, a shorter iteration)
+      if (kind == kKepler && kepler_lane_supported(d, n_items, a))
+        return launch_kepler_lanes(d, a, n_items, st);
+      return launch_small_class(kind, size, d, a, n_items, num_cus, st);
     case kClassWg: return launch_wg_class(kind, d, size, a, n_items, num_cus, st, tune.wg_block);
     case kClassStage: return launch_stage_class(d, size, a, n_items, num_cus, st);
     default: return hipErrorInvalidValue;

@@ -1,0 +1,109 @@
+"""Kepler orbits in small batches (at most 64) run in the one-wavefront-per-
+orbit latency kernel; larger batches run in the eight-slot small-system
+kernel.  Both evaluate the same operations in the same order, so an orbit's
+trajectory, per-step iteration counts and status must not depend on the batch
+it comes in: bit-identical results alone, in a batch of 64 and in a batch of
+100, in both arithmetic modes, in 2 and 3 dimensions, across launches (plain
+form: one launch per step, the state handed over through device memory) and
+for a non-finite orbit."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2511_03655_amd import irkgl16 as K
+
+pytestmark = pytest.mark.gpu
+
+
+def _orbits(n, d, seed):
+    """Bound orbits around a unit central mass (G = 1): radius 0.3..1.5,
+    speed 0.6..1.3 of the circular speed, random direction of motion in the
+    plane normal to a random axis (d = 3)."""
+    rng = np.random.default_rng(seed)
+    r = rng.uniform(0.3, 1.5, n)
+    f = rng.uniform(0.6, 1.3, n)
+    if d == 2:
+        a = rng.uniform(0, 2 * math.pi, n)
+        q = np.stack([r * np.cos(a), r * np.sin(a)], 1)
+        t = np.stack([-np.sin(a), np.cos(a)], 1)
+    else:
+        u = rng.normal(size=(n, 3))
+        u /= np.linalg.norm(u, axis=1, keepdims=True)
+        w = rng.normal(size=(n, 3))
+        w -= np.sum(w * u, 1, keepdims=True) * u
+        w /= np.linalg.norm(w, axis=1, keepdims=True)
+        q = r[:, None] * u
+        t = w
+    p = (f * np.sqrt(1.0 / r))[:, None] * t
+    return q.ravel(), p.ravel()
+
+
+def _run(n, d, q0, p0, steps, stride, flags=0, max_iter=100):
+    probs = [dict(kind=K.IRKGL16_KEPLER, n=1, d=d, G=1.0)] * n
+    integ = K.Integrator(probs, record_iters=True, flags=flags, max_iter=max_iter)
+    return integ.integrate(q0, p0, 2 * math.pi / 128, steps, stride)
+
+
+def _same(a, b, lo, hi, steps):
+    """a (whole result) against instances lo..hi-1 of b."""
+    qa, pa, sa, _ = a
+    qb, pb, sb, _ = b
+    nfq = qa.size // (hi - lo)
+    assert np.array_equal(qa, qb[lo * nfq:hi * nfq], equal_nan=True)
+    assert np.array_equal(pa, pb[lo * nfq:hi * nfq], equal_nan=True)
+    assert np.array_equal(sa["step_iters"], sb["step_iters"][lo * steps:hi * steps])
+    assert np.array_equal(sa["inst_iterations"], sb["inst_iterations"][lo:hi])
+    assert np.array_equal(sa["inst_status"], sb["inst_status"][lo:hi])
+
+
+@pytest.mark.parametrize("flags", [0, K.IRKGL16_REPRODUCIBLE])
+@pytest.mark.parametrize("d", [2, 3])
+def test_orbit_alone_equals_in_batches(flags, d):
+    N, steps, stride = 100, 600, 50
+    q0, p0 = _orbits(N, d, seed=50 + d)
+    big = _run(N, d, q0, p0, steps, stride, flags)  # eight-slot kernel
+    assert big[3] == 0
+    few = _run(64, d, q0[:64 * d], p0[:64 * d], steps, stride, flags)  # latency kernel
+    _same(few, big, 0, 64, steps)
+    for i in (0, 37, 99):
+        one = _run(1, d, q0[i * d:(i + 1) * d], p0[i * d:(i + 1) * d], steps, stride, flags)
+        _same(one, big, i, i + 1, steps)
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_plain_form_equals_batched(d):
+    N, steps, stride = 100, 80, 10
+    q0, p0 = _orbits(N, d, seed=7)
+    big = _run(N, d, q0, p0, steps, stride)
+    probs = [dict(kind=K.IRKGL16_KEPLER, n=1, d=d, G=1.0)] * 3
+    integ = K.Integrator(probs, record_iters=True, flags=K.IRKGL16_PLAIN)
+    plain = integ.integrate(q0[:3 * d], p0[:3 * d], 2 * math.pi / 128, steps, stride)
+    _same(plain, big, 0, 3, steps)
+
+
+def test_nonfinite_orbit_alone_equals_in_batch():
+    """An orbit started at rest at the centre (every stage value at r = 0)
+    turns non-finite in its first step: NaN frames, status non-finite, the
+    other orbits unaffected."""
+    N, d, steps, stride = 100, 2, 20, 5
+    q0, p0 = _orbits(N, d, seed=11)
+    q0[3 * d:4 * d] = 0.0
+    p0[3 * d:4 * d] = 0.0
+    big = _run(N, d, q0, p0, steps, stride)
+    few = _run(8, d, q0[:8 * d], p0[:8 * d], steps, stride)
+    assert big[3] == K.IRKGL16_ENONFINITE and few[3] == K.IRKGL16_ENONFINITE
+    assert few[2]["inst_status"][3] == K.IRKGL16_ENONFINITE
+    nf = steps // stride + 1
+    assert np.all(np.isnan(few[0][3 * nf * d + d:4 * nf * d]))
+    assert np.all(np.isfinite(np.delete(few[0], np.s_[3 * nf * d:4 * nf * d])))
+    _same(few, big, 0, 8, steps)
+
+
+def test_iteration_cap_alone_equals_in_batch():
+    N, d, steps, stride = 100, 2, 30, 10
+    q0, p0 = _orbits(N, d, seed=12)
+    big = _run(N, d, q0, p0, steps, stride, max_iter=2)
+    few = _run(5, d, q0[:5 * d], p0[:5 * d], steps, stride, max_iter=2)
+    assert few[3] == K.IRKGL16_ENOCONV
+    _same(few, big, 0, 5, steps)
