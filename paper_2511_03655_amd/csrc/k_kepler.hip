@@ -6,54 +6,63 @@
 // a component role and through the slot bookkeeping that keeps eight
 // independent systems in step.  A lone orbit (a batch of a few) pays all of
 // that on its critical path.  Here each lane holds its own stage: the force
-// (eq. Gi) is lane-local, the 8 increments R_j reach every lane by shuffles,
-// the stage update (eq. IRK_FP2) uses the lane's eta row held in registers,
+// (eq. Gi) is lane-local, the 8 increments R_j reach every lane through a
+// small LDS tile (one write and D reads of 16 or 8 bytes per stage, ordered by
+// the wavefront's in-order LDS pipeline rather than a barrier), the stage
+// update (eq. IRK_FP2) uses the lane's eta row held in registers,
 // the max-norm increment (eq. Delta_n) is a DPP maximum over the 8 lanes and
 // the stopping rule (eq. stopping), the compensated update (eq. qnvn2) and the
 // next initial guess (eq. IRK_init2) run redundantly (update) or per stage
 // (guess) in the lanes.  Every operation is the few-body kernel's own, in the
 // same order (kepler_increment, stage_value, step_sums / dw_add, guess_stage),
 // so an orbit gives the same bits in either kernel and the choice between them
-// can depend on the batch.
+// can depend on the batch.  The instance's bookkeeping is wave-uniform (scalar
+// registers), and the frame number advances by counting steps instead of a
+// 64-bit division per step.
 #include "device_common.h"
 #include "launch.h"
 #include "store_index.h"
 
 namespace irk {
 
-// Maximum over the 8 stage lanes (DPP: swap neighbours, swap pairs, mirror
-// within the 8 lanes); exact in any order.  fmax drops NaN: non-finite values
-// are detected separately.
-__device__ __forceinline__ double kp_group_max(double x) {
-  x = fmax(x, dpp_double<0xB1>(x));
-  x = fmax(x, dpp_double<0x4E>(x));
-  return fmax(x, dpp_double<0x141>(x));
+// A double from another lane of the 8-lane group by a DPP pattern (0xB1: lane
+// xor 1, 0x4E: lane xor 2, 0x141: mirror within the 8 lanes).  All 8 lanes of
+// the group are active and every pattern stays inside the group, so no lane
+// reads an inactive source.
+template <int CTRL>
+__device__ __forceinline__ double kp_dpp(double x) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
 }
 
-// q + h (c v + sum_j M_j R_j) with the row M and c of this lane's stage in
-// registers: the operations of stage_value<false> in the same order.
-__device__ __forceinline__ double kp_row_value(const double (&row)[kS], double c, double q,
-                                               double v, double h, const double (&R)[kS]) {
-  double acc = c * v;
-#pragma unroll
-  for (int j = 0; j < kS; ++j) acc = fma(row[j], R[j], acc);
-  return fma(h, acc, q);
+// Orders the LDS accesses of the lanes of this one-wavefront workgroup: a
+// wavefront's LDS operations execute in program order, so fences at wavefront
+// scope (which emit no wait) and the wave barrier only keep the compiler from
+// moving accesses across this point.
+__device__ __forceinline__ void kp_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <int D, bool EXACT>
 __global__ __launch_bounds__(kS) void kepler_lane_kernel(LaunchArgs a) {
   const int s = threadIdx.x;  // stage
   const ConstTab T = const_tab(a.tab);
+  // this iteration's increments, [stage][component]
+  __shared__ __align__(16) double xr[kS * D];
 
-  // instance of this wavefront
+  // instance of this wavefront (wave-uniform: its bookkeeping lives in
+  // scalar registers)
   int idx = (int)blockIdx.x;
   if (a.queue_head) {
     int got = 0;
     if (s == 0) got = atomicAdd(a.queue_head, 1);
-    idx = __shfl(got, 0, kS);
+    idx = __builtin_amdgcn_readfirstlane(got);
   }
   if (idx >= queue_length(a)) return;
-  const int inst = a.queue[idx];
+  const int inst = __builtin_amdgcn_readfirstlane(a.queue[idx]);
   const InstDesc& dsc = a.desc[inst];
   const InstStat st0 = a.stat[inst];
   const double h = dsc.h, G = dsc.G;
@@ -65,6 +74,10 @@ __global__ __launch_bounds__(kS) void kepler_lane_kernel(LaunchArgs a) {
   int32_t maxk = st0.max_k;
   int32_t status = st0.status;
   const double m = (dsc.mass_off >= 0) ? a.params[dsc.mass_off] : 1.0;
+  // next frame: number fnext, written at the end of step fstep (one division
+  // per launch instead of one per step)
+  int64_t fnext = step / stride + 1;
+  int64_t fstep = fnext * stride;
   const double hb = h * T[kTabB + s];
   // the fast mode's rows of this lane's stage (eta for the iteration, the
   // folded K for the initial guess)
@@ -75,14 +88,35 @@ __global__ __launch_bounds__(kS) void kepler_lane_kernel(LaunchArgs a) {
     kg[j] = a.tab[kTabK + s * kS + j];
   }
   const double cs = a.tab[kTabC + s];
-  auto guess = [&](double q, double v, const double (&Rp)[kS]) {
-    if constexpr (EXACT)
-      return guess_stage<kKepler, true>(T, s, q, v, Rp, h);
-    else
-      return kp_row_value(kg, cs, q, v, h, Rp);
-  };
+  // all nodes c_j (wave-uniform) for the end-of-step sums
+  double cn[kS];
+#pragma unroll
+  for (int j = 0; j < kS; ++j) cn[j] = T[kTabC + j];
 
   double qh[D], ql[D], vh[D], vl[D], Q[D], R[D], Rall[D][kS];
+  // stage value of every component from the rows of this lane's stage: the
+  // operations of stage_value<false> (M = eta) or of the folded guess (M = K),
+  // with the components' chains interleaved
+  auto rows_value = [&](const double (&row)[kS], const double (&Rj)[D][kS], double (&out)[D]) {
+    double acc[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) acc[d] = cs * vh[d];
+#pragma unroll
+    for (int j = 0; j < kS; ++j)
+#pragma unroll
+      for (int d = 0; d < D; ++d) acc[d] = fma(row[j], Rj[d][j], acc[d]);
+#pragma unroll
+    for (int d = 0; d < D; ++d) out[d] = fma(h, acc[d], qh[d]);
+  };
+  auto guess = [&]() {
+    if constexpr (EXACT) {
+#pragma unroll
+      for (int d = 0; d < D; ++d) Q[d] = guess_stage<kKepler, true>(T, s, qh[d], vh[d], Rall[d], h);
+    } else {
+      rows_value(kg, Rall, Q);
+    }
+  };
+
   if (step < target) {
     // state and this lane's stage of the initial guess
 #pragma unroll
@@ -93,9 +127,9 @@ __global__ __launch_bounds__(kS) void kepler_lane_kernel(LaunchArgs a) {
       vl[d] = a.state[state_index(state_off, D, 3, d)];
 #pragma unroll
       for (int j = 0; j < kS; ++j) Rall[d][j] = a.state[rprev_index(state_off, D, d, j, kS)];
-      Q[d] = guess(qh[d], vh[d], Rall[d]);
-      R[d] = Rall[d][s];
+      R[d] = 0.0;  // set by every iteration; stored only after a step
     }
+    guess();
   }
 
   while (step < target) {
@@ -107,22 +141,41 @@ __global__ __launch_bounds__(kS) void kepler_lane_kernel(LaunchArgs a) {
     for (;;) {
       ++k;
       kepler_increment<D, EXACT>(Q, hb, G, R);
+      // every lane takes the 8 stages' increments
 #pragma unroll
-      for (int d = 0; d < D; ++d)
+      for (int d = 0; d < D; ++d) xr[s * D + d] = R[d];
+      kp_wave_sync();
 #pragma unroll
-        for (int j = 0; j < kS; ++j) Rall[d][j] = __shfl(R[d], j, kS);
-      ok = true;
+      for (int j = 0; j < kS; ++j)
+#pragma unroll
+        for (int d = 0; d < D; ++d) Rall[d][j] = xr[j * D + d];
+      kp_wave_sync();
+      double qn[D], dm[D];
+      if constexpr (EXACT) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) qn[d] = stage_value<true>(T, s, qh[d], vh[d], h, Rall[d]);
+      } else {
+        rows_value(eta, Rall, qn);
+      }
       bool nf = false;
 #pragma unroll
       for (int d = 0; d < D; ++d) {
-        const double qn = EXACT ? stage_value<true>(T, s, qh[d], vh[d], h, Rall[d])
-                                : kp_row_value(eta, cs, qh[d], vh[d], h, Rall[d]);
-        const double dd = fabs(qn - Q[d]);
-        nf |= !finite(dd);
-        const double dmax = kp_group_max(dd);
-        Q[d] = qn;
-        ok &= stop_component(dmax, mind[d], prv[d]);
+        dm[d] = fabs(qn[d] - Q[d]);
+        nf |= !__builtin_isfinite(dm[d]);
+        Q[d] = qn[d];
       }
+      // max-norm over the 8 stages (exact in any order; fmax drops NaN, which
+      // nf has caught)
+#pragma unroll
+      for (int d = 0; d < D; ++d) dm[d] = fmax(dm[d], kp_dpp<0xB1>(dm[d]));
+#pragma unroll
+      for (int d = 0; d < D; ++d) dm[d] = fmax(dm[d], kp_dpp<0x4E>(dm[d]));
+#pragma unroll
+      for (int d = 0; d < D; ++d) dm[d] = fmax(dm[d], kp_dpp<0x141>(dm[d]));
+      int okl = 1;
+#pragma unroll
+      for (int d = 0; d < D; ++d) okl &= stop_component(dm[d], mind[d], prv[d]) ? 1 : 0;
+      ok = __builtin_amdgcn_readfirstlane(okl) != 0;  // the same in every lane
       bad = __ballot(nf) != 0;
       if (bad || ok || k >= a.max_iter) break;
     }
@@ -145,17 +198,44 @@ __global__ __launch_bounds__(kS) void kepler_lane_kernel(LaunchArgs a) {
     it_sum += k;
     nonconv += ok ? 0 : 1;
     maxk = k > maxk ? k : maxk;
-    const bool frame = (step % stride) == 0;
+    if constexpr (EXACT) {
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      form_update<kKepler, EXACT>(row_tab(T), Rall[d], h, qh[d], ql[d], vh[d], vl[d]);
-      if (s == 0 && frame) {
-        const int64_t f = step / stride;
-        a.qout[frame_index(out_off, f, D, d)] = qh[d];
-        a.pout[frame_index(out_off, f, D, d)] = m * vh[d];
+      for (int d = 0; d < D; ++d)
+        form_update<kKepler, true>(row_tab(T), Rall[d], h, qh[d], ql[d], vh[d], vl[d]);
+    } else {
+      // form_update's operations (step_sums, then the two compensated
+      // additions) with the nodes held in registers
+      double sv[D], sc[D];
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        sv[d] = Rall[d][0];
+        sc[d] = cn[0] * Rall[d][0];
       }
-      if (step < target) Q[d] = guess(qh[d], vh[d], Rall[d]);
+#pragma unroll
+      for (int i = 1; i < kS; ++i)
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          sv[d] += Rall[d][i];
+          sc[d] = fma(cn[i], Rall[d][i], sc[d]);
+        }
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        dw_add(vh[d], vl[d], sv[d]);
+        dw_add(qh[d], ql[d], h * (vh[d] - sc[d]));
+      }
     }
+    if (step == fstep) {
+      if (s == 0) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          a.qout[frame_index(out_off, fnext, D, d)] = qh[d];
+          a.pout[frame_index(out_off, fnext, D, d)] = m * vh[d];
+        }
+      }
+      ++fnext;
+      fstep += stride;
+    }
+    if (step < target) guess();
   }
 
   if (step > st0.steps_done && status == kOk) {  // resumable state for a later launch
