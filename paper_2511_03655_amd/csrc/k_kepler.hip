@@ -74,10 +74,8 @@ __global__ __launch_bounds__(kS) void kepler_lane_kernel(LaunchArgs a) {
   int32_t maxk = st0.max_k;
   int32_t status = st0.status;
   const double m = (dsc.mass_off >= 0) ? a.params[dsc.mass_off] : 1.0;
-  // next frame: number fnext, written at the end of step fstep (one division
-  // per launch instead of one per step)
-  int64_t fnext = step / stride + 1;
-  int64_t fstep = fnext * stride;
+  // next frame by counting steps (one division per launch instead of one per step)
+  FrameClock fclk = frame_clock(step, stride);
   const double hb = h * T[kTabB + s];
   // the fast mode's rows of this lane's stage (eta for the iteration, the
   // folded K for the initial guess)
@@ -224,16 +222,13 @@ __global__ __launch_bounds__(kS) void kepler_lane_kernel(LaunchArgs a) {
         dw_add(qh[d], ql[d], h * (vh[d] - sc[d]));
       }
     }
-    if (step == fstep) {
-      if (s == 0) {
+    int64_t f;
+    if (frame_due(fclk, step, stride, f) && s == 0) {
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-          a.qout[frame_index(out_off, fnext, D, d)] = qh[d];
-          a.pout[frame_index(out_off, fnext, D, d)] = m * vh[d];
-        }
+      for (int d = 0; d < D; ++d) {
+        a.qout[frame_index(out_off, f, D, d)] = qh[d];
+        a.pout[frame_index(out_off, f, D, d)] = m * vh[d];
       }
-      ++fnext;
-      fstep += stride;
     }
     if (step < target) guess();
   }

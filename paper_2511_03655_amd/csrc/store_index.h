@@ -52,6 +52,26 @@ IRK_HD inline int64_t last_frame_of_launch(int64_t target, int64_t stride) {
   return target / stride;
 }
 
+// Frames by counting steps instead of dividing at every step: `next` is the
+// number of the next frame and `at` the step count after which it is written
+// (frame f holds the state after f * stride steps).  Set once per launch from
+// the steps already done; frame_due advances it after each step and agrees
+// with step % stride == 0 and f = step / stride.
+struct FrameClock {
+  int64_t next, at;
+};
+IRK_HD inline FrameClock frame_clock(int64_t steps_done, int64_t stride) {
+  const int64_t f = steps_done / stride + 1;
+  return FrameClock{f, f * stride};
+}
+IRK_HD inline bool frame_due(FrameClock& c, int64_t step, int64_t stride, int64_t& f) {
+  if (step != c.at) return false;
+  f = c.next;
+  ++c.next;
+  c.at += stride;
+  return true;
+}
+
 // Iteration count of step step0 + 1.
 IRK_HD inline int64_t iters_index(int64_t iters_off, int64_t step0) { return iters_off + step0; }
 

@@ -10,7 +10,9 @@
 // instance stops at the end of its step with its state saved; the end of a
 // chunked call fills the NaN frames of later launches.  Every index comes from
 // the kernels' own helpers (store_index.h) and must lie inside the instance's
-// allocation; every output frame must be written at least once.
+// allocation; every output frame must be written at least once.  The frame
+// clock that the Kepler latency kernel counts steps with (instead of dividing)
+// must name the same frames as step % stride == 0 in every launch.
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
@@ -76,6 +78,7 @@ void launch(std::vector<Inst>& v, Checker& ck, int64_t step_budget, int64_t step
     const int64_t target =
         irk::launch_target_of(in.steps_done, in.nsteps, in.ok, step_budget, step_limit);
     int64_t step0 = in.steps_done;
+    irk::FrameClock clk = irk::frame_clock(step0, in.stride);  // the counting form
     while (step0 < target) {
       if (in.nonfinite_at == step0 + 1) {  // non-finite increment norm in this step
         const int64_t nf = irk::last_frame_of_launch(target, in.stride);
@@ -91,6 +94,12 @@ void launch(std::vector<Inst>& v, Checker& ck, int64_t step_budget, int64_t step
       if (step % in.stride == 0)
         for (int c = 0; c < in.dq; ++c)
           ck.out(in, irk::frame_index(in.out_off, step / in.stride, in.dq, c));
+      int64_t fc = -1;
+      const bool due = irk::frame_due(clk, step, in.stride, fc);
+      if (due != (step % in.stride == 0) || (due && fc != step / in.stride))
+        if (ck.violations++ < 5)
+          std::printf("%s: counted frame %lld at step %lld disagrees with step / stride\n",
+                      ck.where, (long long)fc, (long long)step);
       const bool last = step >= target;
       const bool evict = !last && evictions && in.evict_every > 0 && step % in.evict_every == 0;
       if (last || evict) {
