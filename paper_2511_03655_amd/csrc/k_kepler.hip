@@ -13,7 +13,9 @@
 // the max-norm increment (eq. Delta_n) is a DPP maximum over the 8 lanes and
 // the stopping rule (eq. stopping), the compensated update (eq. qnvn2) and the
 // next initial guess (eq. IRK_init2) run redundantly (update) or per stage
-// (guess) in the lanes.  Every operation is the few-body kernel's own, in the
+// (guess) in the lanes.  The rule cannot stop on a nonzero norm before the
+// third iteration, so the norms of the first two are reduced only when a step
+// needs a third (most steps end at the second, on an exact zero).  Every operation is the few-body kernel's own, in the
 // same order (kepler_increment, stage_value, step_sums / dw_add, guess_stage),
 // so an orbit gives the same bits in either kernel and the choice between them
 // can depend on the batch.  The instance's bookkeeping is wave-uniform (scalar
@@ -44,6 +46,19 @@ __device__ __forceinline__ void kp_wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Maximum of each component's value over the 8 stage lanes, the levels of
+// the components interleaved (exact in any order; fmax drops NaN, which the
+// caller detects separately).
+template <int D>
+__device__ __forceinline__ void kp_group_max(double (&x)[D]) {
+#pragma unroll
+  for (int d = 0; d < D; ++d) x[d] = fmax(x[d], kp_dpp<0xB1>(x[d]));
+#pragma unroll
+  for (int d = 0; d < D; ++d) x[d] = fmax(x[d], kp_dpp<0x4E>(x[d]));
+#pragma unroll
+  for (int d = 0; d < D; ++d) x[d] = fmax(x[d], kp_dpp<0x141>(x[d]));
 }
 
 template <int D, bool EXACT>
@@ -131,9 +146,9 @@ __global__ __launch_bounds__(kS) void kepler_lane_kernel(LaunchArgs a) {
   }
 
   while (step < target) {
-    double mind[D], prv[D];
-#pragma unroll
-    for (int d = 0; d < D; ++d) mind[d] = prv[d] = __builtin_inf();
+    // stopping-rule state (eq. stopping): per component the minimum of the
+    // earlier norms and the previous norm; per-lane norms of iterations 1, 2
+    double mind[D], prv[D], dd1[D], dd2[D];
     int k = 0;
     bool ok = false, bad = false;
     for (;;) {
@@ -155,26 +170,43 @@ __global__ __launch_bounds__(kS) void kepler_lane_kernel(LaunchArgs a) {
       } else {
         rows_value(eta, Rall, qn);
       }
-      bool nf = false;
+      bool nf = false, nz = false;
 #pragma unroll
       for (int d = 0; d < D; ++d) {
         dm[d] = fabs(qn[d] - Q[d]);
         nf |= !__builtin_isfinite(dm[d]);
+        nz |= dm[d] != 0.0;
         Q[d] = qn[d];
       }
-      // max-norm over the 8 stages (exact in any order; fmax drops NaN, which
-      // nf has caught)
-#pragma unroll
-      for (int d = 0; d < D; ++d) dm[d] = fmax(dm[d], kp_dpp<0xB1>(dm[d]));
-#pragma unroll
-      for (int d = 0; d < D; ++d) dm[d] = fmax(dm[d], kp_dpp<0x4E>(dm[d]));
-#pragma unroll
-      for (int d = 0; d < D; ++d) dm[d] = fmax(dm[d], kp_dpp<0x141>(dm[d]));
-      int okl = 1;
-#pragma unroll
-      for (int d = 0; d < D; ++d) okl &= stop_component(dm[d], mind[d], prv[d]) ? 1 : 0;
-      ok = __builtin_amdgcn_readfirstlane(okl) != 0;  // the same in every lane
       bad = __ballot(nf) != 0;
+      if (k <= 2) {
+        // In iterations 1 and 2 the rule's minimum is still +inf, so it stops
+        // only on increments that are all exactly zero; the max-norms are
+        // formed only if a third iteration needs them.
+        ok = __ballot(nz) == 0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+          if (k == 1)
+            dd1[d] = dm[d];
+          else
+            dd2[d] = dm[d];
+        }
+      } else {
+        if (k == 3) {  // the rule's state after two iterations: min = norm 1, previous = norm 2
+          kp_group_max(dd1);
+          kp_group_max(dd2);
+#pragma unroll
+          for (int d = 0; d < D; ++d) {
+            mind[d] = dd1[d];
+            prv[d] = dd2[d];
+          }
+        }
+        kp_group_max(dm);
+        int okl = 1;
+#pragma unroll
+        for (int d = 0; d < D; ++d) okl &= stop_component(dm[d], mind[d], prv[d]) ? 1 : 0;
+        ok = __builtin_amdgcn_readfirstlane(okl) != 0;  // the same in every lane
+      }
       if (bad || ok || k >= a.max_iter) break;
     }
     if (bad) {  // non-finite: this launch's remaining frames NaN, the instance stops
