@@ -5,7 +5,7 @@ trajectory, per-step iteration counts and status must not depend on the batch
 it comes in: bit-identical results alone, in a batch of 64 and in a batch of
 100, in both arithmetic modes, in 2 and 3 dimensions, across launches (plain
 form: one launch per step, the state handed over through device memory) and
-for a non-finite orbit."""
+for a non-finite orbit, and when served in slices."""
 import math
 
 import numpy as np
@@ -111,3 +111,24 @@ def test_iteration_cap_alone_equals_in_batch(cap):
     if cap < 3:
         assert few[3] == K.IRKGL16_ENOCONV
     _same(few, big, 0, 5, steps)
+
+
+@pytest.mark.parametrize("flags", [0, K.IRKGL16_REPRODUCIBLE])
+def test_served_orbits_equal_alone(flags):
+    """Served Kepler requests (the latency kernel, resumed slice after slice
+    under per-slice step budgets) give the bits of the same orbit alone."""
+    from paper_2511_03655_amd import serve
+    d, n_req = 3, 6
+    q0, p0 = _orbits(n_req, d, seed=21)
+    reqs = []
+    for i in range(n_req):
+        inst = dict(kind=K.IRKGL16_KEPLER, n=1, d=d, mass=None, G=1.0, eps=0.0, beta=0.0,
+                    q=q0[i * d:(i + 1) * d].copy(), p=p0[i * d:(i + 1) * d].copy(),
+                    h=2 * math.pi / 128, nsteps=300 + 100 * i, stride=50, cls="kepler")
+        reqs.append((0.001 * i, inst))
+    out = serve.run_stream(reqs, cap_bytes=1 << 26, slice_steps=70, keep_frames=True,
+                           flags=flags)
+    for (t, inst), (q, p, info, rc) in zip(reqs, out["results"]):
+        qa, pa, sa, rca = _run(1, d, inst["q"], inst["p"], inst["nsteps"], inst["stride"], flags)
+        assert rc == rca and info["steps"] == inst["nsteps"]
+        assert np.array_equal(q, qa) and np.array_equal(p, pa)
