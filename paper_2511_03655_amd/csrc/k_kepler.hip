@@ -5,22 +5,25 @@
 // fixed-point iteration passing through an LDS tile between a stage role and
 // a component role and through the slot bookkeeping that keeps eight
 // independent systems in step.  A lone orbit (a batch of a few) pays all of
-// that on its critical path.  Here each lane holds its own stage: the force
-// (eq. Gi) is lane-local, the 8 increments R_j reach every lane through a
-// small LDS tile (one write and D reads of 16 or 8 bytes per stage, ordered by
-// the wavefront's in-order LDS pipeline rather than a barrier), the stage
-// update (eq. IRK_FP2) uses the lane's eta row held in registers,
-// the max-norm increment (eq. Delta_n) is a DPP maximum over the 8 lanes and
-// the stopping rule (eq. stopping), the compensated update (eq. qnvn2) and the
-// next initial guess (eq. IRK_init2) run redundantly (update) or per stage
-// (guess) in the lanes.  The rule cannot stop on a nonzero norm before the
-// third iteration, so the norms of the first two are reduced only when a step
-// needs a third (most steps end at the second, on an exact zero).  Every operation is the few-body kernel's own, in the
-// same order (kepler_increment, stage_value, step_sums / dw_add, guess_stage),
-// so an orbit gives the same bits in either kernel and the choice between them
-// can depend on the batch.  The instance's bookkeeping is wave-uniform (scalar
-// registers), and the frame number advances by counting steps instead of a
-// 64-bit division per step.
+// that on its critical path.  Here each lane holds its own stage:
+//  * the force (eq. Gi) is lane-local;
+//  * the 8 increments R_j reach every lane through a small LDS tile (each lane
+//    stores its D values, then reads all 8 D), ordered by the wavefront's
+//    in-order LDS pipeline rather than a barrier;
+//  * the stage update (eq. IRK_FP2) uses the lane's eta row in registers;
+//  * the max-norm increment (eq. Delta_n) is a DPP maximum over the 8 lanes;
+//    the stopping rule (eq. stopping) cannot stop on a nonzero norm before
+//    the third iteration, so the first two iterations are tested with one
+//    ballot (all increments exactly zero?) and their norms are reduced only
+//    when a step needs a third (most steps end at the second);
+//  * the compensated update (eq. qnvn2) runs redundantly in every lane and
+//    the next initial guess (eq. IRK_init2) per stage.
+// Every operation is the few-body kernel's own, in the same order
+// (kepler_increment, stage_value, step_sums / dw_add, guess_stage), and every
+// stopping decision is the same, so an orbit gives the same bits in either
+// kernel and the choice between them can depend on the batch.  The instance's
+// bookkeeping is wave-uniform (scalar registers), and the frame number
+// advances by counting steps instead of a 64-bit division per step.
 #include "device_common.h"
 #include "launch.h"
 #include "store_index.h"
