@@ -291,8 +291,13 @@ __global__ __launch_bounds__(kS) void kepler_lane_kernel(LaunchArgs a) {
   }
 }
 
-// Batches of at most this many Kepler orbits take the latency kernel.
-constexpr int kKeplerLaneMaxBatch = 64;
+// Batches of at most this many Kepler orbits take the latency kernel.  One
+// wavefront per orbit uses 8 of its 64 lanes, but at every batch size
+// measured up to this one it finished first (2,000 steps of eccentric orbits,
+// against the eight-slot kernel: 128 orbits 4.0 ms against 19.9, 1,024 orbits
+// 8.0 against 22.7, 8,192 orbits 14.9 against 24.9); the slots of the other
+// kernel advance in lockstep at the pace of their slowest orbit.
+constexpr int kKeplerLaneMaxBatch = 8192;
 
 bool kepler_lane_supported(int d, int n_items, const LaunchArgs& a) {
   return (d == 2 || d == 3) && n_items <= kKeplerLaneMaxBatch && a.evict_k <= 0.0;

@@ -1,11 +1,12 @@
-"""Kepler orbits in small batches (at most 64) run in the one-wavefront-per-
+"""Kepler orbits in batches of at most LIMIT run in the one-wavefront-per-
 orbit latency kernel; larger batches run in the eight-slot small-system
 kernel.  Both evaluate the same operations in the same order, so an orbit's
 trajectory, per-step iteration counts and status must not depend on the batch
-it comes in: bit-identical results alone, in a batch of 64 and in a batch of
-100, in both arithmetic modes, in 2 and 3 dimensions, across launches (plain
-form: one launch per step, the state handed over through device memory) and
-for a non-finite orbit, and when served in slices."""
+it comes in: bit-identical results alone, in a batch of LIMIT and in a batch
+of BIG, in both arithmetic modes, in 2 and 3 dimensions, across launches
+(plain form: one launch per step, the state handed over through device
+memory), for a non-finite orbit, at iteration caps, and when served in
+slices."""
 import math
 
 import numpy as np
@@ -14,6 +15,9 @@ import pytest
 from paper_2511_03655_amd import irkgl16 as K
 
 pytestmark = pytest.mark.gpu
+
+LIMIT = 8192      # the latency kernel's largest batch (kKeplerLaneMaxBatch)
+BIG = LIMIT + 8   # a batch for the eight-slot kernel
 
 
 def _orbits(n, d, seed):
@@ -60,20 +64,20 @@ def _same(a, b, lo, hi, steps):
 @pytest.mark.parametrize("flags", [0, K.IRKGL16_REPRODUCIBLE])
 @pytest.mark.parametrize("d", [2, 3])
 def test_orbit_alone_equals_in_batches(flags, d):
-    N, steps, stride = 100, 600, 50
+    N, steps, stride = BIG, 600, 50
     q0, p0 = _orbits(N, d, seed=50 + d)
     big = _run(N, d, q0, p0, steps, stride, flags)  # eight-slot kernel
     assert big[3] == 0
-    few = _run(64, d, q0[:64 * d], p0[:64 * d], steps, stride, flags)  # latency kernel
-    _same(few, big, 0, 64, steps)
-    for i in (0, 37, 99):
+    few = _run(LIMIT, d, q0[:LIMIT * d], p0[:LIMIT * d], steps, stride, flags)  # latency kernel
+    _same(few, big, 0, LIMIT, steps)
+    for i in (0, 37, N - 1):
         one = _run(1, d, q0[i * d:(i + 1) * d], p0[i * d:(i + 1) * d], steps, stride, flags)
         _same(one, big, i, i + 1, steps)
 
 
 @pytest.mark.parametrize("d", [2, 3])
 def test_plain_form_equals_batched(d):
-    N, steps, stride = 100, 80, 10
+    N, steps, stride = BIG, 80, 10
     q0, p0 = _orbits(N, d, seed=7)
     big = _run(N, d, q0, p0, steps, stride)
     probs = [dict(kind=K.IRKGL16_KEPLER, n=1, d=d, G=1.0)] * 3
@@ -86,7 +90,7 @@ def test_nonfinite_orbit_alone_equals_in_batch():
     """An orbit started at rest at the centre (every stage value at r = 0)
     turns non-finite in its first step: NaN frames, status non-finite, the
     other orbits unaffected."""
-    N, d, steps, stride = 100, 2, 20, 5
+    N, d, steps, stride = BIG, 2, 20, 5
     q0, p0 = _orbits(N, d, seed=11)
     q0[3 * d:4 * d] = 0.0
     p0[3 * d:4 * d] = 0.0
@@ -104,7 +108,7 @@ def test_nonfinite_orbit_alone_equals_in_batch():
 def test_iteration_cap_alone_equals_in_batch(cap):
     """Steps cut at 1, 2 or 3 iterations: the caps on either side of the
     iteration where the stopping rule first compares earlier norms."""
-    N, d, steps, stride = 100, 2, 30, 10
+    N, d, steps, stride = BIG, 2, 30, 10
     q0, p0 = _orbits(N, d, seed=12)
     big = _run(N, d, q0, p0, steps, stride, max_iter=cap)
     few = _run(5, d, q0[:5 * d], p0[:5 * d], steps, stride, max_iter=cap)
