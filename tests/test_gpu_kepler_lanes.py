@@ -136,3 +136,41 @@ def test_served_orbits_equal_alone(flags):
         qa, pa, sa, rca = _run(1, d, inst["q"], inst["p"], inst["nsteps"], inst["stride"], flags)
         assert rc == rca and info["steps"] == inst["nsteps"]
         assert np.array_equal(q, qa) and np.array_equal(p, pa)
+
+
+def test_mixed_step_counts_and_strides():
+    """Zero steps, one step, and different output strides in one batch: each
+    orbit gives the bits of its run alone, in the latency kernel and in the
+    eight-slot kernel; a zero-step orbit has frame 0 only and no iterations.
+    A step count that is not a multiple of its stride is refused."""
+    d, h = 2, 2 * math.pi / 128
+    ns_e = np.array([0, 1, 9, 64, 0, 13], np.int64)
+    sd_e = np.array([1, 1, 3, 16, 5, 13], np.int64)
+    N = BIG
+    q0, p0 = _orbits(N, d, seed=31)
+    ns = np.full(N, 20, np.int64)
+    sd = np.full(N, 4, np.int64)
+    ns[:6], sd[:6] = ns_e, sd_e
+
+    def run(n, q, p, nsv, sdv):
+        probs = [dict(kind=K.IRKGL16_KEPLER, n=1, d=d, G=1.0)] * n
+        return K.Integrator(probs, record_iters=True).integrate(q, p, h, nsv, sdv)
+
+    big = run(N, q0, p0, ns, sd)          # eight-slot kernel
+    few = run(6, q0[:6 * d], p0[:6 * d], ns_e, sd_e)  # latency kernel
+    assert big[3] == 0 and few[3] == 0
+    off = np.concatenate([[0], np.cumsum(d * (ns_e // sd_e + 1))])
+    soff = np.concatenate([[0], np.cumsum(ns_e)])
+    for i in range(6):
+        one = run(1, q0[i * d:(i + 1) * d], p0[i * d:(i + 1) * d], ns_e[i:i + 1], sd_e[i:i + 1])
+        assert one[0].size == off[i + 1] - off[i]
+        for other in (few, big):
+            assert np.array_equal(one[0], other[0][off[i]:off[i + 1]])
+            assert np.array_equal(one[1], other[1][off[i]:off[i + 1]])
+            assert np.array_equal(one[2]["step_iters"], other[2]["step_iters"][soff[i]:soff[i + 1]])
+            assert one[2]["inst_iterations"][0] == other[2]["inst_iterations"][i]
+        if ns_e[i] == 0:
+            assert np.array_equal(one[0], q0[i * d:(i + 1) * d])
+            assert one[2]["inst_iterations"][0] == 0
+    bad = K.Integrator([dict(kind=K.IRKGL16_KEPLER, n=1, d=d, G=1.0)])
+    assert bad.integrate(q0[:d], p0[:d], h, 7, 3, check=False)[3] == K.IRKGL16_EINVAL
