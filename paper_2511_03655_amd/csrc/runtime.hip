@@ -94,6 +94,11 @@ int validate_problem(const irkgl16_problem& p) {
   }
 }
 
+std::atomic<int>& live_streams() {
+  static std::atomic<int> n{0};
+  return n;
+}
+
 int summarize_stats(const InstStat* h_stat, int32_t n, irkgl16_stats* stats) {
   int worst = IRKGL16_OK;
   int64_t steps = 0, iters = 0, nonconv = 0;
@@ -131,6 +136,7 @@ struct irkgl16_ctx {
   int num_cus = 1;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  bool halves = false;  // a class was split in two (per-class chunk pipelines)
   int32_t n_inst = 0;
   int32_t max_iter = 100;
   bool record = false;
@@ -180,6 +186,7 @@ struct irkgl16_ctx {
     for (hipStream_t sk : aux) (void)hipStreamDestroy(sk);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
+    irk::live_streams() -= (int)aux.size() + ((own_stream && stream) ? 1 : 0);
     irk::user_kernel_free(user);
   }
 };
@@ -373,6 +380,38 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
   // Recent iterations per step from which the small-system kernel stops an
   // instance mid-chunk for promotion at the next chunk (0: never).
   if (const char* ek = std::getenv("IRKGL16_EVICT_K")) c->evict_k = std::max(0.0, std::atof(ek));
+  // A promotable few-body class with at least twice as many instances as the
+  // GPU holds slots for (8 wavefronts of 8 slots per CU) runs as two halves
+  // (alternate instances), each with its own stream, chunk pipeline and
+  // promotion stream: while one half drains the end of a chunk, the other's
+  // wavefronts take the freed slots.  That needs the two halves' streams on
+  // hardware queues of their own, so it is done only while this process's
+  // streams (the caller's and the default one, the library's live ones and
+  // this context's) fit in GPU_MAX_HW_QUEUES; IRKGL16_HALVES=0/1 overrides.
+  bool halves = false;
+  if (const char* hv = std::getenv("IRKGL16_HALVES")) {
+    halves = std::atoi(hv) != 0;
+  } else {
+    int hwq = 4;
+    if (const char* q = std::getenv("GPU_MAX_HW_QUEUES")) hwq = std::max(1, std::atoi(q));
+    const int own = irkgl16_ctx::kMaxAux + (hip_stream ? 0 : 1);
+    halves = irk::live_streams().load() + own + 2 <= hwq;
+  }
+  if (halves) {
+    const size_t resident = (size_t)8 * 8 * (size_t)c->num_cus;
+    const size_t n_cls = c->classes.size();
+    for (size_t k = 0; k < n_cls; ++k) {
+      KernelClass& kc = c->classes[k];
+      if (!promotable(c, kc) || kc.ids.size() < 2 * resident) continue;
+      KernelClass half = kc;
+      half.ids.clear();
+      std::vector<int32_t> keep;
+      for (size_t t = 0; t < kc.ids.size(); ++t) (t % 2 ? half.ids : keep).push_back(kc.ids[t]);
+      kc.ids.swap(keep);
+      c->classes.push_back(half);
+      c->halves = true;
+    }
+  }
   for (auto& kc : c->classes)
     if (kc.cls == irk::kClassWg)
       kc.tune.wg_block = c->tune.get(irk::wg_tune_key(kc.kind, kc.d, kc.size), 0);
@@ -390,6 +429,7 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
   } else {
     if (hipStreamCreate(&c->stream) != hipSuccess) return fail(IRKGL16_EDEVICE);
     c->own_stream = true;
+    ++irk::live_streams();
   }
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess)
     return fail(IRKGL16_EDEVICE);
@@ -447,6 +487,7 @@ static int create_impl(irkgl16_ctx** out, const irkgl16_problem* probs, int32_t 
     hipEvent_t ek;
     if (hipStreamCreateWithFlags(&sk, hipStreamNonBlocking) != hipSuccess) return fail(IRKGL16_EDEVICE);
     c->aux.push_back(sk);
+    ++irk::live_streams();
     if (hipEventCreateWithFlags(&ek, hipEventDisableTiming) != hipSuccess) return fail(IRKGL16_EDEVICE);
     c->aux_done.push_back(ek);
   }
@@ -698,15 +739,18 @@ static int integrate_impl(irkgl16_ctx* c, const double* q0, const double* p0, co
     // count is given) runs in chunks ending at multiples of a step count (the
     // few-body kernel stops an instance early once its iterations per step
     // grow large; it catches up in the next chunk); between chunks the order
-    // kernel, on the main stream, sorts its queue by estimated remaining work
-    // and picks the instances for the stage-parallel kernel (evicted ones and
-    // slow ones), whose chunk runs concurrently, at the highest wave priority,
-    // on an auxiliary stream that no class uses.  Each chunk
-    // forks the class's stream and its promotion stream from one event, so the
-    // promoted chunk is placed on the GPU as early as the class's own (a
-    // promoted chunk queued behind a full grid of the class's workgroups would
-    // wait for free wave slots), and joins both back before the next order
-    // kernel.  With every auxiliary stream taken by a class, nothing is
+    // kernel sorts its queue by estimated remaining work and picks the
+    // instances for the stage-parallel kernel (evicted ones and slow ones),
+    // whose chunk runs concurrently, at the highest wave priority, on an
+    // auxiliary stream that no class uses.  The promoted chunk starts with the
+    // class's own (a promoted chunk queued behind a full grid of the class's
+    // workgroups would wait for free wave slots), and both end before the next
+    // order kernel.  Normally all chunked classes step through their chunks
+    // together, forked from and joined into the main stream, where the order
+    // kernels run; a large ensemble split in two halves instead runs each half
+    // as a pipeline on its own stream (order kernel included), so that the
+    // halves' chunk ends fall at different times.  With every auxiliary stream
+    // taken by a class, nothing is
     // promoted or chunked.  An instance whose iteration slows down mid-run is
     // thus neither pulled late nor left on the slower path.  Every launch
     // resumes each instance's state exactly, so chunking never changes
@@ -752,72 +796,146 @@ static int integrate_impl(irkgl16_ctx* c, const double* q0, const double* p0, co
       max_nch = std::max(max_nch, pl.nch);
       plans.push_back(pl);
     }
-    std::vector<char> used(c->aux.size(), 0);
-    auto fork = [&](int j) -> hipError_t {
-      used[j] = 1;
-      return hipStreamWaitEvent(c->aux[j], c->ev_fork, 0);
-    };
-    for (int ch = 0; ch < max_nch; ++ch) {
+    if (c->halves) {
+      // Each class runs its chunks as a pipeline on its own stream: chunk, then
+      // (joined with its promoted chunk) the order kernel, then the next chunk.
+      // Classes do not wait for each other at chunk boundaries, so one class's
+      // wavefronts fill the GPU while another drains the end of a chunk.
       HIP_TRY(hipEventRecord(c->ev_fork, c->stream));
-      std::vector<char> step_used(c->aux.size(), 0);
+      std::vector<char> used(c->aux.size(), 0);
+      auto start = [&](int j) -> hipError_t {
+        if (used[j]) return hipSuccess;
+        used[j] = 1;
+        return hipStreamWaitEvent(c->aux[j], c->ev_fork, 0);
+      };
       for (const Plan& pl : plans) {
-        if (ch >= pl.nch || (ch > 0 && pl.nch == 1)) continue;
         const auto& kc = c->classes[pl.k];
-        irk::LaunchArgs ca = a;
-        ca.queue = (ch == 0 ? members : qnorm) + kc.queue_off;
-        ca.queue_len = (int32_t)kc.ids.size();
-        ca.queue_head = c->d_heads.as<int32_t>() + pl.k;
-        // chunk boundary: instances behind it (evicted ones) catch up; the
-        // last chunk runs every instance to its end
-        ca.step_limit = (pl.nch > 1 && ch + 1 < pl.nch) ? (ch + 1) * pl.budget : 0;
-        if (pl.jp >= 0 && ch + 1 < pl.nch) {
-          ca.evict_k = c->evict_k;
-          ca.evicted = c->d_evicted.as<uint8_t>();
-        }
-        if (ch > 0) ca.queue_len_dev = counts + 2 * pl.k;  // set by the order kernel
-        HIP_TRY(fork(pl.j));
-        if (pl.nch > 1) step_used[pl.j] = 1;
-        HIP_TRY(launch_class(c, kc, ca, (int)kc.ids.size(), c->aux[pl.j]));
-        if (ch > 0 && pl.jp >= 0) {
-          KernelClass ks = kc;
-          ks.cls = irk::kClassStage;
-          ks.size = irk::stage_np(kc.size);
-          irk::LaunchArgs pa = ca;
-          pa.evict_k = 0.0;
-          pa.promoted = 1;
-          pa.queue = c->d_qprom.as<int32_t>() + kc.queue_off;
-          pa.queue_len_dev = counts + 2 * pl.k + 1;
-          pa.queue_head = c->d_heads_prom.as<int32_t>() + pl.k;
-          HIP_TRY(fork(pl.jp));
-          step_used[pl.jp] = 1;
-          HIP_TRY(launch_class(c, ks, pa, std::min((int)kc.ids.size(), c->num_cus),
-                               c->aux[pl.jp]));
+        hipStream_t sj = c->aux[pl.j];
+        HIP_TRY(start(pl.j));
+        if (pl.jp >= 0) HIP_TRY(start(pl.jp));
+        for (int ch = 0; ch < pl.nch; ++ch) {
+          irk::LaunchArgs ca = a;
+          ca.queue = (ch == 0 ? members : qnorm) + kc.queue_off;
+          ca.queue_len = (int32_t)kc.ids.size();
+          ca.queue_head = c->d_heads.as<int32_t>() + pl.k;
+          // chunk boundary: instances behind it (evicted ones) catch up; the
+          // last chunk runs every instance to its end
+          ca.step_limit = (pl.nch > 1 && ch + 1 < pl.nch) ? (ch + 1) * pl.budget : 0;
+          if (pl.jp >= 0 && ch + 1 < pl.nch) {
+            ca.evict_k = c->evict_k;
+            ca.evicted = c->d_evicted.as<uint8_t>();
+          }
+          if (ch > 0) ca.queue_len_dev = counts + 2 * pl.k;  // set by the order kernel
+          const bool prom_chunk = ch > 0 && pl.jp >= 0;
+          if (prom_chunk) {  // the promoted chunk starts with the class's chunk
+            HIP_TRY(hipEventRecord(c->aux_done[pl.j], sj));
+            HIP_TRY(hipStreamWaitEvent(c->aux[pl.jp], c->aux_done[pl.j], 0));
+          }
+          HIP_TRY(launch_class(c, kc, ca, (int)kc.ids.size(), sj));
+          if (prom_chunk) {
+            KernelClass ks = kc;
+            ks.cls = irk::kClassStage;
+            ks.size = irk::stage_np(kc.size);
+            irk::LaunchArgs pa = ca;
+            pa.evict_k = 0.0;
+            pa.promoted = 1;
+            pa.queue = c->d_qprom.as<int32_t>() + kc.queue_off;
+            pa.queue_len_dev = counts + 2 * pl.k + 1;
+            pa.queue_head = c->d_heads_prom.as<int32_t>() + pl.k;
+            HIP_TRY(launch_class(c, ks, pa, std::min((int)kc.ids.size(), c->num_cus),
+                                 c->aux[pl.jp]));
+          }
+          if (ch + 1 == pl.nch) break;
+          // join the promoted chunk, then order the next chunk
+          if (prom_chunk) {
+            HIP_TRY(hipEventRecord(c->aux_done[pl.jp], c->aux[pl.jp]));
+            HIP_TRY(hipStreamWaitEvent(sj, c->aux_done[pl.jp], 0));
+          }
+          HIP_TRY(irk::launch_order(members + kc.queue_off, qnorm + kc.queue_off,
+                                    (int32_t)kc.ids.size(), c->d_desc.as<irk::InstDesc>(),
+                                    c->d_stat.as<irk::InstStat>(), c->d_prev.as<int64_t>(),
+                                    c->d_heads.as<int32_t>() + pl.k,
+                                    c->d_qprom.as<int32_t>() + kc.queue_off, counts + 2 * pl.k,
+                                    c->d_heads_prom.as<int32_t>() + pl.k,
+                                    pl.jp >= 0 ? c->promote_k : 0.0,
+                                    c->d_evicted.as<uint8_t>(), sj));
         }
       }
-      if (ch + 1 == max_nch) break;
-      // join the chunked classes' streams, then order their next chunk
       for (int j = 0; j < naux; ++j) {
-        if (!step_used[j]) continue;
+        if (!used[j]) continue;
         HIP_TRY(hipEventRecord(c->aux_done[j], c->aux[j]));
         HIP_TRY(hipStreamWaitEvent(c->stream, c->aux_done[j], 0));
       }
-      for (const Plan& pl : plans) {
-        if (ch + 1 >= pl.nch) continue;
-        const auto& kc = c->classes[pl.k];
-        HIP_TRY(irk::launch_order(members + kc.queue_off, qnorm + kc.queue_off,
-                                  (int32_t)kc.ids.size(), c->d_desc.as<irk::InstDesc>(),
-                                  c->d_stat.as<irk::InstStat>(), c->d_prev.as<int64_t>(),
-                                  c->d_heads.as<int32_t>() + pl.k,
-                                  c->d_qprom.as<int32_t>() + kc.queue_off, counts + 2 * pl.k,
-                                  c->d_heads_prom.as<int32_t>() + pl.k,
-                                  pl.jp >= 0 ? c->promote_k : 0.0,
-                                  c->d_evicted.as<uint8_t>(), c->stream));
+    } else {
+      // One class, or classes that each fit the GPU: all chunked classes step
+      // through their chunks together, the order kernels on the main stream.
+      std::vector<char> used(c->aux.size(), 0);
+      auto fork = [&](int j) -> hipError_t {
+        used[j] = 1;
+        return hipStreamWaitEvent(c->aux[j], c->ev_fork, 0);
+      };
+      for (int ch = 0; ch < max_nch; ++ch) {
+        HIP_TRY(hipEventRecord(c->ev_fork, c->stream));
+        std::vector<char> step_used(c->aux.size(), 0);
+        for (const Plan& pl : plans) {
+          if (ch >= pl.nch || (ch > 0 && pl.nch == 1)) continue;
+          const auto& kc = c->classes[pl.k];
+          irk::LaunchArgs ca = a;
+          ca.queue = (ch == 0 ? members : qnorm) + kc.queue_off;
+          ca.queue_len = (int32_t)kc.ids.size();
+          ca.queue_head = c->d_heads.as<int32_t>() + pl.k;
+          // chunk boundary: instances behind it (evicted ones) catch up; the
+          // last chunk runs every instance to its end
+          ca.step_limit = (pl.nch > 1 && ch + 1 < pl.nch) ? (ch + 1) * pl.budget : 0;
+          if (pl.jp >= 0 && ch + 1 < pl.nch) {
+            ca.evict_k = c->evict_k;
+            ca.evicted = c->d_evicted.as<uint8_t>();
+          }
+          if (ch > 0) ca.queue_len_dev = counts + 2 * pl.k;  // set by the order kernel
+          HIP_TRY(fork(pl.j));
+          if (pl.nch > 1) step_used[pl.j] = 1;
+          HIP_TRY(launch_class(c, kc, ca, (int)kc.ids.size(), c->aux[pl.j]));
+          if (ch > 0 && pl.jp >= 0) {
+            KernelClass ks = kc;
+            ks.cls = irk::kClassStage;
+            ks.size = irk::stage_np(kc.size);
+            irk::LaunchArgs pa = ca;
+            pa.evict_k = 0.0;
+            pa.promoted = 1;
+            pa.queue = c->d_qprom.as<int32_t>() + kc.queue_off;
+            pa.queue_len_dev = counts + 2 * pl.k + 1;
+            pa.queue_head = c->d_heads_prom.as<int32_t>() + pl.k;
+            HIP_TRY(fork(pl.jp));
+            step_used[pl.jp] = 1;
+            HIP_TRY(launch_class(c, ks, pa, std::min((int)kc.ids.size(), c->num_cus),
+                                 c->aux[pl.jp]));
+          }
+        }
+        if (ch + 1 == max_nch) break;
+        // join the chunked classes' streams, then order their next chunk
+        for (int j = 0; j < naux; ++j) {
+          if (!step_used[j]) continue;
+          HIP_TRY(hipEventRecord(c->aux_done[j], c->aux[j]));
+          HIP_TRY(hipStreamWaitEvent(c->stream, c->aux_done[j], 0));
+        }
+        for (const Plan& pl : plans) {
+          if (ch + 1 >= pl.nch) continue;
+          const auto& kc = c->classes[pl.k];
+          HIP_TRY(irk::launch_order(members + kc.queue_off, qnorm + kc.queue_off,
+                                    (int32_t)kc.ids.size(), c->d_desc.as<irk::InstDesc>(),
+                                    c->d_stat.as<irk::InstStat>(), c->d_prev.as<int64_t>(),
+                                    c->d_heads.as<int32_t>() + pl.k,
+                                    c->d_qprom.as<int32_t>() + kc.queue_off, counts + 2 * pl.k,
+                                    c->d_heads_prom.as<int32_t>() + pl.k,
+                                    pl.jp >= 0 ? c->promote_k : 0.0,
+                                    c->d_evicted.as<uint8_t>(), c->stream));
+        }
       }
-    }
-    for (int j = 0; j < naux; ++j) {
-      if (!used[j]) continue;
-      HIP_TRY(hipEventRecord(c->aux_done[j], c->aux[j]));
-      HIP_TRY(hipStreamWaitEvent(c->stream, c->aux_done[j], 0));
+      for (int j = 0; j < naux; ++j) {
+        if (!used[j]) continue;
+        HIP_TRY(hipEventRecord(c->aux_done[j], c->aux[j]));
+        HIP_TRY(hipStreamWaitEvent(c->stream, c->aux_done[j], 0));
+      }
     }
     if (max_nch > 1)
       HIP_TRY(irk::launch_nan_fill(c->d_desc.as<irk::InstDesc>(), c->d_stat.as<irk::InstStat>(),

@@ -138,6 +138,7 @@ struct irkgl16_server {
     if (ev_s0) (void)hipEventDestroy(ev_s0);
     if (ev_s1) (void)hipEventDestroy(ev_s1);
     if (own_stream && stream) (void)hipStreamDestroy(stream);
+    irk::live_streams() -= (int)aux.size() + ((own_stream && stream) ? 1 : 0);
   }
   void run();
   int slice(std::vector<Request*>& live, std::vector<Request*>& fresh);
@@ -542,12 +543,14 @@ int irkgl16_server_create(irkgl16_server** out, const irkgl16_server_options* op
     } else {
       if (hipStreamCreate(&s->stream) != hipSuccess) return IRKGL16_EDEVICE;
       s->own_stream = true;
+      ++irk::live_streams();
     }
     for (int k = 0; k < irkgl16_server::kMaxAux; ++k) {
       hipStream_t sk;
       hipEvent_t ek;
       if (hipStreamCreateWithFlags(&sk, hipStreamNonBlocking) != hipSuccess) return IRKGL16_EDEVICE;
       s->aux.push_back(sk);
+      ++irk::live_streams();
       if (hipEventCreateWithFlags(&ek, hipEventDisableTiming) != hipSuccess) return IRKGL16_EDEVICE;
       s->aux_done.push_back(ek);
     }

@@ -229,6 +229,30 @@ def test_alone_equals_in_mix():
         assert np.array_equal(alone[1], mix[1][i * 36:(i + 1) * 36])
 
 
+def test_halves_of_a_large_ensemble_equal_alone(monkeypatch):
+    """An ensemble with at least twice as many systems as the GPU holds slots
+    (8 wavefronts of 8 slots per CU) can run as two halves, alternate systems,
+    each with its own chunk pipeline and promotion stream (IRKGL16_HALVES
+    forces the choice): the whole call gives the same bits either way, and
+    systems of both halves give the bits of their runs alone."""
+    N, n = 40000, 300
+    sy = _c2_subset(N, seed=13)
+    q0 = np.concatenate([s["q"] for s in sy])
+    p0 = np.concatenate([s["p"] for s in sy])
+    probs = [_problem(s) for s in sy]
+    monkeypatch.setenv("IRKGL16_HALVES", "1")
+    q, p, st, rc = K.Integrator(probs).integrate(q0, p0, 1.0, n, n)
+    assert st["steps"] == N * n
+    monkeypatch.setenv("IRKGL16_HALVES", "0")
+    q1, p1, st1, _ = K.Integrator(probs).integrate(q0, p0, 1.0, n, n)
+    assert np.array_equal(q, q1) and np.array_equal(p, p1)
+    assert np.array_equal(st["inst_iterations"], st1["inst_iterations"])
+    for i in (0, 1, 20001, N - 1):
+        alone = K.Integrator([_problem(sy[i])]).integrate(sy[i]["q"], sy[i]["p"], 1.0, n, n)
+        assert np.array_equal(alone[0], q[i * 36:(i + 1) * 36]), i
+        assert np.array_equal(alone[1], p[i * 36:(i + 1) * 36]), i
+
+
 def test_nonfinite_instance_is_isolated(orc):
     m = np.array([1.0, 1.0])
     bad = dict(kind=K.IRKGL16_GRAVITY, n=2, d=3, mass=m, G=1.0, eps=0.0)
