@@ -224,7 +224,13 @@ int irkgl16_ode_compile_check(const char *rhs_src, int32_t D, char *log, int64_t
  * C, sched/promote_k10 = 10 P or sched/evict_k10 = 10 E.  Environment, read by
  * irkgl16_create*, overriding the table: IRKGL16_CHUNKS = c (a positive
  * integer; fixed chunk count, every batched class chunked), IRKGL16_PROMOTE_K
- * = P, IRKGL16_EVICT_K = E (0: never, for either). */
+ * = P, IRKGL16_EVICT_K = E (0: never, for either).  A promotable few-body
+ * class with at least 128 instances per CU runs as two halves of alternate
+ * instances, each chunked on its own stream without waiting for the other at
+ * chunk boundaries, while the process's streams (the caller's and the default
+ * one, the library's live contexts and servers, this context's) fit in HIP's
+ * GPU_MAX_HW_QUEUES (4 unless set); IRKGL16_HALVES = 0 or 1, read by
+ * irkgl16_create*, forces the choice. */
 int irkgl16_integrate(irkgl16_ctx *ctx, const double *q0, const double *p0, const double *h,
                       const int64_t *nsteps, const int64_t *out_stride, double *q_out,
                       double *p_out, irkgl16_stats *stats);
